@@ -1,0 +1,301 @@
+/*
+ * ckpt.h -- C ABI of libckpt: drain live device allocations into a checkpoint
+ * image on an AMD Instinct MI355X (gfx950), and refill them from it.
+ *
+ * The operation is the one CRAC (Jain & Cooperman, "CRAC: Checkpoint-Restart
+ * Architecture for CUDA with Streams and UVM") performs on the GPU side of a
+ * checkpoint:
+ *   - the library logs the pointers returned by the allocation calls of the
+ *     cudaMalloc family, not the allocator's mmap calls (Sec. 3.2, "Issue of
+ *     library-allocated memory");
+ *   - at checkpoint time it saves only the memory of the *active mallocs*,
+ *     allocations made and not yet freed, never the allocator's arena
+ *     (Sec. 3.2, "Saving the library-allocated arena"), and handles them in
+ *     the order in which they were allocated (Sec. 3.1, "Log-and-replay");
+ *   - device (cudaMalloc) and managed (cudaMallocManaged) regions are saved at
+ *     checkpoint time and copied back at restart (Sec. 3.2, "restoring the
+ *     CUDA library-allocated regions");
+ *   - before copying, the queue of pending GPU work is drained, as CheCUDA's
+ *     first step does with a device-wide synchronize (Sec. 2.2).
+ * Here the caller mirrors its allocation calls with ckpt_register /
+ * ckpt_unregister (the log), ckpt_checkpoint drains the live set into an
+ * image, and ckpt_restore refills fresh buffers from it.
+ *
+ * The image format, the per-chunk CRC-32C, the ZERO/DIRTY flags, incremental
+ * images, batching and serving are this library's design; the paper fixes
+ * none of them.  Their exact definitions are given next to each call below.
+ *
+ * Conventions for every call:
+ *   - Return value: CKPT_OK (0) or a negative ckpt_status.  Out-parameters
+ *     are written only on success, except ckpt_restore's report, which is
+ *     also written with CKPT_E_CORRUPT.
+ *   - Device pointers are plain virtual addresses in the HIP device's address
+ *     space (e.g. from hipMalloc, hipMallocManaged, or a PyTorch tensor's
+ *     data_ptr()).  Host pointers are plain process addresses.
+ *   - A stream argument is a hipStream_t passed as `void *`; NULL means the
+ *     device's null stream.
+ *   - Sizes are in bytes.
+ *   - The caller owns all registered and destination memory; the library never
+ *     frees or reallocates it.  Images belong to the caller and are freed with
+ *     ckpt_image_free; a view of an image stays valid until then.  A context
+ *     owns its device staging, pinned host buffers, tables and side stream.
+ *   - A context is used by one thread at a time.  ckpt_server_* calls are
+ *     thread-safe.
+ *   - After CKPT_E_HIP, ckpt_last_hip_error() / ckpt_last_error() describe
+ *     the failing HIP call (thread-local).
+ */
+#ifndef CKPT_H
+#define CKPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ckpt_ctx ckpt_ctx;
+typedef struct ckpt_image ckpt_image;
+typedef struct ckpt_server ckpt_server;
+
+/* Registration sequence number: 1, 2, 3, ... in ckpt_register order within a
+ * context, never reused.  The live set is always ordered by id. */
+typedef uint64_t ckpt_id;
+
+enum ckpt_kind {
+    CKPT_DEVICE = 0,   /* memory from hipMalloc (or a device tensor)      */
+    CKPT_MANAGED = 1   /* memory from hipMallocManaged                      */
+};
+
+enum ckpt_mode {
+    CKPT_FULL = 0,         /* every live chunk                                */
+    CKPT_INCREMENTAL = 1   /* only chunks whose CRC differs from a base image */
+};
+
+enum ckpt_status {
+    CKPT_OK = 0,
+    CKPT_E_INVAL = -1,     /* bad argument, alignment, overlap, truncated image   */
+    CKPT_E_NOTFOUND = -2,  /* unregister of a pointer that is not registered      */
+    CKPT_E_NOMEM = -3,     /* device, host or pinned allocation failed            */
+    CKPT_E_HIP = -4,       /* a HIP runtime call failed                          */
+    CKPT_E_MISMATCH = -5,  /* image / base / destination shapes disagree         */
+    CKPT_E_CORRUPT = -6,   /* restore: some chunk's CRC did not verify           */
+    CKPT_E_AGAIN = -7,     /* server: request not finished yet                   */
+    CKPT_E_BUDGET = -8     /* request larger than the staging budget              */
+};
+
+/* ckpt_config.flags */
+#define CKPT_STREAM_ORDERED 0x1u  /* order the checkpoint after work on the given
+                                     stream only; the caller promises that no
+                                     other stream writes registered memory.
+                                     Default: device-wide drain first.          */
+#define CKPT_KEEP_DENSE     0x2u  /* each image keeps its dense device copy
+                                     (section CKPT_SEC_DENSE)                    */
+#define CKPT_NO_DRAIN       0x4u  /* stop after pack + CRC: the image holds CRC,
+                                     flags and the dense device copy, and no host
+                                     DATA.  Without CKPT_KEEP_DENSE the dense copy
+                                     is the context's staging, valid until the
+                                     context's next checkpoint or restore.       */
+#define CKPT_TIMING         0x8u  /* record HIP events around each phase;
+                                     read them with ckpt_last_timing             */
+#define CKPT_DRAIN_DIRECT   0x10u /* drain by kernel stores straight into pinned
+                                     host memory instead of gather + copy engine */
+
+typedef struct ckpt_config {
+    int32_t device;            /* HIP device ordinal                                  */
+    uint32_t chunk_bytes;      /* C: a multiple of 16, 16 .. 2^30; 0 selects 4096     */
+    uint64_t staging_budget;   /* cap on device staging bytes held by the context
+                                  (dense image + compact drain buffer); 0 = no cap    */
+    uint32_t flags;            /* CKPT_* flags above                                  */
+    uint32_t block_threads;    /* threads per workgroup for the chunk kernels:
+                                  64, 128, 256, 512 or 1024; 0 selects 256            */
+    uint32_t waves_per_chunk;  /* waves that share one chunk (1, 2, 4, 8 or 16,
+                                  at most block_threads / 64); 0 selects 1            */
+    uint32_t wgs_per_cu;       /* persistent workgroups per compute unit; 0 = auto    */
+} ckpt_config;
+
+/* One row of an image's allocation table (section CKPT_SEC_ALLOCS). */
+typedef struct ckpt_alloc_rec {
+    uint64_t id;      /* registration id                                   */
+    uint32_t kind;    /* ckpt_kind                                         */
+    uint32_t pad;     /* 0                                                 */
+    uint64_t size;    /* bytes                                             */
+    uint64_t off;     /* offset in the dense image: exclusive prefix sum of
+                         sizes rounded up to 16                            */
+    uint64_t cb;      /* first global chunk id: exclusive prefix sum of
+                         ceil(size / C)                                    */
+} ckpt_alloc_rec;
+
+typedef struct ckpt_image_meta {
+    uint32_t mode;              /* CKPT_FULL or CKPT_INCREMENTAL                    */
+    uint32_t chunk_bytes;       /* C                                                */
+    uint64_t n_allocs;          /* rows in CKPT_SEC_ALLOCS                          */
+    uint64_t n_chunks;          /* N = sum of ceil(size / C)                        */
+    uint64_t data_bytes;        /* dense image bytes = sum of roundup16(size)       */
+    uint64_t serialized_bytes;  /* bytes in CKPT_SEC_DATA                           */
+    uint64_t n_dirty;           /* entries in CKPT_SEC_DIRTY_IDS (incremental)      */
+    uint64_t serial;            /* unique per image within the process              */
+    uint64_t base_serial;       /* incremental: serial of the base; else 0          */
+    uint64_t crc_digest;        /* 64-bit FNV-1a of the CRC section (checks a load) */
+    uint32_t has_dense;         /* 1 when CKPT_SEC_DENSE is available               */
+    uint32_t drained;           /* 1 when CKPT_SEC_DATA is valid                    */
+} ckpt_image_meta;
+
+enum ckpt_section {
+    CKPT_SEC_ALLOCS = 0,    /* host, ckpt_alloc_rec[n_allocs]                         */
+    CKPT_SEC_CRC = 1,       /* host, uint32_t[N]: CRC-32C of each chunk's bytes        */
+    CKPT_SEC_FLAGS = 2,     /* host, uint8_t[N]: bit0 ZERO (all bytes 0), bit1 DIRTY   */
+                            /* (no base, or CRC differs from the base's); others 0      */
+    CKPT_SEC_DATA = 3,      /* host (pinned), serialized bytes: full image = non-ZERO   */
+                            /* chunks in ascending id; incremental = DIRTY non-ZERO     */
+                            /* chunks; each chunk padded with zeros to a multiple of 16 */
+    CKPT_SEC_DIRTY_IDS = 4, /* host, uint64_t[n_dirty]: ascending ids of DIRTY chunks   */
+    CKPT_SEC_DENSE = 5      /* DEVICE pointer, data_bytes: allocation k at off_k,       */
+                            /* pad bytes zero (with CKPT_KEEP_DENSE or CKPT_NO_DRAIN)    */
+};
+
+#define CKPT_REPORT_MAX 64
+typedef struct ckpt_verify_report {
+    uint64_t n_bad;                 /* chunks whose CRC did not verify            */
+    uint64_t n_ids;                 /* min(n_bad, CKPT_REPORT_MAX)                */
+    uint64_t ids[CKPT_REPORT_MAX];  /* the smallest bad chunk ids, ascending      */
+} ckpt_verify_report;
+
+/* Per-phase times of the last checkpoint / restore on a context (needs
+ * CKPT_TIMING), measured with HIP events on the streams that ran each phase. */
+typedef struct ckpt_timing {
+    float order_ms;       /* device-wide drain of prior work                     */
+    float layout_ms;      /* descriptor upload + size scan + chunk map            */
+    float pack_ms;        /* fused pack + CRC + flags (or hash-only) kernel        */
+    float select_ms;      /* flag scan / compaction                                */
+    float gather_ms;      /* gather of selected chunks                             */
+    float d2h_ms;         /* device-to-host copy of data + metadata                */
+    float h2d_ms;         /* restore: host-to-device copy                          */
+    float scatter_ms;     /* restore: scatter + verify kernel(s)                   */
+    float total_ms;       /* whole call                                            */
+    float pad;
+    uint64_t pack_read_bytes;     /* algorithmic bytes read by the pack kernel      */
+    uint64_t pack_write_bytes;    /* algorithmic bytes written by the pack kernel   */
+    uint64_t link_bytes;          /* bytes over the host link                      */
+} ckpt_timing;
+
+/* --------------------------------------------------------------- context */
+
+/* Create a context on cfg->device.  cfg may be NULL (device 0, defaults).
+ * CKPT_E_INVAL: chunk_bytes not a multiple of 16 / out of range, bad
+ * block_threads or waves_per_chunk.  CKPT_E_HIP: no such device. */
+int ckpt_init(const ckpt_config *cfg, ckpt_ctx **out);
+
+/* Release the context's staging, pinned buffers, streams.  NULL is a no-op.
+ * Registered memory is the caller's and is not touched. */
+void ckpt_destroy(ckpt_ctx *ctx);
+
+/* Log one allocation, after the caller's own hipMalloc/hipMallocManaged
+ * (mirrors the paper's log of cudaMalloc-family pointers, Sec. 3.2).
+ * ptr must be 16-byte aligned; bytes may be 0; [ptr, ptr+bytes) must not
+ * overlap a live registration; kind is a ckpt_kind.  *out gets the id.
+ * CKPT_E_INVAL on a violation.  The memory is not read until a checkpoint. */
+int ckpt_register(ckpt_ctx *ctx, void *ptr, size_t bytes, int kind, ckpt_id *out);
+
+/* Remove the live registration that starts at ptr, before the caller frees it
+ * (mirrors the logged free that ends an active malloc, Sec. 3.2).
+ * CKPT_E_NOTFOUND if no live registration starts at ptr. */
+int ckpt_unregister(ckpt_ctx *ctx, void *ptr);
+
+/* Number of live registrations. */
+int ckpt_live_count(const ckpt_ctx *ctx, size_t *out);
+
+/* ------------------------------------------------------------ checkpoint */
+
+/*
+ * Drain every live registration, in id order, into a new image.
+ *
+ * Ordering: the image reflects all work enqueued on the device before the
+ * call (device-wide synchronize first, as in the paper's Sec. 2.2), or with
+ * CKPT_STREAM_ORDERED only the work enqueued on `stream` before the call.
+ * The packing kernel runs on `stream`; once it ends, `stream` may run new
+ * work, which does not affect the image: the drain to pinned host memory runs
+ * on the context's side stream from the dense device copy.  The call returns
+ * when the image is complete.
+ *
+ * mode CKPT_FULL: base may be NULL (every chunk DIRTY) or an image of the same
+ *   allocation table and chunk size (DIRTY against it).  DATA = non-ZERO chunks.
+ * mode CKPT_INCREMENTAL: base is required and must have the same allocation
+ *   table (ids, kinds, sizes) and chunk size, else CKPT_E_MISMATCH.  DATA =
+ *   DIRTY non-ZERO chunks; DIRTY_IDS = every DIRTY chunk; CRC and FLAGS are
+ *   complete, so the result can be the base of the next increment.
+ * CKPT_E_BUDGET if the dense image exceeds the staging budget.
+ */
+int ckpt_checkpoint(ckpt_ctx *ctx, void *stream, int mode, const ckpt_image *base,
+                    ckpt_image **out);
+
+/*
+ * Refill n_dst destination buffers from an image, and optionally overlay an
+ * incremental image (delta) on top.  dst[k] receives allocation k (id order);
+ * each dst[k] must be 16-byte aligned device memory of at least the
+ * allocation's size (dst_bytes[k] gives the buffer sizes; NULL = assume
+ * equal).  Every chunk is written (ZERO chunks as zeros) and its CRC
+ * recomputed on the device and compared with the stored one; a chunk that
+ * fails is still written.  The delta's chunks are applied after the base's,
+ * each verified against the delta's CRC.  Runs on `stream` and returns when
+ * the destination memory is written.
+ *
+ * CKPT_E_MISMATCH: n_dst differs from the image's allocation count, a
+ *   dst_bytes entry is smaller than its allocation, or the delta's allocation
+ *   table / chunk size / base serial does not match img.
+ * CKPT_E_INVAL: image without host DATA, misaligned dst.
+ * CKPT_E_CORRUPT: some chunk failed; rep (if given) holds the number of
+ *   distinct failing chunk ids and the smallest 64, ascending.
+ */
+int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, const ckpt_image *delta,
+                 void *const *dst, const size_t *dst_bytes, size_t n_dst,
+                 ckpt_verify_report *rep);
+
+/* ----------------------------------------------------------------- image */
+
+int ckpt_image_info(const ckpt_image *img, ckpt_image_meta *out);
+
+/* Pointer and length of one section (ckpt_section).  Host sections point into
+ * the image's own buffers; CKPT_SEC_DENSE is a device pointer.  A section that
+ * is absent gives *p = NULL, *bytes = 0 and CKPT_OK. */
+int ckpt_image_view(const ckpt_image *img, int section, const void **p, size_t *bytes);
+
+/* Serialize into buf (header + ALLOCS + CRC + FLAGS + DIRTY_IDS + DATA, all
+ * little-endian).  *need gets the required size; with cap < need nothing is
+ * written and CKPT_E_INVAL is returned (buf may be NULL to query). */
+int ckpt_image_serialize(const ckpt_image *img, void *buf, size_t cap, size_t *need);
+
+/* Parse a buffer written by ckpt_image_serialize into a new image (host
+ * sections only).  CKPT_E_INVAL: bad magic/version, truncated, inconsistent
+ * sizes. */
+int ckpt_image_load(ckpt_ctx *ctx, const void *buf, size_t bytes, ckpt_image **out);
+
+void ckpt_image_free(ckpt_image *img);
+
+/* --------------------------------------------------------------- batched */
+
+/*
+ * Checkpoint (CKPT_FULL) several contexts in one pass: every context's
+ * registrations are laid out in one table and packed by one persistent
+ * kernel launch.  outs[i] is the image of ctxs[i], identical to what
+ * ckpt_checkpoint(ctxs[i], stream, CKPT_FULL, NULL, ...) produces.  All
+ * contexts must be on one device with one chunk size (else CKPT_E_INVAL);
+ * ctxs[0] provides staging and streams.
+ */
+int ckpt_checkpoint_batch(ckpt_ctx *const *ctxs, size_t n, void *stream, ckpt_image **outs);
+
+/* --------------------------------------------------------------- timing */
+
+int ckpt_last_timing(const ckpt_ctx *ctx, ckpt_timing *out);
+
+/* ------------------------------------------------------------ diagnostics */
+
+const char *ckpt_strerror(int status);
+int ckpt_last_hip_error(void);          /* hipError_t of the last failing HIP call */
+const char *ckpt_last_error(void);      /* text for the last error on this thread  */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CKPT_H */

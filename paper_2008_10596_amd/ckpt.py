@@ -1,0 +1,354 @@
+"""ctypes binding of libckpt (include/ckpt.h): argument marshalling only.
+
+Every step of the data path runs in the library's HIP kernels; this module
+only converts Python values (ints, torch tensors, streams) to the C ABI and
+back.  The raw entry points keep their C names (ckpt_init, ckpt_register,
+...); Context / Image / checkpoint_batch are thin conveniences over them.
+
+torch is imported first on purpose: it loads its HIP runtime
+(libamdhip64.so.7), and libckpt.so then binds to that same runtime, so torch
+tensors and streams are valid in the library.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library shares)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libckpt.so")
+
+# ---- constants (mirror include/ckpt.h) -----------------------------------
+CKPT_DEVICE, CKPT_MANAGED = 0, 1
+CKPT_FULL, CKPT_INCREMENTAL = 0, 1
+CKPT_OK = 0
+CKPT_E_INVAL, CKPT_E_NOTFOUND, CKPT_E_NOMEM, CKPT_E_HIP = -1, -2, -3, -4
+CKPT_E_MISMATCH, CKPT_E_CORRUPT, CKPT_E_AGAIN, CKPT_E_BUDGET = -5, -6, -7, -8
+CKPT_STREAM_ORDERED = 0x1
+CKPT_KEEP_DENSE = 0x2
+CKPT_NO_DRAIN = 0x4
+CKPT_TIMING = 0x8
+CKPT_DRAIN_DIRECT = 0x10
+CKPT_SEC_ALLOCS, CKPT_SEC_CRC, CKPT_SEC_FLAGS, CKPT_SEC_DATA, CKPT_SEC_DIRTY_IDS, CKPT_SEC_DENSE = range(6)
+CKPT_REPORT_MAX = 64
+CKPT_REQ_CHECKPOINT, CKPT_REQ_RESTORE = 0, 1
+
+STATUS_NAMES = {0: "CKPT_OK", -1: "CKPT_E_INVAL", -2: "CKPT_E_NOTFOUND", -3: "CKPT_E_NOMEM",
+                -4: "CKPT_E_HIP", -5: "CKPT_E_MISMATCH", -6: "CKPT_E_CORRUPT", -7: "CKPT_E_AGAIN",
+                -8: "CKPT_E_BUDGET"}
+
+
+class ckpt_config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("chunk_bytes", ctypes.c_uint32),
+                ("staging_budget", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("block_threads", ctypes.c_uint32), ("waves_per_chunk", ctypes.c_uint32),
+                ("wgs_per_cu", ctypes.c_uint32)]
+
+
+class ckpt_alloc_rec(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("kind", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("size", ctypes.c_uint64), ("off", ctypes.c_uint64), ("cb", ctypes.c_uint64)]
+
+
+ALLOC_DTYPE = np.dtype([("id", "<u8"), ("kind", "<u4"), ("pad", "<u4"), ("size", "<u8"),
+                        ("off", "<u8"), ("cb", "<u8")])
+
+
+class ckpt_image_meta(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_uint32), ("chunk_bytes", ctypes.c_uint32),
+                ("n_allocs", ctypes.c_uint64), ("n_chunks", ctypes.c_uint64),
+                ("data_bytes", ctypes.c_uint64), ("serialized_bytes", ctypes.c_uint64),
+                ("n_dirty", ctypes.c_uint64), ("serial", ctypes.c_uint64),
+                ("base_serial", ctypes.c_uint64), ("crc_digest", ctypes.c_uint64),
+                ("has_dense", ctypes.c_uint32), ("drained", ctypes.c_uint32)]
+
+
+class ckpt_verify_report(ctypes.Structure):
+    _fields_ = [("n_bad", ctypes.c_uint64), ("n_ids", ctypes.c_uint64),
+                ("ids", ctypes.c_uint64 * CKPT_REPORT_MAX)]
+
+
+class ckpt_timing(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_float) for n in ("order_ms", "layout_ms", "pack_ms", "select_ms",
+                                                "gather_ms", "d2h_ms", "h2d_ms", "scatter_ms",
+                                                "total_ms", "pad")] + \
+               [("pack_read_bytes", ctypes.c_uint64), ("pack_write_bytes", ctypes.c_uint64),
+                ("link_bytes", ctypes.c_uint64)]
+
+
+class ckpt_server_config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("chunk_bytes", ctypes.c_uint32),
+                ("staging_budget", ctypes.c_uint64), ("step_bytes", ctypes.c_uint64),
+                ("max_active", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("block_threads", ctypes.c_uint32), ("waves_per_chunk", ctypes.c_uint32)]
+
+
+class ckpt_request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_uint32), ("n", ctypes.c_uint32),
+                ("ptrs", ctypes.POINTER(ctypes.c_void_p)), ("sizes", ctypes.POINTER(ctypes.c_uint64)),
+                ("kinds", ctypes.POINTER(ctypes.c_uint32)), ("image", ctypes.c_void_p)]
+
+
+class ckpt_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("op", ctypes.c_uint32), ("image", ctypes.c_void_p),
+                ("latency_ms", ctypes.c_double), ("queue_ms", ctypes.c_double),
+                ("bytes", ctypes.c_uint64), ("n_bad", ctypes.c_uint64)]
+
+
+class ckpt_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("makespan_s", ctypes.c_double), ("gbps", ctypes.c_double),
+                ("steps", ctypes.c_uint64), ("max_concurrent", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
+
+
+_vp = ctypes.c_void_p
+_ip = ctypes.POINTER(ctypes.c_int)
+
+# (name, restype, argtypes) of every entry point in include/ckpt.h
+SIGNATURES = [
+    ("ckpt_init", ctypes.c_int, [ctypes.POINTER(ckpt_config), ctypes.POINTER(_vp)]),
+    ("ckpt_destroy", None, [_vp]),
+    ("ckpt_register", ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]),
+    ("ckpt_unregister", ctypes.c_int, [_vp, _vp]),
+    ("ckpt_live_count", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    ("ckpt_checkpoint", ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
+    ("ckpt_restore", ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t),
+                                    ctypes.c_size_t, ctypes.POINTER(ckpt_verify_report)]),
+    ("ckpt_image_info", ctypes.c_int, [_vp, ctypes.POINTER(ckpt_image_meta)]),
+    ("ckpt_image_view", ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t)]),
+    ("ckpt_image_serialize", ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    ("ckpt_image_load", ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]),
+    ("ckpt_image_free", None, [_vp]),
+    ("ckpt_checkpoint_batch", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    ("ckpt_last_timing", ctypes.c_int, [_vp, ctypes.POINTER(ckpt_timing)]),
+    ("ckpt_strerror", ctypes.c_char_p, [ctypes.c_int]),
+    ("ckpt_last_hip_error", ctypes.c_int, []),
+    ("ckpt_last_error", ctypes.c_char_p, []),
+    ("ckpt_server_create", ctypes.c_int, [ctypes.POINTER(ckpt_server_config), ctypes.POINTER(_vp)]),
+    ("ckpt_server_submit", ctypes.c_int, [_vp, ctypes.POINTER(ckpt_request), ctypes.POINTER(ctypes.c_uint64)]),
+    ("ckpt_server_poll", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ckpt_result)]),
+    ("ckpt_server_wait", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ckpt_result)]),
+    ("ckpt_server_stats", ctypes.c_int, [_vp, ctypes.POINTER(ckpt_stats)]),
+    ("ckpt_server_reset_stats", ctypes.c_int, [_vp]),
+    ("ckpt_server_destroy", None, [_vp]),
+]
+
+_lib = None
+
+
+def lib():
+    """The loaded libckpt.so.  Raises if it has not been built: there is no
+    fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libckpt.so is not built (%s); run `python -m paper_2008_10596_amd.build`"
+                               % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name, None)
+            if fn is None:
+                continue
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class CkptError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        msg = lib().ckpt_last_error()
+        self.detail = msg.decode() if msg else ""
+        super().__init__("%s: %s (%s) %s" % (where, STATUS_NAMES.get(status, status),
+                                             lib().ckpt_strerror(status).decode(), self.detail))
+
+
+def _check(rc, where):
+    if rc != CKPT_OK:
+        raise CkptError(rc, where)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream   # torch.cuda.Stream
+
+
+def _ptr(x):
+    if isinstance(x, torch.Tensor):
+        return x.data_ptr()
+    return int(x)
+
+
+def _nbytes(x):
+    return x.numel() * x.element_size()
+
+
+def _np_view(p, nbytes, dtype):
+    """Zero-copy numpy view of host memory owned by the library."""
+    dt = np.dtype(dtype)
+    if not p or nbytes == 0:
+        return np.zeros(0, dt)
+    buf = (ctypes.c_uint8 * nbytes).from_address(p)
+    return np.frombuffer(buf, dtype=dt)
+
+
+# ---- images ---------------------------------------------------------------
+
+class Image:
+    """Owns one ckpt_image; frees it on close() / garbage collection."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            lib().ckpt_image_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        m = ckpt_image_meta()
+        _check(lib().ckpt_image_info(self.handle, ctypes.byref(m)), "ckpt_image_info")
+        return {f: getattr(m, f) for f, _ in ckpt_image_meta._fields_}
+
+    def view(self, section):
+        p, n = _vp(), ctypes.c_size_t()
+        _check(lib().ckpt_image_view(self.handle, section, ctypes.byref(p), ctypes.byref(n)), "ckpt_image_view")
+        return p.value or 0, n.value
+
+    def _arr(self, section, dtype):
+        p, n = self.view(section)
+        return _np_view(p, n, dtype)
+
+    # numpy views (valid while the image is open)
+    @property
+    def allocs(self):
+        return self._arr(CKPT_SEC_ALLOCS, ALLOC_DTYPE)
+
+    @property
+    def crc(self):
+        return self._arr(CKPT_SEC_CRC, np.uint32)
+
+    @property
+    def flags(self):
+        return self._arr(CKPT_SEC_FLAGS, np.uint8)
+
+    @property
+    def data(self):
+        return self._arr(CKPT_SEC_DATA, np.uint8)
+
+    @property
+    def dirty_ids(self):
+        return self._arr(CKPT_SEC_DIRTY_IDS, np.uint64)
+
+    @property
+    def dense_ptr(self):
+        return self.view(CKPT_SEC_DENSE)
+
+    def serialize(self):
+        need = ctypes.c_size_t()
+        _check(lib().ckpt_image_serialize(self.handle, None, 0, ctypes.byref(need)), "ckpt_image_serialize")
+        buf = (ctypes.c_uint8 * need.value)()
+        _check(lib().ckpt_image_serialize(self.handle, buf, need.value, ctypes.byref(need)),
+               "ckpt_image_serialize")
+        return bytes(buf)
+
+    @staticmethod
+    def load(buf, ctx=None):
+        b = (ctypes.c_uint8 * len(buf)).from_buffer_copy(buf)
+        out = _vp()
+        _check(lib().ckpt_image_load(ctx.handle if ctx else None, b, len(buf), ctypes.byref(out)),
+               "ckpt_image_load")
+        return Image(out.value)
+
+
+# ---- contexts ---------------------------------------------------------------
+
+class Context:
+    def __init__(self, device=0, chunk_bytes=4096, staging_budget=0, flags=0, block_threads=0,
+                 waves_per_chunk=0, wgs_per_cu=0):
+        cfg = ckpt_config(device, chunk_bytes, staging_budget, flags, block_threads, waves_per_chunk,
+                          wgs_per_cu)
+        h = _vp()
+        _check(lib().ckpt_init(ctypes.byref(cfg), ctypes.byref(h)), "ckpt_init")
+        self.handle = h.value
+        self.chunk_bytes = chunk_bytes or 4096
+
+    def close(self):
+        if self.handle:
+            lib().ckpt_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def register(self, ptr, nbytes=None, kind=CKPT_DEVICE):
+        if nbytes is None:
+            nbytes = _nbytes(ptr)
+        out = ctypes.c_uint64()
+        _check(lib().ckpt_register(self.handle, _ptr(ptr), nbytes, kind, ctypes.byref(out)), "ckpt_register")
+        return out.value
+
+    def unregister(self, ptr):
+        _check(lib().ckpt_unregister(self.handle, _ptr(ptr)), "ckpt_unregister")
+
+    def live_count(self):
+        n = ctypes.c_size_t()
+        _check(lib().ckpt_live_count(self.handle, ctypes.byref(n)), "ckpt_live_count")
+        return n.value
+
+    def checkpoint(self, stream=None, mode=CKPT_FULL, base=None):
+        out = _vp()
+        _check(lib().ckpt_checkpoint(self.handle, _stream_handle(stream), mode,
+                                     base.handle if base else None, ctypes.byref(out)), "ckpt_checkpoint")
+        return Image(out.value)
+
+    def restore(self, image, dsts, delta=None, stream=None, dst_bytes=None, raise_on_corrupt=False):
+        """Refill dsts (tensors or device addresses) from image (+ delta).
+        Returns (status, report dict); raises on every status but OK/CORRUPT."""
+        n = len(dsts)
+        ptrs = (_vp * max(n, 1))(*[_ptr(d) for d in dsts])
+        if dst_bytes is None and all(isinstance(d, torch.Tensor) for d in dsts):
+            dst_bytes = [_nbytes(d) for d in dsts]
+        sizes = (ctypes.c_size_t * max(n, 1))(*dst_bytes) if dst_bytes is not None else None
+        rep = ckpt_verify_report()
+        rc = lib().ckpt_restore(self.handle, _stream_handle(stream), image.handle,
+                                delta.handle if delta else None, ptrs, sizes, n, ctypes.byref(rep))
+        if rc not in (CKPT_OK, CKPT_E_CORRUPT) or (rc == CKPT_E_CORRUPT and raise_on_corrupt):
+            raise CkptError(rc, "ckpt_restore")
+        return rc, {"n_bad": rep.n_bad, "ids": [rep.ids[i] for i in range(rep.n_ids)]}
+
+    def timing(self):
+        t = ckpt_timing()
+        _check(lib().ckpt_last_timing(self.handle, ctypes.byref(t)), "ckpt_last_timing")
+        return {f: getattr(t, f) for f, _ in ckpt_timing._fields_ if f != "pad"}
+
+
+def checkpoint_batch(ctxs, stream=None):
+    n = len(ctxs)
+    hs = (_vp * n)(*[c.handle for c in ctxs])
+    outs = (_vp * n)()
+    _check(lib().ckpt_checkpoint_batch(hs, n, _stream_handle(stream), outs), "ckpt_checkpoint_batch")
+    return [Image(outs[i]) for i in range(n)]

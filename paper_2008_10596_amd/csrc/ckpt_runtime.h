@@ -1,0 +1,148 @@
+// ckpt_runtime.h -- host-side types of libckpt (not part of the public ABI).
+#pragma once
+
+#include <cstddef>
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "ckpt.h"
+#include "internal.h"
+
+namespace ckpt {
+
+int set_error(int status, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what, int line);
+
+#define HIP_TRY(expr)                                                   \
+    do {                                                                \
+        hipError_t e_ = (expr);                                         \
+        if (e_ != hipSuccess)                                           \
+            return ::ckpt::hip_fail(e_, #expr, __LINE__);               \
+    } while (0)
+
+#define CKPT_TRY(expr)                                                  \
+    do {                                                                \
+        int rc_ = (expr);                                               \
+        if (rc_ != CKPT_OK)                                             \
+            return rc_;                                                 \
+    } while (0)
+
+// Grow-only device buffer.
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes);
+    void release();
+};
+
+// Pinned host buffer from the process-wide pool; returned to the pool when
+// released or destroyed.
+struct PinnedBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    PinnedBuf() = default;
+    PinnedBuf(const PinnedBuf &) = delete;
+    PinnedBuf &operator=(const PinnedBuf &) = delete;
+    PinnedBuf(PinnedBuf &&o) noexcept : p(o.p), cap(o.cap) { o.p = nullptr; o.cap = 0; }
+    PinnedBuf &operator=(PinnedBuf &&o) noexcept
+    {
+        if (this != &o) {
+            release();
+            p = o.p;
+            cap = o.cap;
+            o.p = nullptr;
+            o.cap = 0;
+        }
+        return *this;
+    }
+    ~PinnedBuf() { release(); }
+    int ensure(size_t bytes);
+    void release();
+};
+
+class DeviceGuard {
+public:
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+    bool ok() const { return ok_; }
+
+private:
+    int prev_ = 0;
+    bool ok_ = false;
+};
+
+// One row of a table to drain or refill.
+struct Row {
+    uint64_t id = 0;
+    uint32_t kind = 0;
+    uint64_t ptr = 0;    // source (checkpoint) or destination (restore) address
+    uint64_t size = 0;
+};
+using Reg = Row;
+
+struct RangeEnd {
+    uint64_t end;
+    uint64_t id;
+};
+
+}  // namespace ckpt
+
+struct ckpt_ctx {
+    ckpt_config cfg{};
+    int cu_count = 0;
+    int grid_chunks = 0;   // persistent workgroups of the chunk kernels
+    int grid_small = 0;    // grid of the map / gather kernels
+    bool managed_prefetch = false;
+    hipStream_t side = nullptr;
+    hipEvent_t ev[8] = {};
+
+    // the log: live registrations in id order, and their ranges by start
+    std::vector<ckpt::Reg> live;
+    std::map<uint64_t, ckpt::RangeEnd> ranges;
+    uint64_t next_id = 1;
+
+    // device buffers
+    ckpt::DevBuf d_tables, d_plan, d_addr, d_size, d_off, d_cb, d_map;
+    ckpt::DevBuf d_crc, d_flags, d_base_crc, d_prev_crc, d_soff, d_ids, d_tile_b, d_tile_c;
+    ckpt::DevBuf d_dense, d_compact, d_bad, d_pick, d_crc2, d_flags2, d_soff2;
+    ckpt::PinnedBuf h_up, h_plan;
+    uint64_t prev_serial = 0;   // image whose CRC array is in d_prev_crc
+
+    ckpt_timing timing{};
+
+    std::vector<ckpt::DevBuf *> all_dev()
+    {
+        return {&d_tables, &d_plan, &d_addr, &d_size, &d_off, &d_cb, &d_map, &d_crc, &d_flags, &d_base_crc,
+                &d_prev_crc, &d_soff, &d_ids, &d_tile_b, &d_tile_c, &d_dense, &d_compact, &d_bad, &d_pick,
+                &d_crc2, &d_flags2, &d_soff2};
+    }
+};
+
+struct ckpt_image {
+    int device = 0;
+    uint32_t mode = CKPT_FULL;
+    uint32_t C = 0;
+    uint64_t N = 0, data_bytes = 0, ser_bytes = 0, n_dirty = 0;
+    uint64_t serial = 0, base_serial = 0, digest = 0;
+    bool drained = false;
+    std::vector<ckpt_alloc_rec> allocs;
+    ckpt::PinnedBuf crc_buf, flags_buf, ids_buf, data;
+    void *dense = nullptr;
+    bool dense_owned = false;
+    ~ckpt_image();
+};
+
+namespace ckpt {
+
+int ctx_setup(ckpt_ctx *ctx);
+int upload_table(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, bool dst_side, uint64_t N_host,
+                 uint64_t n_items);
+int read_plan(ckpt_ctx *ctx, hipStream_t s, DevPlan *out);
+int run_select(ckpt_ctx *ctx, hipStream_t s, int mode, const uint8_t *flags, const uint64_t *ids,
+               uint64_t max_items, uint64_t *soff, uint64_t *ids_out, uint64_t ids_cap);
+ChunkArgs chunk_args(ckpt_ctx *ctx);
+int run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_image *base, const std::vector<Row> &rows,
+                   const std::vector<size_t> &parts, std::vector<ckpt_image *> &outs);
+
+}  // namespace ckpt

@@ -1,0 +1,47 @@
+// crc_tables.cpp -- CRC-32C shift-operator tables for the GPU kernels.
+//
+// The CRC register is a linear function over GF(2) of its previous value and
+// the data, so "feed m zero bytes" is a 32 x 32 bit matrix.  Its columns are
+// found by running each single-bit register value through m zero bytes, bit by
+// bit; a table entry for byte position j and byte value b is the XOR of the
+// columns of b's set bits, shifted to position j.
+#include "internal.h"
+
+namespace ckpt {
+
+// One zero bit through the reflected register.
+static uint32_t step_bit(uint32_t r) { return (r & 1u) ? (r >> 1) ^ kPolyReflected : (r >> 1); }
+
+uint32_t host_shift(uint32_t reg, uint64_t nbytes)
+{
+    for (uint64_t i = 0; i < 8 * nbytes; i++)
+        reg = step_bit(reg);
+    return reg;
+}
+
+// out[j*256 + b] = shift(b << 8j, m)
+static void build_operator(uint32_t *out, uint64_t m)
+{
+    uint32_t col[32];
+    for (int i = 0; i < 32; i++)
+        col[i] = host_shift(1u << i, m);
+    for (int j = 0; j < 4; j++)
+        for (int b = 0; b < 256; b++) {
+            uint32_t v = 0;
+            for (int i = 0; i < 8; i++)
+                if (b & (1 << i))
+                    v ^= col[8 * j + i];
+            out[j * 256 + b] = v;
+        }
+}
+
+void build_tables(uint32_t *out, uint32_t rounds_per_wave)
+{
+    build_operator(out + kTabChain, 4);
+    build_operator(out + kTabGap, kRoundBytes - 16);
+    for (int k = 0; k < kTreeLevels; k++)
+        build_operator(out + kTabTree + k * kTabWords, 16ull << k);
+    build_operator(out + kTabSeg, (uint64_t)rounds_per_wave * kRoundBytes);
+}
+
+}  // namespace ckpt

@@ -1,0 +1,135 @@
+// internal.h -- shared declarations of libckpt's HIP kernels and host runtime.
+//
+// Not part of the public ABI (that is include/ckpt.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ckpt {
+
+// CRC-32C, reflected form of the Castagnoli polynomial.
+constexpr uint32_t kPolyReflected = 0x82F63B78u;
+
+// Shift-operator tables.  Every table is an operator "feed m zero bytes
+// through the CRC register" stored as 4 x 256 words: S[j][b] is the operator
+// applied to the register value b << 8j, so applying it to v is the XOR of the
+// four entries picked by v's bytes.  The chain step over one 4-byte word w from
+// register s is the 4-byte operator applied to (s ^ w).
+constexpr int kTabWords = 1024;                 // one operator, 4 x 256 words
+constexpr int kTabChain = 0;                    // m = 4 (slicing by 4)
+constexpr int kTabGap = 1 * kTabWords;          // m = 1008: between 16-byte pieces one round apart
+constexpr int kTabTree = 2 * kTabWords;         // m = 16 << k, k = 0..5: cross-lane tree
+constexpr int kTreeLevels = 6;
+constexpr int kTabSeg = kTabTree + kTreeLevels * kTabWords;  // m = rounds_per_wave * 1024:
+                                                              // cross-wave combine
+constexpr int kTabTotalWords = kTabSeg + kTabWords;          // 9 operators, 36 KiB
+
+constexpr int kRoundBytes = 1024;   // one wave64 x 16-byte load
+constexpr int kFlagZero = 1;
+constexpr int kFlagDirty = 2;
+
+// Counts the kernels read from device memory, so that one captured graph
+// serves any table that fits the buffers it was captured with.
+struct DevPlan {
+    uint64_t n_allocs;    // rows in the allocation table
+    uint64_t n_chunks;    // N, written by the layout scan
+    uint64_t data_bytes;  // dense bytes, written by the layout scan
+    uint64_t n_items;     // items of a restore pass (N, or the delta's id count)
+    uint64_t sel_bytes;   // selection scan: total selected bytes
+    uint64_t sel_count;   // selection scan: total selected ids
+    unsigned long long bad_count;  // restore: chunks that failed verification
+    uint64_t pad;
+};
+
+enum ChunkMode { kModePack = 0, kModeHash = 1, kModeRestore = 2 };
+
+struct ChunkArgs {
+    const DevPlan *plan;
+    const uint32_t *tables;   // kTabTotalWords words
+    uint32_t C;
+    uint32_t waves_per_chunk;
+    // allocation table (n rows; off and cb have n + 1)
+    const uint64_t *src;      // pack/hash: source address of each allocation
+    const uint64_t *dst;      // restore: destination address of each allocation
+    const uint64_t *size;
+    const uint64_t *off;
+    const uint64_t *cb;
+    const uint32_t *map;      // chunk id -> allocation row
+    // pack / hash outputs
+    uint8_t *dense;           // pack: dense image
+    uint32_t *crc;
+    uint8_t *flags;
+    const uint32_t *base_crc; // nullable
+    // restore inputs
+    const uint8_t *staging;   // serialized chunks
+    const uint64_t *soff;     // item -> offset in staging
+    const uint32_t *want_crc;
+    const uint8_t *want_flags;
+    const uint64_t *ids;      // nullable: item i is chunk ids[i], else chunk i
+    uint8_t *bad;             // per chunk, set to 1 when verification fails
+    DevPlan *plan_rw;         // bad_count lives here
+};
+
+enum SelMode {
+    kSelNonZero = 0,       // bytes: !ZERO chunks;            count: none
+    kSelDirtyNonZero = 1,  // bytes: DIRTY && !ZERO chunks;   count: DIRTY chunks (ids out)
+    kSelIdsNonZero = 2,    // items are ids[i]; bytes: !ZERO;  count: none
+    kSelBad = 3            // bytes: none;                     count: bad chunks (ids out)
+};
+
+struct SelArgs {
+    DevPlan *plan;
+    int mode;
+    uint32_t C;
+    const uint64_t *size;
+    const uint64_t *cb;
+    const uint32_t *map;
+    const uint8_t *flags;     // flags of the chunks (or bad[] for kSelBad)
+    const uint64_t *ids;      // kSelIdsNonZero
+    uint64_t *tile_bytes;     // per tile totals, then bases
+    uint64_t *tile_count;
+    uint64_t *soff;           // per item: exclusive prefix of selected bytes
+    uint64_t *ids_out;        // selected ids, ascending (count side)
+    uint64_t ids_cap;         // capacity of ids_out
+};
+
+constexpr int kSelThreads = 256;
+constexpr int kSelPerThread = 16;
+constexpr int kSelTile = kSelThreads * kSelPerThread;
+
+struct GatherArgs {
+    const DevPlan *plan;
+    int mode;                 // kSelNonZero or kSelDirtyNonZero: which chunks
+    int from_dense;           // 1: read the dense image; 0: read the allocations
+    uint32_t C;
+    const uint64_t *src;
+    const uint64_t *size;
+    const uint64_t *off;
+    const uint64_t *cb;
+    const uint32_t *map;
+    const uint8_t *dense;
+    const uint8_t *flags;
+    const uint64_t *soff;
+    uint8_t *out;             // device buffer or mapped pinned host buffer
+};
+
+// Launch wrappers (kernels.hip).  All return the hipError_t of the launch.
+hipError_t launch_layout_scan(hipStream_t s, DevPlan *plan, const uint64_t *size, uint32_t C,
+                              uint64_t *off, uint64_t *cb);
+hipError_t launch_chunk_map(hipStream_t s, const DevPlan *plan, const uint64_t *cb, uint32_t *map,
+                            int grid);
+hipError_t launch_chunks(hipStream_t s, int mode, const ChunkArgs &a, int grid, int block);
+hipError_t launch_select(hipStream_t s, const SelArgs &a, uint64_t max_items);
+hipError_t launch_gather(hipStream_t s, const GatherArgs &a, int grid);
+hipError_t launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t n_words, uint64_t value);
+hipError_t launch_pick_u64(hipStream_t s, const uint64_t *src, const uint64_t *idx, uint64_t *out,
+                           uint32_t m);
+
+// Host-side table generation (crc_tables.cpp): fills kTabTotalWords words for
+// a launch in which each wave owns `rounds_per_wave` consecutive 1 KiB rounds.
+void build_tables(uint32_t *out, uint32_t rounds_per_wave);
+// Register after feeding nbytes zero bytes (host, for tests of the tables).
+uint32_t host_shift(uint32_t reg, uint64_t nbytes);
+
+}  // namespace ckpt

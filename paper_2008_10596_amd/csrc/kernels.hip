@@ -1,0 +1,632 @@
+// kernels.hip -- gfx950 kernels of libckpt: size scan, chunk map, fused
+// pack + CRC-32C + ZERO/DIRTY flags (and its hash-only and restore/verify
+// variants), selection scan, gather, and small helpers.
+//
+// The data path drains the memory of live allocations into an image and
+// refills it (CRAC, Sec. 3.2 "Saving the library-allocated arena" and
+// "restoring the CUDA library-allocated regions").  It is pure bandwidth
+// work: no MFMA.  The CRC-32C per chunk is the library's own check.
+//
+// CRC scheme (one wave64 per chunk, or `waves_per_chunk` waves):
+//   * The chunk's bytes are read in rounds of 1 KiB: lane l of round r loads
+//     the 16-byte piece r*64 + l (one coalesced 16-byte load per lane).
+//   * A chunk of len bytes is placed at the END of a window of R whole rounds
+//     (leading zero pieces, and zeros after len up to the next 16 bytes).
+//     Leading zeros leave a zero CRC register unchanged, so the window's raw
+//     CRC (zero init, no final XOR) equals that of the data followed by its
+//     s = roundup16(len) - len zero pad bytes; the pad is undone at the end by
+//     running the register backwards s bytes.
+//   * Each lane folds its pieces into one register: a slicing-by-4 chain over
+//     the piece's four words, with the register moved forward 1008 bytes (the
+//     gap to the same lane's piece in the next round) before each new piece.
+//   * A 6-level tree across lanes combines the registers: at level k the left
+//     partner is moved forward 16 << k bytes and XORed with the right one.
+//   * With several waves per chunk, each wave owns consecutive rounds and the
+//     per-wave results are combined by one more operator (rounds_per_wave KiB).
+//   * CRC-32C's initial value 0xFFFFFFFF is folded in by complementing the
+//     first min(len, 4) data bytes before hashing (and, for len < 4, XORing
+//     the part of the initial value that is still in the register), and the
+//     final XOR is applied last.
+//   Every "move forward m bytes" is a GF(2)-linear operator stored in LDS as
+//   four 256-entry byte tables (crc_tables.cpp).
+#include "internal.h"
+
+namespace ckpt {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ uint32_t apply_op(const uint32_t *__restrict__ t, uint32_t v)
+{
+    return t[v & 0xffu] ^ t[256 + ((v >> 8) & 0xffu)] ^ t[512 + ((v >> 16) & 0xffu)] ^
+           t[768 + (v >> 24)];
+}
+
+__device__ __forceinline__ uint64_t round_up16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
+
+// Wave64 inclusive scan of a u64 (Hillis-Steele with shuffles).
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint64_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Bytes [0, valid) of a 16-byte piece, zeros after; never reads past valid.
+__device__ __forceinline__ uint4 load_partial(const uint8_t *p, uint32_t valid)
+{
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 16; i++)
+        if ((uint32_t)i < valid)
+            w[i >> 2] |= (uint32_t)p[i] << (8 * (i & 3));
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Writes bytes [0, valid) of a 16-byte piece only.
+__device__ __forceinline__ void store_partial(uint8_t *p, uint32_t valid, uint4 v)
+{
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 16; i++)
+        if ((uint32_t)i < valid)
+            p[i] = (uint8_t)(w[i >> 2] >> (8 * (i & 3)));
+}
+
+// Undo `s` zero pad bytes: the register one zero bit earlier is recovered
+// from its top bit (set exactly when the polynomial was XORed in).
+__device__ __forceinline__ uint32_t unshift_bytes(uint32_t reg, uint32_t s)
+{
+    for (uint32_t i = 0; i < 8 * s; i++)
+        reg = (reg & 0x80000000u) ? (((reg ^ kPolyReflected) << 1) | 1u) : (reg << 1);
+    return reg;
+}
+
+// Mask that complements the first min(n, 4) bytes of the first data word.
+__device__ __forceinline__ uint32_t init_mask(uint32_t n)
+{
+    return n >= 4 ? 0xFFFFFFFFu : ((1u << (8 * n)) - 1u);
+}
+
+// CRC-32C from the window's raw register.
+__device__ __forceinline__ uint32_t finish_crc(uint32_t raw, uint32_t n)
+{
+    uint32_t reg = unshift_bytes(raw, (uint32_t)round_up16(n) - n);
+    if (n < 4)
+        reg ^= 0xFFFFFFFFu >> (8 * n);
+    return ~reg;
+}
+
+// ---------------------------------------------------------- K1: size scan
+//
+// off[k] = exclusive prefix sum of roundup16(size), cb[k] = exclusive prefix
+// sum of ceil(size / C); off[n] and cb[n] get the totals, copied to the plan.
+// One workgroup of 1024 threads walks the table in tiles of 1024.
+
+__global__ __launch_bounds__(1024) void k_layout_scan(DevPlan *plan, const uint64_t *__restrict__ size,
+                                                      uint32_t C, uint64_t *__restrict__ off,
+                                                      uint64_t *__restrict__ cb)
+{
+    __shared__ uint64_t s_off[16], s_cb[16];
+    const uint64_t n = plan->n_allocs;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t carry_off = 0, carry_cb = 0;
+    for (uint64_t base = 0; base < n; base += 1024) {
+        const uint64_t k = base + threadIdx.x;
+        const uint64_t sz = k < n ? size[k] : 0;
+        const uint64_t e = round_up16(sz), c = (sz + C - 1) / C;
+        const uint64_t ie = wave_incl_scan(e, lane), ic = wave_incl_scan(c, lane);
+        if (lane == 63) {
+            s_off[wave] = ie;
+            s_cb[wave] = ic;
+        }
+        __syncthreads();
+        uint64_t pre_off = carry_off, pre_cb = carry_cb, tot_off = 0, tot_cb = 0;
+        for (int w = 0; w < 16; w++) {
+            if (w < wave) {
+                pre_off += s_off[w];
+                pre_cb += s_cb[w];
+            }
+            tot_off += s_off[w];
+            tot_cb += s_cb[w];
+        }
+        if (k < n) {
+            off[k] = pre_off + ie - e;
+            cb[k] = pre_cb + ic - c;
+        }
+        carry_off += tot_off;
+        carry_cb += tot_cb;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        off[n] = carry_off;
+        cb[n] = carry_cb;
+        plan->data_bytes = carry_off;
+        plan->n_chunks = carry_cb;
+    }
+}
+
+// ------------------------------------------------------- chunk -> row map
+//
+// map[g] = k for every chunk g of allocation k: the descriptor table each
+// workgroup of the chunk kernels stages into LDS, one load per chunk instead
+// of a binary search.
+
+__global__ void k_chunk_map(const DevPlan *plan, const uint64_t *__restrict__ cb, uint32_t *__restrict__ map)
+{
+    const uint64_t n = plan->n_allocs;
+    const int lane = threadIdx.x & 63;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t k = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); k < n; k += waves) {
+        const uint64_t b = cb[k], e = cb[k + 1];
+        for (uint64_t g = b + lane; g < e; g += 64)
+            map[g] = (uint32_t)k;
+    }
+}
+
+// -------------------------------------------- K3/K4/K8: the chunk kernels
+//
+// Persistent workgroups take tiles of kTile chunk items; each tile's
+// descriptors are staged in LDS once, then groups of waves_per_chunk waves
+// take one item each.
+//   kModePack:    read the allocation, write the dense image, CRC + flags.
+//   kModeHash:    read the allocation, CRC + flags (incremental checkpoints).
+//   kModeRestore: read the serialized chunk from staging (or zeros for a
+//                 ZERO chunk), write the destination (exactly len bytes),
+//                 recompute the CRC and compare with the stored one.
+
+constexpr int kTile = 64;
+
+struct Desc {
+    uint64_t src;   // pack/hash: source address; restore: staging address (0 for ZERO)
+    uint64_t dst;   // pack: dense address; restore: destination address
+    uint64_t g;     // chunk id
+    uint32_t len;   // bytes in the chunk
+    uint32_t zero;  // restore: the chunk is ZERO
+};
+
+template <int MODE>
+__device__ __forceinline__ uint4 load_piece(const Desc &d, uint32_t start)
+{
+    if (MODE == kModeRestore) {
+        if (d.zero)
+            return make_uint4(0u, 0u, 0u, 0u);
+        return *(const uint4 *)(d.src + start);   // staging pieces are padded to 16
+    }
+    const uint8_t *p = (const uint8_t *)d.src + start;
+    if (start + 16 <= d.len)
+        return *(const uint4 *)p;
+    return load_partial(p, d.len - start);
+}
+
+template <int MODE>
+__device__ __forceinline__ void store_piece(const Desc &d, uint32_t start, uint4 v)
+{
+    if (MODE == kModePack) {
+        *(uint4 *)(d.dst + start) = v;            // dense image keeps the zero pad
+    } else if (MODE == kModeRestore) {
+        uint8_t *p = (uint8_t *)d.dst + start;
+        if (start + 16 <= d.len)
+            *(uint4 *)p = v;
+        else
+            store_partial(p, d.len - start, v);
+    }
+}
+
+// One wave's share of a chunk: rounds [r_begin, r_end) of a window of r_win
+// rounds.  Returns the raw register of those rounds in lane 0 (as a message
+// ending with the wave's last round) and ORs the data words into *orv.
+template <int MODE>
+__device__ __forceinline__ uint32_t wave_rounds(const uint32_t *__restrict__ tabs, const Desc &d, int lane,
+                                                uint32_t r_begin, uint32_t r_end, uint32_t r_win,
+                                                uint32_t *orv)
+{
+    const uint32_t np = (d.len + 15) >> 4;               // data pieces
+    const uint32_t z = r_win * 64 - np;                  // leading zero pieces
+    const uint32_t r0 = max(r_begin, z >> 6);            // earlier rounds are all zero
+    uint32_t acc = 0, o = 0;
+    for (uint32_t r = r0; r < r_end; r++) {
+        const int p = (int)(r * 64 + lane) - (int)z;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (p >= 0) {
+            const uint32_t start = (uint32_t)p * 16;
+            v = load_piece<MODE>(d, start);
+            store_piece<MODE>(d, start, v);
+        }
+        o |= v.x | v.y | v.z | v.w;
+        if (p == 0)
+            v.x ^= init_mask(d.len);
+        if (r > r0)
+            acc = apply_op(tabs + kTabGap, acc);
+        acc = apply_op(tabs + kTabChain, acc ^ v.x);
+        acc = apply_op(tabs + kTabChain, acc ^ v.y);
+        acc = apply_op(tabs + kTabChain, acc ^ v.z);
+        acc = apply_op(tabs + kTabChain, acc ^ v.w);
+    }
+#pragma unroll
+    for (int k = 0; k < kTreeLevels; k++) {
+        const uint32_t right = __shfl_down(acc, 1 << k, 64);
+        acc = apply_op(tabs + kTabTree + k * kTabWords, acc) ^ right;
+    }
+    *orv = o;
+    return acc;
+}
+
+template <int MODE>
+__device__ __forceinline__ void finish_chunk(const ChunkArgs &a, const Desc &d, uint32_t raw, bool nonzero)
+{
+    const uint32_t crc = finish_crc(raw, d.len);
+    if (MODE == kModeRestore) {
+        if (crc != a.want_crc[d.g]) {
+            a.bad[d.g] = 1;
+            atomicAdd(&a.plan_rw->bad_count, 1ull);
+        }
+    } else {
+        uint8_t f = nonzero ? 0 : kFlagZero;
+        if (a.base_crc == nullptr || a.base_crc[d.g] != crc)
+            f |= kFlagDirty;
+        a.crc[d.g] = crc;
+        a.flags[d.g] = f;
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
+{
+    __shared__ uint32_t tabs[kTabTotalWords];
+    __shared__ Desc desc[kTile];
+    __shared__ uint32_t s_part[16];
+    __shared__ uint32_t s_nz[16];
+
+    for (int i = threadIdx.x; i < kTabTotalWords; i += blockDim.x)
+        tabs[i] = a.tables[i];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int W = a.waves_per_chunk;
+    const int groups = nwaves / W, group = wave / W, wig = wave % W;
+    const uint32_t C = a.C;
+    const uint32_t r_full = (C + kRoundBytes - 1) / kRoundBytes;
+    const uint32_t rw = (r_full + W - 1) / W;            // rounds per wave
+    const uint32_t r_win = rw * W;
+    const uint64_t M = (MODE == kModeRestore) ? a.plan->n_items : a.plan->n_chunks;
+
+    for (uint64_t g0 = (uint64_t)blockIdx.x * kTile; g0 < M; g0 += (uint64_t)gridDim.x * kTile) {
+        __syncthreads();   // tables loaded / previous tile's descriptors consumed
+        for (int t = threadIdx.x; t < kTile; t += blockDim.x) {
+            const uint64_t i = g0 + t;
+            if (i < M) {
+                const uint64_t g = (MODE == kModeRestore && a.ids) ? a.ids[i] : i;
+                const uint32_t k = a.map[g];
+                const uint64_t start = (g - a.cb[k]) * C;
+                const uint64_t rest = a.size[k] - start;
+                Desc d;
+                d.g = g;
+                d.len = (uint32_t)(rest < C ? rest : C);
+                if (MODE == kModeRestore) {
+                    d.zero = a.want_flags[g] & kFlagZero;
+                    d.src = d.zero ? 0 : (uint64_t)(a.staging + a.soff[i]);
+                    d.dst = a.dst[k] + start;
+                } else {
+                    d.zero = 0;
+                    d.src = a.src[k] + start;
+                    d.dst = (MODE == kModePack) ? (uint64_t)(a.dense + a.off[k] + start) : 0;
+                }
+                desc[t] = d;
+            }
+        }
+        __syncthreads();
+        for (int slot = 0; slot < kTile; slot += groups) {
+            const int t = slot + group;
+            const bool valid = t < kTile && g0 + t < M;
+            uint32_t raw = 0, orv = 0;
+            Desc d;
+            if (valid) {
+                d = desc[t];
+                raw = wave_rounds<MODE>(tabs, d, lane, wig * rw, (wig + 1) * rw, r_win, &orv);
+            }
+            const bool nonzero = __ballot(orv != 0) != 0;
+            if (W == 1) {
+                if (valid && lane == 0)
+                    finish_chunk<MODE>(a, d, raw, nonzero);
+            } else {
+                if (lane == 0) {
+                    s_part[wave] = raw;
+                    s_nz[wave] = nonzero;
+                }
+                __syncthreads();
+                if (valid && wig == 0 && lane == 0) {
+                    uint32_t acc = s_part[wave];
+                    bool nz = s_nz[wave];
+                    for (int w = 1; w < W; w++) {
+                        acc = apply_op(tabs + kTabSeg, acc) ^ s_part[wave + w];
+                        nz = nz || s_nz[wave + w];
+                    }
+                    finish_chunk<MODE>(a, d, acc, nz);
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------ K5: selection scan
+//
+// Reduce-then-scan over items in tiles of kSelTile: each thread owns
+// kSelPerThread consecutive items.  Per item: `bytes` (roundup16 of the
+// chunk's length when the chunk is selected) and `count` (1 when its id goes
+// to the id list).  soff[i] gets the exclusive prefix of bytes; ids_out gets
+// the counted ids in ascending order.
+
+__device__ __forceinline__ uint64_t sel_items(const SelArgs &a)
+{
+    return a.mode == kSelIdsNonZero ? a.plan->n_items : a.plan->n_chunks;
+}
+
+__device__ __forceinline__ void sel_item(const SelArgs &a, uint64_t i, uint64_t *bytes, uint32_t *count,
+                                         uint64_t *gout)
+{
+    const uint64_t g = a.mode == kSelIdsNonZero ? a.ids[i] : i;
+    const uint8_t f = a.flags[g];
+    bool take_bytes = false;
+    uint32_t c = 0;
+    switch (a.mode) {
+    case kSelNonZero:
+    case kSelIdsNonZero:
+        take_bytes = !(f & kFlagZero);
+        break;
+    case kSelDirtyNonZero:
+        take_bytes = (f & kFlagDirty) && !(f & kFlagZero);
+        c = (f & kFlagDirty) ? 1 : 0;
+        break;
+    default:   // kSelBad: flags holds the bad marks
+        c = f ? 1 : 0;
+        break;
+    }
+    uint64_t b = 0;
+    if (take_bytes) {
+        const uint32_t k = a.map[g];
+        const uint64_t rest = a.size[k] - (g - a.cb[k]) * a.C;
+        b = round_up16(rest < a.C ? rest : a.C);
+    }
+    *bytes = b;
+    *count = c;
+    *gout = g;
+}
+
+// Block-wide exclusive scan of (bytes, count) pairs; returns the block totals.
+__device__ __forceinline__ void block_excl_scan(uint64_t &b, uint64_t &c, uint64_t *tot_b, uint64_t *tot_c)
+{
+    __shared__ uint64_t sb[16], sc[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint64_t ib = wave_incl_scan(b, lane), ic = wave_incl_scan(c, lane);
+    if (lane == 63) {
+        sb[wave] = ib;
+        sc[wave] = ic;
+    }
+    __syncthreads();
+    uint64_t pb = 0, pc = 0, tb = 0, tc = 0;
+    for (int w = 0; w < nw; w++) {
+        if (w < wave) {
+            pb += sb[w];
+            pc += sc[w];
+        }
+        tb += sb[w];
+        tc += sc[w];
+    }
+    __syncthreads();
+    b = pb + ib - b;
+    c = pc + ic - c;
+    *tot_b = tb;
+    *tot_c = tc;
+}
+
+__global__ __launch_bounds__(kSelThreads) void k_sel_reduce(SelArgs a)
+{
+    const uint64_t M = sel_items(a);
+    const uint64_t base = (uint64_t)blockIdx.x * kSelTile + (uint64_t)threadIdx.x * kSelPerThread;
+    uint64_t b = 0, c = 0;
+    if ((uint64_t)blockIdx.x * kSelTile < M) {
+        for (int j = 0; j < kSelPerThread; j++) {
+            const uint64_t i = base + j;
+            if (i < M) {
+                uint64_t ib, g;
+                uint32_t ic;
+                sel_item(a, i, &ib, &ic, &g);
+                b += ib;
+                c += ic;
+            }
+        }
+    }
+    uint64_t tb, tc;
+    block_excl_scan(b, c, &tb, &tc);
+    if (threadIdx.x == 0) {
+        a.tile_bytes[blockIdx.x] = tb;
+        a.tile_count[blockIdx.x] = tc;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_sel_scan(SelArgs a)
+{
+    const uint64_t M = sel_items(a);
+    const uint64_t tiles = (M + kSelTile - 1) / kSelTile;
+    uint64_t carry_b = 0, carry_c = 0;
+    for (uint64_t base = 0; base < tiles; base += 1024) {
+        const uint64_t t = base + threadIdx.x;
+        uint64_t b = t < tiles ? a.tile_bytes[t] : 0, c = t < tiles ? a.tile_count[t] : 0;
+        uint64_t tb, tc;
+        block_excl_scan(b, c, &tb, &tc);
+        if (t < tiles) {
+            a.tile_bytes[t] = carry_b + b;
+            a.tile_count[t] = carry_c + c;
+        }
+        carry_b += tb;
+        carry_c += tc;
+    }
+    if (threadIdx.x == 0) {
+        a.plan->sel_bytes = carry_b;
+        a.plan->sel_count = carry_c;
+    }
+}
+
+__global__ __launch_bounds__(kSelThreads) void k_sel_down(SelArgs a)
+{
+    const uint64_t M = sel_items(a);
+    if ((uint64_t)blockIdx.x * kSelTile >= M)
+        return;
+    const uint64_t base = (uint64_t)blockIdx.x * kSelTile + (uint64_t)threadIdx.x * kSelPerThread;
+    uint64_t ib[kSelPerThread], ig[kSelPerThread];
+    uint32_t ic[kSelPerThread];
+    uint64_t b = 0, c = 0;
+    for (int j = 0; j < kSelPerThread; j++) {
+        const uint64_t i = base + j;
+        ib[j] = 0;
+        ic[j] = 0;
+        ig[j] = 0;
+        if (i < M)
+            sel_item(a, i, &ib[j], &ic[j], &ig[j]);
+        b += ib[j];
+        c += ic[j];
+    }
+    uint64_t tb, tc;
+    block_excl_scan(b, c, &tb, &tc);
+    b += a.tile_bytes[blockIdx.x];
+    c += a.tile_count[blockIdx.x];
+    for (int j = 0; j < kSelPerThread; j++) {
+        const uint64_t i = base + j;
+        if (i < M) {
+            if (a.soff)
+                a.soff[i] = b;
+            if (ic[j] && a.ids_out && c < a.ids_cap)
+                a.ids_out[c] = ig[j];
+        }
+        b += ib[j];
+        c += ic[j];
+    }
+}
+
+// --------------------------------------------------------------- K6: gather
+//
+// Copies each selected chunk (roundup16(len) bytes) to out + soff[g], from the
+// dense image or straight from the allocation (zero pad written, never read).
+
+__global__ __launch_bounds__(256) void k_gather(GatherArgs a)
+{
+    const uint64_t N = a.plan->n_chunks;
+    const int lane = threadIdx.x & 63;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t g = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g < N; g += waves) {
+        const uint8_t f = a.flags[g];
+        const bool take = a.mode == kSelNonZero ? !(f & kFlagZero) : ((f & kFlagDirty) && !(f & kFlagZero));
+        if (!take)
+            continue;
+        const uint32_t k = a.map[g];
+        const uint64_t start = (g - a.cb[k]) * a.C;
+        const uint64_t rest = a.size[k] - start;
+        const uint32_t len = (uint32_t)(rest < a.C ? rest : a.C);
+        const uint32_t np = (len + 15) >> 4;
+        uint8_t *out = a.out + a.soff[g];
+        if (a.from_dense) {
+            const uint8_t *in = a.dense + a.off[k] + start;
+            for (uint32_t p = lane; p < np; p += 64)
+                *(uint4 *)(out + 16 * p) = *(const uint4 *)(in + 16 * p);
+        } else {
+            const uint8_t *in = (const uint8_t *)a.src[k] + start;
+            for (uint32_t p = lane; p < np; p += 64) {
+                const uint32_t s = 16 * p;
+                *(uint4 *)(out + s) = s + 16 <= len ? *(const uint4 *)(in + s) : load_partial(in + s, len - s);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ helpers
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_pick_u64(const uint64_t *src, const uint64_t *idx, uint64_t *out, uint32_t m)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m)
+        out[i] = src[idx[i]];
+}
+
+// ----------------------------------------------------------- launch wrappers
+
+hipError_t launch_layout_scan(hipStream_t s, DevPlan *plan, const uint64_t *size, uint32_t C, uint64_t *off,
+                              uint64_t *cb)
+{
+    hipLaunchKernelGGL(k_layout_scan, dim3(1), dim3(1024), 0, s, plan, size, C, off, cb);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_map(hipStream_t s, const DevPlan *plan, const uint64_t *cb, uint32_t *map, int grid)
+{
+    hipLaunchKernelGGL(k_chunk_map, dim3(grid), dim3(256), 0, s, plan, cb, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunks(hipStream_t s, int mode, const ChunkArgs &a, int grid, int block)
+{
+    switch (mode) {
+    case kModePack:
+        hipLaunchKernelGGL(k_chunks<kModePack>, dim3(grid), dim3(block), 0, s, a);
+        break;
+    case kModeHash:
+        hipLaunchKernelGGL(k_chunks<kModeHash>, dim3(grid), dim3(block), 0, s, a);
+        break;
+    default:
+        hipLaunchKernelGGL(k_chunks<kModeRestore>, dim3(grid), dim3(block), 0, s, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_select(hipStream_t s, const SelArgs &a, uint64_t max_items)
+{
+    const uint64_t tiles = (max_items + kSelTile - 1) / kSelTile;
+    const unsigned grid = (unsigned)(tiles ? tiles : 1);
+    hipLaunchKernelGGL(k_sel_reduce, dim3(grid), dim3(kSelThreads), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(1024), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_sel_down, dim3(grid), dim3(kSelThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(hipStream_t s, const GatherArgs &a, int grid)
+{
+    hipLaunchKernelGGL(k_gather, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t n_words, uint64_t value)
+{
+    if (n_words == 0)
+        return hipSuccess;
+    uint64_t blocks = (n_words + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, n_words, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_pick_u64(hipStream_t s, const uint64_t *src, const uint64_t *idx, uint64_t *out, uint32_t m)
+{
+    if (m == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_pick_u64, dim3((m + 255) / 256), dim3(256), 0, s, src, idx, out, m);
+    return hipGetLastError();
+}
+
+}  // namespace ckpt

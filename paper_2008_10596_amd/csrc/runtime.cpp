@@ -1,0 +1,1212 @@
+// runtime.cpp -- host runtime of libckpt behind the C ABI in include/ckpt.h.
+//
+// Registration table (the log of live allocations), device staging, pinned
+// host buffers, the checkpoint path (pack on the caller's stream, drain on a
+// side stream), restore with verification, image (de)serialization and the
+// batched form.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ckpt.h"
+#include "ckpt_runtime.h"
+
+using namespace ckpt;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local int t_last_hip = 0;
+static thread_local char t_last_msg[512];
+
+int ckpt::set_error(int status, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(t_last_msg, sizeof(t_last_msg), fmt, ap);
+    va_end(ap);
+    return status;
+}
+
+int ckpt::hip_fail(hipError_t e, const char *what, int line)
+{
+    t_last_hip = (int)e;
+    set_error(0, "%s failed: %s (runtime.cpp:%d)", what, hipGetErrorString(e), line);
+    return e == hipErrorOutOfMemory ? CKPT_E_NOMEM : CKPT_E_HIP;
+}
+
+extern "C" int ckpt_last_hip_error(void) { return t_last_hip; }
+extern "C" const char *ckpt_last_error(void) { return t_last_msg; }
+
+extern "C" const char *ckpt_strerror(int status)
+{
+    switch (status) {
+    case CKPT_OK: return "ok";
+    case CKPT_E_INVAL: return "invalid argument";
+    case CKPT_E_NOTFOUND: return "not found";
+    case CKPT_E_NOMEM: return "out of memory";
+    case CKPT_E_HIP: return "HIP runtime error";
+    case CKPT_E_MISMATCH: return "image, base or destination mismatch";
+    case CKPT_E_CORRUPT: return "checksum mismatch";
+    case CKPT_E_AGAIN: return "not finished";
+    case CKPT_E_BUDGET: return "staging budget exceeded";
+    default: return "unknown status";
+    }
+}
+
+// ---------------------------------------------------------- device buffers
+
+int DevBuf::ensure(size_t bytes)
+{
+    if (bytes <= cap)
+        return CKPT_OK;
+    release();
+    size_t want = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return hip_fail(e, "hipMalloc", __LINE__);
+    }
+    cap = want;
+    return CKPT_OK;
+}
+
+void DevBuf::release()
+{
+    if (p)
+        (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+}
+
+// ----------------------------------------------------- pinned host memory
+//
+// hipHostMalloc of gigabytes is slow (it pins every page), so freed pinned
+// buffers are kept for reuse, up to a cap, and handed out best-fit.
+
+namespace {
+class PinnedPool {
+public:
+    void *get(size_t bytes, size_t *cap_out)
+    {
+        if (bytes == 0)
+            bytes = 1;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            auto it = free_.lower_bound(bytes);
+            if (it != free_.end() && it->first <= 2 * bytes + (64u << 20)) {
+                void *p = it->second;
+                *cap_out = it->first;
+                cached_ -= it->first;
+                free_.erase(it);
+                return p;
+            }
+        }
+        const size_t rounded = (bytes + (2u << 20) - 1) & ~size_t((2u << 20) - 1);
+        void *p = nullptr;
+        if (hipHostMalloc(&p, rounded, hipHostMallocDefault) != hipSuccess) {
+            trim(0);   // give cached buffers back and retry once
+            if (hipHostMalloc(&p, rounded, hipHostMallocDefault) != hipSuccess)
+                return nullptr;
+        }
+        *cap_out = rounded;
+        return p;
+    }
+    void put(void *p, size_t cap)
+    {
+        if (!p)
+            return;
+        std::lock_guard<std::mutex> lk(mu_);
+        free_.emplace(cap, p);
+        cached_ += cap;
+        trim_locked(kMaxCached);
+    }
+    void trim(size_t keep)
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        trim_locked(keep);
+    }
+
+private:
+    void trim_locked(size_t keep)
+    {
+        while (cached_ > keep && !free_.empty()) {
+            auto it = std::prev(free_.end());   // largest first
+            (void)hipHostFree(it->second);
+            cached_ -= it->first;
+            free_.erase(it);
+        }
+    }
+    static constexpr size_t kMaxCached = size_t(96) << 30;
+    std::mutex mu_;
+    std::multimap<size_t, void *> free_;
+    size_t cached_ = 0;
+};
+
+PinnedPool &pinned_pool()
+{
+    static PinnedPool *pool = new PinnedPool();   // never destroyed: buffers may outlive statics
+    return *pool;
+}
+
+std::atomic<uint64_t> g_serial{0};
+
+uint64_t next_serial()
+{
+    static const uint64_t base = [] {
+        const uint64_t t = (uint64_t)std::chrono::steady_clock::now().time_since_epoch().count();
+        return (t * 0x9E3779B97F4A7C15ull) & 0xFFFFFFFF00000000ull;
+    }();
+    return base | (++g_serial & 0xFFFFFFFFull);
+}
+
+uint64_t fnv1a64(const void *p, size_t n)
+{
+    const uint8_t *b = (const uint8_t *)p;
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (size_t i = 0; i < n; i++) {
+        h ^= b[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+uint64_t ru16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
+}  // namespace
+
+int PinnedBuf::ensure(size_t bytes)
+{
+    if (bytes <= cap && p)
+        return CKPT_OK;
+    release();
+    p = pinned_pool().get(bytes, &cap);
+    if (!p) {
+        cap = 0;
+        return set_error(CKPT_E_NOMEM, "pinned host allocation of %zu bytes failed", bytes);
+    }
+    return CKPT_OK;
+}
+
+void PinnedBuf::release()
+{
+    if (p)
+        pinned_pool().put(p, cap);
+    p = nullptr;
+    cap = 0;
+}
+
+// -------------------------------------------------------------- the image
+
+ckpt_image::~ckpt_image()
+{
+    if (dense_owned && dense) {
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(device);
+        (void)hipFree(dense);
+        (void)hipSetDevice(prev);
+    }
+}
+
+// ------------------------------------------------------------- device guard
+
+DeviceGuard::DeviceGuard(int dev)
+{
+    (void)hipGetDevice(&prev_);
+    ok_ = hipSetDevice(dev) == hipSuccess;
+}
+DeviceGuard::~DeviceGuard() { (void)hipSetDevice(prev_); }
+
+// ------------------------------------------------------------------ context
+
+extern "C" int ckpt_init(const ckpt_config *cfg_in, ckpt_ctx **out)
+{
+    if (!out)
+        return set_error(CKPT_E_INVAL, "out is NULL");
+    ckpt_config cfg;
+    memset(&cfg, 0, sizeof(cfg));
+    if (cfg_in)
+        cfg = *cfg_in;
+    if (cfg.chunk_bytes == 0)
+        cfg.chunk_bytes = 4096;
+    if (cfg.chunk_bytes % 16 != 0 || cfg.chunk_bytes > (1u << 30))
+        return set_error(CKPT_E_INVAL, "chunk_bytes %u: not a multiple of 16 in [16, 2^30]", cfg.chunk_bytes);
+    if (cfg.block_threads == 0)
+        cfg.block_threads = 256;
+    if (cfg.block_threads != 64 && cfg.block_threads != 128 && cfg.block_threads != 256 &&
+        cfg.block_threads != 512 && cfg.block_threads != 1024)
+        return set_error(CKPT_E_INVAL, "block_threads %u", cfg.block_threads);
+    if (cfg.waves_per_chunk == 0)
+        cfg.waves_per_chunk = 1;
+    const uint32_t w = cfg.waves_per_chunk;
+    if ((w & (w - 1)) != 0 || w > 16 || w > cfg.block_threads / 64)
+        return set_error(CKPT_E_INVAL, "waves_per_chunk %u with block_threads %u", w, cfg.block_threads);
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDeviceCount", __LINE__);
+    if (cfg.device < 0 || cfg.device >= ndev)
+        return set_error(CKPT_E_INVAL, "device %d of %d", cfg.device, ndev);
+
+    DeviceGuard g(cfg.device);
+    auto *ctx = new ckpt_ctx();
+    ctx->cfg = cfg;
+    int rc = ctx_setup(ctx);
+    if (rc != CKPT_OK) {
+        ckpt_destroy(ctx);
+        return rc;
+    }
+    *out = ctx;
+    return CKPT_OK;
+}
+
+int ckpt::ctx_setup(ckpt_ctx *ctx)
+{
+    const ckpt_config &cfg = ctx->cfg;
+    HIP_TRY(hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, cfg.device));
+    int managed = 0;
+    if (hipDeviceGetAttribute(&managed, hipDeviceAttributeConcurrentManagedAccess, cfg.device) == hipSuccess)
+        ctx->managed_prefetch = managed != 0;
+    HIP_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    for (auto &ev : ctx->ev)
+        HIP_TRY(hipEventCreate(&ev));
+    const uint32_t r_full = (cfg.chunk_bytes + kRoundBytes - 1) / kRoundBytes;
+    const uint32_t rw = (r_full + cfg.waves_per_chunk - 1) / cfg.waves_per_chunk;
+    std::vector<uint32_t> tabs(kTabTotalWords);
+    build_tables(tabs.data(), rw);
+    CKPT_TRY(ctx->d_tables.ensure(tabs.size() * 4));
+    HIP_TRY(hipMemcpy(ctx->d_tables.p, tabs.data(), tabs.size() * 4, hipMemcpyHostToDevice));
+    CKPT_TRY(ctx->d_plan.ensure(sizeof(DevPlan)));
+    CKPT_TRY(ctx->h_plan.ensure(sizeof(DevPlan)));
+    const int per_cu = cfg.wgs_per_cu ? (int)cfg.wgs_per_cu
+                                      : std::max(1, std::min(4, 32 / (int)(cfg.block_threads / 64)));
+    ctx->grid_chunks = ctx->cu_count * per_cu;
+    ctx->grid_small = ctx->cu_count * 4;
+    return CKPT_OK;
+}
+
+extern "C" void ckpt_destroy(ckpt_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    {
+        DeviceGuard g(ctx->cfg.device);
+        if (ctx->side) {
+            (void)hipStreamSynchronize(ctx->side);
+            (void)hipStreamDestroy(ctx->side);
+        }
+        for (auto &ev : ctx->ev)
+            if (ev)
+                (void)hipEventDestroy(ev);
+        for (DevBuf *b : ctx->all_dev())
+            b->release();
+        ctx->h_up.release();
+        ctx->h_plan.release();
+    }
+    delete ctx;
+}
+
+// ------------------------------------------------------------ registration
+
+extern "C" int ckpt_register(ckpt_ctx *ctx, void *ptr, size_t bytes, int kind, ckpt_id *out)
+{
+    if (!ctx || !out)
+        return set_error(CKPT_E_INVAL, "ctx or out is NULL");
+    if (kind != CKPT_DEVICE && kind != CKPT_MANAGED)
+        return set_error(CKPT_E_INVAL, "unknown kind %d", kind);
+    const uint64_t start = (uint64_t)(uintptr_t)ptr;
+    if (start % 16 != 0)
+        return set_error(CKPT_E_INVAL, "pointer %p is not 16-byte aligned", ptr);
+    if (start == 0 && bytes != 0)
+        return set_error(CKPT_E_INVAL, "NULL pointer with %zu bytes", bytes);
+    if (start + bytes < start)
+        return set_error(CKPT_E_INVAL, "range wraps the address space");
+    // Overlap: a live range [s, e) with s < start + bytes and start < e, or the
+    // same start (starts identify registrations).
+    auto it = ctx->ranges.lower_bound(start);
+    if (it != ctx->ranges.end() && (it->first == start || it->first < start + bytes))
+        return set_error(CKPT_E_INVAL, "[%p, +%zu) overlaps a live registration", ptr, bytes);
+    if (it != ctx->ranges.begin()) {
+        auto pv = std::prev(it);
+        if (start < pv->second.end)
+            return set_error(CKPT_E_INVAL, "[%p, +%zu) overlaps a live registration", ptr, bytes);
+    }
+    Reg r;
+    r.id = ctx->next_id++;
+    r.kind = (uint32_t)kind;
+    r.ptr = start;
+    r.size = bytes;
+    ctx->live.push_back(r);
+    ctx->ranges.emplace(start, RangeEnd{start + bytes, r.id});
+    *out = r.id;
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_unregister(ckpt_ctx *ctx, void *ptr)
+{
+    if (!ctx)
+        return set_error(CKPT_E_INVAL, "ctx is NULL");
+    auto it = ctx->ranges.find((uint64_t)(uintptr_t)ptr);
+    if (it == ctx->ranges.end())
+        return set_error(CKPT_E_NOTFOUND, "%p is not a live registration", ptr);
+    const uint64_t id = it->second.id;
+    ctx->ranges.erase(it);
+    // live is in id order; ids are unique, so a binary search finds the row
+    auto row = std::lower_bound(ctx->live.begin(), ctx->live.end(), id,
+                                [](const Reg &a, uint64_t v) { return a.id < v; });
+    if (row != ctx->live.end() && row->id == id)
+        ctx->live.erase(row);
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_live_count(const ckpt_ctx *ctx, size_t *out)
+{
+    if (!ctx || !out)
+        return set_error(CKPT_E_INVAL, "ctx or out is NULL");
+    *out = ctx->live.size();
+    return CKPT_OK;
+}
+
+// -------------------------------------------------------------- timing
+
+namespace {
+float ev_ms(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess)
+        return 0.f;
+    return ms;
+}
+}  // namespace
+
+extern "C" int ckpt_last_timing(const ckpt_ctx *ctx, ckpt_timing *out)
+{
+    if (!ctx || !out)
+        return set_error(CKPT_E_INVAL, "ctx or out is NULL");
+    *out = ctx->timing;
+    return CKPT_OK;
+}
+
+// ---------------------------------------------------------- shared helpers
+
+// Uploads the allocation table (addresses, sizes) and a fresh plan header to
+// the device on stream s, then runs the size scan and the chunk map.
+int ckpt::upload_table(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, bool dst_side,
+                       uint64_t N_host, uint64_t n_items)
+{
+    const uint64_t n = rows.size();
+    CKPT_TRY(ctx->d_addr.ensure(std::max<uint64_t>(n, 1) * 8));
+    CKPT_TRY(ctx->d_size.ensure(std::max<uint64_t>(n, 1) * 8));
+    CKPT_TRY(ctx->d_off.ensure((n + 1) * 8));
+    CKPT_TRY(ctx->d_cb.ensure((n + 1) * 8));
+    CKPT_TRY(ctx->d_map.ensure(std::max<uint64_t>(N_host, 1) * 4));
+    const size_t up_bytes = sizeof(DevPlan) + 16 * n;
+    CKPT_TRY(ctx->h_up.ensure(up_bytes));
+    auto *plan = (DevPlan *)ctx->h_up.p;
+    memset(plan, 0, sizeof(DevPlan));
+    plan->n_allocs = n;
+    plan->n_items = n_items;
+    auto *addr = (uint64_t *)((uint8_t *)ctx->h_up.p + sizeof(DevPlan));
+    auto *size = addr + n;
+    for (uint64_t k = 0; k < n; k++) {
+        addr[k] = rows[k].ptr;
+        size[k] = rows[k].size;
+    }
+    (void)dst_side;
+    HIP_TRY(hipMemcpyAsync(ctx->d_plan.p, plan, sizeof(DevPlan), hipMemcpyHostToDevice, s));
+    if (n) {
+        HIP_TRY(hipMemcpyAsync(ctx->d_addr.p, addr, 8 * n, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ctx->d_size.p, size, 8 * n, hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(launch_layout_scan(s, (DevPlan *)ctx->d_plan.p, (const uint64_t *)ctx->d_size.p, ctx->cfg.chunk_bytes,
+                               (uint64_t *)ctx->d_off.p, (uint64_t *)ctx->d_cb.p));
+    if (N_host)
+        HIP_TRY(launch_chunk_map(s, (const DevPlan *)ctx->d_plan.p, (const uint64_t *)ctx->d_cb.p,
+                                 (uint32_t *)ctx->d_map.p, ctx->grid_small));
+    // the host waits on this copy before it next rewrites h_up
+    return CKPT_OK;
+}
+
+int ckpt::read_plan(ckpt_ctx *ctx, hipStream_t s, DevPlan *out)
+{
+    HIP_TRY(hipMemcpyAsync(ctx->h_plan.p, ctx->d_plan.p, sizeof(DevPlan), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    memcpy(out, ctx->h_plan.p, sizeof(DevPlan));
+    return CKPT_OK;
+}
+
+int ckpt::run_select(ckpt_ctx *ctx, hipStream_t s, int mode, const uint8_t *flags, const uint64_t *ids,
+                     uint64_t max_items, uint64_t *soff, uint64_t *ids_out, uint64_t ids_cap)
+{
+    const uint64_t tiles = (max_items + kSelTile - 1) / kSelTile;
+    CKPT_TRY(ctx->d_tile_b.ensure(std::max<uint64_t>(tiles, 1) * 8));
+    CKPT_TRY(ctx->d_tile_c.ensure(std::max<uint64_t>(tiles, 1) * 8));
+    SelArgs a;
+    memset(&a, 0, sizeof(a));
+    a.plan = (DevPlan *)ctx->d_plan.p;
+    a.mode = mode;
+    a.C = ctx->cfg.chunk_bytes;
+    a.size = (const uint64_t *)ctx->d_size.p;
+    a.cb = (const uint64_t *)ctx->d_cb.p;
+    a.map = (const uint32_t *)ctx->d_map.p;
+    a.flags = flags;
+    a.ids = ids;
+    a.tile_bytes = (uint64_t *)ctx->d_tile_b.p;
+    a.tile_count = (uint64_t *)ctx->d_tile_c.p;
+    a.soff = soff;
+    a.ids_out = ids_out;
+    a.ids_cap = ids_cap;
+    HIP_TRY(launch_select(s, a, max_items));
+    return CKPT_OK;
+}
+
+ChunkArgs ckpt::chunk_args(ckpt_ctx *ctx)
+{
+    ChunkArgs a;
+    memset(&a, 0, sizeof(a));
+    a.plan = (const DevPlan *)ctx->d_plan.p;
+    a.plan_rw = (DevPlan *)ctx->d_plan.p;
+    a.tables = (const uint32_t *)ctx->d_tables.p;
+    a.C = ctx->cfg.chunk_bytes;
+    a.waves_per_chunk = ctx->cfg.waves_per_chunk;
+    a.size = (const uint64_t *)ctx->d_size.p;
+    a.off = (const uint64_t *)ctx->d_off.p;
+    a.cb = (const uint64_t *)ctx->d_cb.p;
+    a.map = (const uint32_t *)ctx->d_map.p;
+    return a;
+}
+
+namespace {
+
+struct Layout {
+    std::vector<uint64_t> off, cb;   // n + 1 each
+    uint64_t data_bytes = 0, N = 0;
+};
+
+Layout host_layout(const std::vector<Row> &rows, uint32_t C)
+{
+    Layout L;
+    L.off.resize(rows.size() + 1);
+    L.cb.resize(rows.size() + 1);
+    uint64_t o = 0, g = 0;
+    for (size_t k = 0; k < rows.size(); k++) {
+        L.off[k] = o;
+        L.cb[k] = g;
+        o += ru16(rows[k].size);
+        g += (rows[k].size + C - 1) / C;
+    }
+    L.off[rows.size()] = o;
+    L.cb[rows.size()] = g;
+    L.data_bytes = o;
+    L.N = g;
+    return L;
+}
+
+bool same_table(const ckpt_image *a, const std::vector<Row> &rows, uint32_t C)
+{
+    if (a->C != C || a->allocs.size() != rows.size())
+        return false;
+    for (size_t k = 0; k < rows.size(); k++)
+        if (a->allocs[k].id != rows[k].id || a->allocs[k].kind != rows[k].kind || a->allocs[k].size != rows[k].size)
+            return false;
+    return true;
+}
+
+bool same_table(const ckpt_image *a, const ckpt_image *b)
+{
+    if (a->C != b->C || a->allocs.size() != b->allocs.size())
+        return false;
+    for (size_t k = 0; k < a->allocs.size(); k++)
+        if (a->allocs[k].id != b->allocs[k].id || a->allocs[k].kind != b->allocs[k].kind ||
+            a->allocs[k].size != b->allocs[k].size)
+            return false;
+    return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- checkpoint
+//
+// rows: the table to drain, possibly the concatenation of several contexts'
+// tables (batched form); parts[i] = first row of output i (parts.size() =
+// number of outputs).  Each output's image is the one its rows alone give.
+
+int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_image *base, const std::vector<Row> &rows,
+                         const std::vector<size_t> &parts, std::vector<ckpt_image *> &outs)
+{
+    const ckpt_config &cfg = ctx->cfg;
+    const uint32_t C = cfg.chunk_bytes;
+    const bool timing = cfg.flags & CKPT_TIMING;
+    const bool no_drain = cfg.flags & CKPT_NO_DRAIN;
+    const bool keep_dense = cfg.flags & CKPT_KEEP_DENSE;
+    const bool direct = cfg.flags & CKPT_DRAIN_DIRECT;
+    const bool incremental = mode == CKPT_INCREMENTAL;
+    const Layout L = host_layout(rows, C);
+    const uint64_t n = rows.size(), N = L.N;
+    ckpt_timing &T = ctx->timing;
+    memset(&T, 0, sizeof(T));
+    const auto t_call = std::chrono::steady_clock::now();
+
+    if (base && !same_table(base, rows, C))
+        return set_error(CKPT_E_MISMATCH, "base image has another allocation table or chunk size");
+    if (!incremental && cfg.staging_budget && L.data_bytes > cfg.staging_budget)
+        return set_error(CKPT_E_BUDGET, "dense image %llu B exceeds the staging budget %llu B",
+                         (unsigned long long)L.data_bytes, (unsigned long long)cfg.staging_budget);
+
+    // Drain pending device work first (CheCUDA's step (a)), unless the caller
+    // asked for stream order only.
+    if (!(cfg.flags & CKPT_STREAM_ORDERED)) {
+        const auto t0 = std::chrono::steady_clock::now();
+        HIP_TRY(hipDeviceSynchronize());
+        T.order_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (ctx->managed_prefetch)
+        for (const Row &r : rows)
+            if (r.kind == CKPT_MANAGED && r.size)
+                HIP_TRY(hipMemPrefetchAsync((const void *)r.ptr, r.size, cfg.device, s));
+
+    if (timing)
+        HIP_TRY(hipEventRecord(ctx->ev[0], s));
+    CKPT_TRY(upload_table(ctx, s, rows, false, N, 0));
+    CKPT_TRY(ctx->d_crc.ensure(std::max<uint64_t>(N, 1) * 4));
+    CKPT_TRY(ctx->d_flags.ensure(std::max<uint64_t>(N, 1)));
+
+    // DIRTY is judged against the base's CRC array; the context keeps the last
+    // image's array on the device, so a chain of increments uploads nothing.
+    const uint32_t *d_base = nullptr;
+    if (base) {
+        if (base->serial == ctx->prev_serial && ctx->d_prev_crc.cap >= N * 4) {
+            d_base = (const uint32_t *)ctx->d_prev_crc.p;
+        } else {
+            CKPT_TRY(ctx->d_base_crc.ensure(std::max<uint64_t>(N, 1) * 4));
+            if (N)
+                HIP_TRY(hipMemcpyAsync(ctx->d_base_crc.p, base->crc_buf.p, N * 4, hipMemcpyHostToDevice, s));
+            d_base = (const uint32_t *)ctx->d_base_crc.p;
+        }
+    }
+
+    // Dense image: the context's staging, or a buffer the image will own.
+    uint8_t *dense = nullptr;
+    void *dense_owned = nullptr;
+    if (!incremental) {
+        if (keep_dense) {
+            hipError_t e = hipMalloc(&dense_owned, std::max<uint64_t>(L.data_bytes, 16));
+            if (e != hipSuccess)
+                return hip_fail(e, "hipMalloc(dense image)", __LINE__);
+            dense = (uint8_t *)dense_owned;
+        } else {
+            int rc = ctx->d_dense.ensure(std::max<uint64_t>(L.data_bytes, 16));
+            if (rc != CKPT_OK)
+                return rc;
+            dense = (uint8_t *)ctx->d_dense.p;
+        }
+    }
+    struct DenseGuard {
+        void *p;
+        ~DenseGuard() { if (p) (void)hipFree(p); }
+    } dense_guard{dense_owned};
+
+    if (timing)
+        HIP_TRY(hipEventRecord(ctx->ev[1], s));
+    ChunkArgs a = chunk_args(ctx);
+    a.src = (const uint64_t *)ctx->d_addr.p;
+    a.dense = dense;
+    a.crc = (uint32_t *)ctx->d_crc.p;
+    a.flags = (uint8_t *)ctx->d_flags.p;
+    a.base_crc = d_base;
+    if (N)
+        HIP_TRY(launch_chunks(s, incremental ? kModeHash : kModePack, a, ctx->grid_chunks, cfg.block_threads));
+    if (timing)
+        HIP_TRY(hipEventRecord(ctx->ev[2], s));
+    T.pack_read_bytes = 0;
+    for (const Row &r : rows)
+        T.pack_read_bytes += r.size;
+    T.pack_write_bytes = incremental ? 0 : L.data_bytes;
+    T.pack_write_bytes += 5 * N;
+
+    CKPT_TRY(ctx->d_soff.ensure(std::max<uint64_t>(N, 1) * 8));
+    CKPT_TRY(ctx->d_ids.ensure(std::max<uint64_t>(N, 1) * 8));
+    uint64_t *d_soff = (uint64_t *)ctx->d_soff.p;
+    DevPlan P;
+    uint8_t *d_out = nullptr;        // where the gather writes (device compact or pinned host)
+    std::vector<PinnedBuf> data(outs.size());
+    PinnedBuf all_data;              // one pinned buffer when there is a single output
+
+    hipStream_t ds = ctx->side;      // drain stream
+    if (incremental) {
+        // The delta is gathered from the allocations themselves, so it must be
+        // taken before `s` may run new work: hash, select and gather all on s.
+        CKPT_TRY(run_select(ctx, s, kSelDirtyNonZero, a.flags, nullptr, N, d_soff, (uint64_t *)ctx->d_ids.p, N));
+        CKPT_TRY(read_plan(ctx, s, &P));
+        ds = s;
+    } else {
+        HIP_TRY(hipEventRecord(ctx->ev[3], s));   // packed: the caller's stream is free
+        HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->ev[3], 0));
+        if (no_drain) {
+            P.sel_bytes = 0;
+            P.sel_count = 0;
+        } else {
+            CKPT_TRY(run_select(ctx, ds, kSelNonZero, a.flags, nullptr, N, d_soff, nullptr, 0));
+            CKPT_TRY(read_plan(ctx, ds, &P));
+        }
+    }
+    if (timing)
+        HIP_TRY(hipEventRecord(ctx->ev[4], ds));
+
+    // Per-output slices: rows [parts[i], parts[i+1]) -> chunks [cb_i, cb_i+1)
+    // -> serialized bytes [soff(cb_i), soff(cb_i+1)).
+    const size_t nout = outs.size();
+    std::vector<uint64_t> part_row(nout + 1), part_chunk(nout + 1), part_data(nout + 1, 0);
+    for (size_t i = 0; i < nout; i++)
+        part_row[i] = parts[i];
+    part_row[nout] = n;
+    for (size_t i = 0; i <= nout; i++)
+        part_chunk[i] = L.cb[part_row[i]];
+    const uint64_t sel_bytes = no_drain ? 0 : P.sel_bytes;
+    if (!no_drain) {
+        if (nout == 1) {
+            part_data[1] = sel_bytes;
+        } else {
+            // serialized offset of each part's first chunk: soff[cb_i] (or the total)
+            CKPT_TRY(ctx->d_pick.ensure((nout + 1) * 16));
+            std::vector<uint64_t> idx(nout + 1);
+            for (size_t i = 0; i <= nout; i++)
+                idx[i] = std::min<uint64_t>(part_chunk[i], N ? N - 1 : 0);
+            uint64_t *d_idx = (uint64_t *)ctx->d_pick.p, *d_val = d_idx + nout + 1;
+            HIP_TRY(hipMemcpyAsync(d_idx, idx.data(), idx.size() * 8, hipMemcpyHostToDevice, ds));
+            HIP_TRY(launch_pick_u64(ds, d_soff, d_idx, d_val, (uint32_t)(nout + 1)));
+            std::vector<uint64_t> val(nout + 1);
+            HIP_TRY(hipMemcpyAsync(val.data(), d_val, val.size() * 8, hipMemcpyDeviceToHost, ds));
+            HIP_TRY(hipStreamSynchronize(ds));
+            for (size_t i = 0; i <= nout; i++)
+                part_data[i] = part_chunk[i] >= N ? sel_bytes : val[i];
+        }
+    }
+
+    // Drain: gather the selected chunks, then copy them to pinned host memory.
+    if (!no_drain && sel_bytes) {
+        if (cfg.staging_budget && !direct &&
+            (incremental ? 0 : L.data_bytes) + sel_bytes > cfg.staging_budget)
+            return set_error(CKPT_E_BUDGET, "drain staging %llu B exceeds the budget",
+                             (unsigned long long)((incremental ? 0 : L.data_bytes) + sel_bytes));
+        if (direct) {
+            if (nout != 1)
+                return set_error(CKPT_E_INVAL, "CKPT_DRAIN_DIRECT is not available for batches");
+            CKPT_TRY(data[0].ensure(sel_bytes));
+            d_out = (uint8_t *)data[0].p;
+        } else {
+            CKPT_TRY(ctx->d_compact.ensure(sel_bytes));
+            d_out = (uint8_t *)ctx->d_compact.p;
+        }
+        GatherArgs ga;
+        memset(&ga, 0, sizeof(ga));
+        ga.plan = (const DevPlan *)ctx->d_plan.p;
+        ga.mode = incremental ? kSelDirtyNonZero : kSelNonZero;
+        ga.from_dense = incremental ? 0 : 1;
+        ga.C = C;
+        ga.src = (const uint64_t *)ctx->d_addr.p;
+        ga.size = (const uint64_t *)ctx->d_size.p;
+        ga.off = (const uint64_t *)ctx->d_off.p;
+        ga.cb = (const uint64_t *)ctx->d_cb.p;
+        ga.map = (const uint32_t *)ctx->d_map.p;
+        ga.dense = dense;
+        ga.flags = a.flags;
+        ga.soff = d_soff;
+        ga.out = d_out;
+        HIP_TRY(launch_gather(ds, ga, ctx->grid_small));
+        if (incremental) {
+            HIP_TRY(hipEventRecord(ctx->ev[3], s));   // delta taken: the caller's stream is free
+        }
+        if (timing)
+            HIP_TRY(hipEventRecord(ctx->ev[5], ds));
+        if (!direct)
+            for (size_t i = 0; i < nout; i++) {
+                const uint64_t b = part_data[i + 1] - part_data[i];
+                CKPT_TRY(data[i].ensure(b));
+                if (b)
+                    HIP_TRY(hipMemcpyAsync(data[i].p, d_out + part_data[i], b, hipMemcpyDeviceToHost, ds));
+            }
+    } else {
+        if (incremental)
+            HIP_TRY(hipEventRecord(ctx->ev[3], s));
+        if (timing)
+            HIP_TRY(hipEventRecord(ctx->ev[5], ds));
+    }
+
+    // Metadata: CRC, flags, dirty ids, layout.
+    std::vector<ckpt_image *> imgs(nout, nullptr);
+    struct ImgGuard {
+        std::vector<ckpt_image *> &v;
+        bool keep = false;
+        ~ImgGuard() { if (!keep) for (auto *p : v) delete p; }
+    } img_guard{imgs};
+    for (size_t i = 0; i < nout; i++) {
+        auto *img = new ckpt_image();
+        imgs[i] = img;
+        img->device = cfg.device;
+        img->mode = incremental ? CKPT_INCREMENTAL : CKPT_FULL;
+        img->C = C;
+        img->N = part_chunk[i + 1] - part_chunk[i];
+        img->data_bytes = L.off[part_row[i + 1]] - L.off[part_row[i]];
+        img->ser_bytes = part_data[i + 1] - part_data[i];
+        img->serial = next_serial();
+        img->base_serial = base ? base->serial : 0;
+        img->drained = !no_drain;
+        CKPT_TRY(img->crc_buf.ensure(std::max<uint64_t>(img->N, 1) * 4));
+        CKPT_TRY(img->flags_buf.ensure(std::max<uint64_t>(img->N, 1)));
+        if (img->N) {
+            HIP_TRY(hipMemcpyAsync(img->crc_buf.p, (uint32_t *)ctx->d_crc.p + part_chunk[i], img->N * 4,
+                                   hipMemcpyDeviceToHost, ds));
+            HIP_TRY(hipMemcpyAsync(img->flags_buf.p, (uint8_t *)ctx->d_flags.p + part_chunk[i], img->N,
+                                   hipMemcpyDeviceToHost, ds));
+        }
+        img->data = std::move(data[i]);
+        const uint64_t r0 = part_row[i], r1 = part_row[i + 1];
+        img->allocs.resize(r1 - r0);
+        for (uint64_t k = r0; k < r1; k++) {
+            ckpt_alloc_rec &rec = img->allocs[k - r0];
+            rec.id = rows[k].id;
+            rec.kind = rows[k].kind;
+            rec.pad = 0;
+            rec.size = rows[k].size;
+            rec.off = L.off[k] - L.off[r0];
+            rec.cb = L.cb[k] - L.cb[r0];
+        }
+    }
+    if (incremental) {
+        imgs[0]->n_dirty = P.sel_count;
+        CKPT_TRY(imgs[0]->ids_buf.ensure(std::max<uint64_t>(P.sel_count, 1) * 8));
+        if (P.sel_count)
+            HIP_TRY(hipMemcpyAsync(imgs[0]->ids_buf.p, ctx->d_ids.p, P.sel_count * 8, hipMemcpyDeviceToHost, ds));
+    }
+    // keep this CRC array on the device as the base of the next increment
+    if (nout == 1 && N) {
+        CKPT_TRY(ctx->d_prev_crc.ensure(N * 4));
+        HIP_TRY(hipMemcpyAsync(ctx->d_prev_crc.p, ctx->d_crc.p, N * 4, hipMemcpyDeviceToDevice, ds));
+    }
+    if (timing)
+        HIP_TRY(hipEventRecord(ctx->ev[6], ds));
+    HIP_TRY(hipStreamSynchronize(ds));
+    if (ds != s)
+        HIP_TRY(hipStreamSynchronize(s));
+    ctx->prev_serial = nout == 1 && N ? imgs[0]->serial : 0;
+
+    if (timing) {
+        T.layout_ms = ev_ms(ctx->ev[0], ctx->ev[1]);
+        T.pack_ms = ev_ms(ctx->ev[1], ctx->ev[2]);
+        T.select_ms = incremental ? ev_ms(ctx->ev[2], ctx->ev[4]) : ev_ms(ctx->ev[3], ctx->ev[4]);
+        T.gather_ms = ev_ms(ctx->ev[4], ctx->ev[5]);
+        T.d2h_ms = ev_ms(ctx->ev[5], ctx->ev[6]);
+    }
+    T.link_bytes = sel_bytes + 5 * N;
+    T.total_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t_call).count();
+
+    for (size_t i = 0; i < nout; i++) {
+        ckpt_image *img = imgs[i];
+        img->digest = fnv1a64(img->crc_buf.p, img->N * 4);
+        if (keep_dense && nout == 1) {
+            img->dense = dense_owned;
+            img->dense_owned = true;
+            dense_guard.p = nullptr;
+        } else if (no_drain && nout == 1) {
+            img->dense = dense;   // the context's staging: valid until its next checkpoint
+        }
+        outs[i] = img;
+    }
+    img_guard.keep = true;
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_checkpoint(ckpt_ctx *ctx, void *stream, int mode, const ckpt_image *base, ckpt_image **out)
+{
+    if (!ctx || !out)
+        return set_error(CKPT_E_INVAL, "ctx or out is NULL");
+    if (mode != CKPT_FULL && mode != CKPT_INCREMENTAL)
+        return set_error(CKPT_E_INVAL, "unknown mode %d", mode);
+    if (mode == CKPT_INCREMENTAL && !base)
+        return set_error(CKPT_E_INVAL, "an incremental checkpoint needs a base image");
+    DeviceGuard g(ctx->cfg.device);
+    if (!g.ok())
+        return set_error(CKPT_E_HIP, "cannot select device %d", ctx->cfg.device);
+    std::vector<Row> rows(ctx->live.begin(), ctx->live.end());
+    std::vector<size_t> parts{0};
+    std::vector<ckpt_image *> outs(1, nullptr);
+    int rc = run_checkpoint(ctx, (hipStream_t)stream, mode, base, rows, parts, outs);
+    if (rc == CKPT_OK)
+        *out = outs[0];
+    return rc;
+}
+
+extern "C" int ckpt_checkpoint_batch(ckpt_ctx *const *ctxs, size_t n, void *stream, ckpt_image **outs)
+{
+    if (!ctxs || !outs || n == 0)
+        return set_error(CKPT_E_INVAL, "empty batch");
+    ckpt_ctx *c0 = ctxs[0];
+    for (size_t i = 0; i < n; i++) {
+        if (!ctxs[i])
+            return set_error(CKPT_E_INVAL, "ctxs[%zu] is NULL", i);
+        if (ctxs[i]->cfg.device != c0->cfg.device || ctxs[i]->cfg.chunk_bytes != c0->cfg.chunk_bytes)
+            return set_error(CKPT_E_INVAL, "batched contexts differ in device or chunk size");
+    }
+    if (c0->cfg.flags & (CKPT_KEEP_DENSE | CKPT_NO_DRAIN | CKPT_DRAIN_DIRECT))
+        return set_error(CKPT_E_INVAL, "batches keep no dense image and drain through staging");
+    DeviceGuard g(c0->cfg.device);
+    std::vector<Row> rows;
+    std::vector<size_t> parts(n);
+    for (size_t i = 0; i < n; i++) {
+        parts[i] = rows.size();
+        rows.insert(rows.end(), ctxs[i]->live.begin(), ctxs[i]->live.end());
+    }
+    std::vector<ckpt_image *> o(n, nullptr);
+    int rc = run_checkpoint(c0, (hipStream_t)stream, CKPT_FULL, nullptr, rows, parts, o);
+    if (rc == CKPT_OK)
+        for (size_t i = 0; i < n; i++)
+            outs[i] = o[i];
+    return rc;
+}
+
+// ------------------------------------------------------------------ restore
+
+extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, const ckpt_image *delta,
+                            void *const *dst, const size_t *dst_bytes, size_t n_dst, ckpt_verify_report *rep)
+{
+    if (!ctx || !img)
+        return set_error(CKPT_E_INVAL, "ctx or image is NULL");
+    if (!img->drained || img->mode != CKPT_FULL)
+        return set_error(CKPT_E_INVAL, "restore needs a drained full image");
+    if (img->C != ctx->cfg.chunk_bytes)
+        return set_error(CKPT_E_MISMATCH, "image chunk size %u, context %u", img->C, ctx->cfg.chunk_bytes);
+    const uint64_t n = img->allocs.size();
+    if (n_dst != n)
+        return set_error(CKPT_E_MISMATCH, "%zu destinations for %llu allocations", n_dst, (unsigned long long)n);
+    if (n && !dst)
+        return set_error(CKPT_E_INVAL, "dst is NULL");
+    std::vector<Row> rows(n);
+    for (uint64_t k = 0; k < n; k++) {
+        const uint64_t d = (uint64_t)(uintptr_t)dst[k], sz = img->allocs[k].size;
+        if (dst_bytes && dst_bytes[k] < sz)
+            return set_error(CKPT_E_MISMATCH, "dst[%llu] holds %zu of %llu bytes", (unsigned long long)k,
+                             dst_bytes[k], (unsigned long long)sz);
+        if (d % 16 != 0 || (sz && d == 0))
+            return set_error(CKPT_E_INVAL, "dst[%llu] is NULL or not 16-byte aligned", (unsigned long long)k);
+        rows[k].id = img->allocs[k].id;
+        rows[k].kind = img->allocs[k].kind;
+        rows[k].ptr = d;
+        rows[k].size = sz;
+    }
+    if (delta) {
+        if (delta->mode != CKPT_INCREMENTAL || !delta->drained)
+            return set_error(CKPT_E_INVAL, "delta is not a drained incremental image");
+        if (delta->base_serial != img->serial || !same_table(img, delta))
+            return set_error(CKPT_E_MISMATCH, "delta was not taken against this image");
+        // ids index chunk arrays on the device: they must be ascending and < N
+        const uint64_t *ids = (const uint64_t *)delta->ids_buf.p;
+        for (uint64_t i = 0; i < delta->n_dirty; i++)
+            if (ids[i] >= img->N || (i && ids[i] <= ids[i - 1]))
+                return set_error(CKPT_E_INVAL, "delta id list is not ascending below %llu",
+                                 (unsigned long long)img->N);
+    }
+    const uint64_t N = img->N;
+    const uint64_t stage = img->ser_bytes + (delta ? delta->ser_bytes : 0);
+    if (ctx->cfg.staging_budget && stage > ctx->cfg.staging_budget)
+        return set_error(CKPT_E_BUDGET, "restore staging %llu B exceeds the budget", (unsigned long long)stage);
+
+    DeviceGuard g(ctx->cfg.device);
+    hipStream_t s = (hipStream_t)stream;
+    const bool timing = ctx->cfg.flags & CKPT_TIMING;
+    ckpt_timing &T = ctx->timing;
+    memset(&T, 0, sizeof(T));
+    const auto t_call = std::chrono::steady_clock::now();
+
+    if (timing)
+        HIP_TRY(hipEventRecord(ctx->ev[0], s));
+    CKPT_TRY(upload_table(ctx, s, rows, true, N, N));
+    CKPT_TRY(ctx->d_crc.ensure(std::max<uint64_t>(N, 1) * 4));
+    CKPT_TRY(ctx->d_flags.ensure(std::max<uint64_t>(N, 1)));
+    CKPT_TRY(ctx->d_bad.ensure(std::max<uint64_t>(N, 1)));
+    CKPT_TRY(ctx->d_soff.ensure(std::max<uint64_t>(N, 1) * 8));
+    CKPT_TRY(ctx->d_compact.ensure(std::max<uint64_t>(stage, 16)));
+    uint8_t *staging = (uint8_t *)ctx->d_compact.p;
+    if (N) {
+        HIP_TRY(hipMemcpyAsync(ctx->d_crc.p, img->crc_buf.p, N * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ctx->d_flags.p, img->flags_buf.p, N, hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_fill_u64(s, (uint64_t *)ctx->d_bad.p, (N + 7) / 8, 0));
+    }
+    if (img->ser_bytes)
+        HIP_TRY(hipMemcpyAsync(staging, img->data.p, img->ser_bytes, hipMemcpyHostToDevice, s));
+    if (timing)
+        HIP_TRY(hipEventRecord(ctx->ev[1], s));
+
+    ChunkArgs a = chunk_args(ctx);
+    a.dst = (const uint64_t *)ctx->d_addr.p;
+    a.staging = staging;
+    a.soff = (const uint64_t *)ctx->d_soff.p;
+    a.want_crc = (const uint32_t *)ctx->d_crc.p;
+    a.want_flags = (const uint8_t *)ctx->d_flags.p;
+    a.bad = (uint8_t *)ctx->d_bad.p;
+    DevPlan P;
+    if (N) {
+        CKPT_TRY(run_select(ctx, s, kSelNonZero, (const uint8_t *)ctx->d_flags.p, nullptr, N,
+                            (uint64_t *)ctx->d_soff.p, nullptr, 0));
+        // The flags decide which chunks are read from staging: they must account
+        // for exactly the serialized bytes, or the scatter would read past them.
+        CKPT_TRY(read_plan(ctx, s, &P));
+        if (P.sel_bytes != img->ser_bytes)
+            return set_error(CKPT_E_INVAL, "flags select %llu serialized bytes, image holds %llu",
+                             (unsigned long long)P.sel_bytes, (unsigned long long)img->ser_bytes);
+        HIP_TRY(launch_chunks(s, kModeRestore, a, ctx->grid_chunks, ctx->cfg.block_threads));
+    } else if (img->ser_bytes) {
+        return set_error(CKPT_E_INVAL, "image without chunks holds serialized bytes");
+    }
+    if (delta && delta->n_dirty) {
+        const uint64_t nd = delta->n_dirty;
+        CKPT_TRY(ctx->d_crc2.ensure(std::max<uint64_t>(N, 1) * 4));
+        CKPT_TRY(ctx->d_flags2.ensure(std::max<uint64_t>(N, 1)));
+        CKPT_TRY(ctx->d_ids.ensure(nd * 8));
+        CKPT_TRY(ctx->d_soff2.ensure(nd * 8));
+        uint8_t *staging2 = staging + img->ser_bytes;
+        HIP_TRY(hipMemcpyAsync(ctx->d_crc2.p, delta->crc_buf.p, N * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ctx->d_flags2.p, delta->flags_buf.p, N, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ctx->d_ids.p, delta->ids_buf.p, nd * 8, hipMemcpyHostToDevice, s));
+        if (delta->ser_bytes)
+            HIP_TRY(hipMemcpyAsync(staging2, delta->data.p, delta->ser_bytes, hipMemcpyHostToDevice, s));
+        // n_items = the delta's id count (plan field written from pinned memory)
+        auto *hp = (DevPlan *)ctx->h_plan.p;
+        HIP_TRY(hipStreamSynchronize(s));   // h_plan is reused below; keep the copy ordered
+        hp->n_items = nd;
+        HIP_TRY(hipMemcpyAsync((uint8_t *)ctx->d_plan.p + offsetof(DevPlan, n_items), &hp->n_items, 8,
+                               hipMemcpyHostToDevice, s));
+        CKPT_TRY(run_select(ctx, s, kSelIdsNonZero, (const uint8_t *)ctx->d_flags2.p, (const uint64_t *)ctx->d_ids.p,
+                            nd, (uint64_t *)ctx->d_soff2.p, nullptr, 0));
+        CKPT_TRY(read_plan(ctx, s, &P));
+        if (P.sel_bytes != delta->ser_bytes)
+            return set_error(CKPT_E_INVAL, "delta flags select %llu bytes, delta holds %llu",
+                             (unsigned long long)P.sel_bytes, (unsigned long long)delta->ser_bytes);
+        ChunkArgs b = a;
+        b.staging = staging2;
+        b.soff = (const uint64_t *)ctx->d_soff2.p;
+        b.want_crc = (const uint32_t *)ctx->d_crc2.p;
+        b.want_flags = (const uint8_t *)ctx->d_flags2.p;
+        b.ids = (const uint64_t *)ctx->d_ids.p;
+        HIP_TRY(launch_chunks(s, kModeRestore, b, ctx->grid_chunks, ctx->cfg.block_threads));
+    }
+    if (timing)
+        HIP_TRY(hipEventRecord(ctx->ev[2], s));
+    CKPT_TRY(read_plan(ctx, s, &P));
+    uint64_t n_bad = 0, n_ids = 0;
+    uint64_t ids[CKPT_REPORT_MAX];
+    if (P.bad_count) {
+        CKPT_TRY(ctx->d_ids.ensure(CKPT_REPORT_MAX * 8));
+        CKPT_TRY(run_select(ctx, s, kSelBad, (const uint8_t *)ctx->d_bad.p, nullptr, N, nullptr,
+                            (uint64_t *)ctx->d_ids.p, CKPT_REPORT_MAX));
+        CKPT_TRY(read_plan(ctx, s, &P));
+        n_bad = P.sel_count;
+        n_ids = std::min<uint64_t>(n_bad, CKPT_REPORT_MAX);
+        HIP_TRY(hipMemcpy(ids, ctx->d_ids.p, n_ids * 8, hipMemcpyDeviceToHost));
+    }
+    if (timing) {
+        T.h2d_ms = ev_ms(ctx->ev[0], ctx->ev[1]);
+        T.scatter_ms = ev_ms(ctx->ev[1], ctx->ev[2]);
+    }
+    T.link_bytes = stage + 5 * N;
+    T.total_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t_call).count();
+    if (rep) {
+        memset(rep, 0, sizeof(*rep));
+        rep->n_bad = n_bad;
+        rep->n_ids = n_ids;
+        memcpy(rep->ids, ids, n_ids * 8);
+    }
+    return n_bad ? set_error(CKPT_E_CORRUPT, "%llu chunks failed verification", (unsigned long long)n_bad)
+                 : CKPT_OK;
+}
+
+// -------------------------------------------------------------------- image
+
+extern "C" int ckpt_image_info(const ckpt_image *img, ckpt_image_meta *out)
+{
+    if (!img || !out)
+        return set_error(CKPT_E_INVAL, "image or out is NULL");
+    memset(out, 0, sizeof(*out));
+    out->mode = img->mode;
+    out->chunk_bytes = img->C;
+    out->n_allocs = img->allocs.size();
+    out->n_chunks = img->N;
+    out->data_bytes = img->data_bytes;
+    out->serialized_bytes = img->ser_bytes;
+    out->n_dirty = img->n_dirty;
+    out->serial = img->serial;
+    out->base_serial = img->base_serial;
+    out->crc_digest = img->digest;
+    out->has_dense = img->dense != nullptr;
+    out->drained = img->drained;
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_image_view(const ckpt_image *img, int section, const void **p, size_t *bytes)
+{
+    if (!img || !p || !bytes)
+        return set_error(CKPT_E_INVAL, "NULL argument");
+    switch (section) {
+    case CKPT_SEC_ALLOCS:
+        *p = img->allocs.empty() ? nullptr : img->allocs.data();
+        *bytes = img->allocs.size() * sizeof(ckpt_alloc_rec);
+        break;
+    case CKPT_SEC_CRC:
+        *p = img->N ? img->crc_buf.p : nullptr;
+        *bytes = img->N * 4;
+        break;
+    case CKPT_SEC_FLAGS:
+        *p = img->N ? img->flags_buf.p : nullptr;
+        *bytes = img->N;
+        break;
+    case CKPT_SEC_DATA:
+        *p = img->ser_bytes ? img->data.p : nullptr;
+        *bytes = img->ser_bytes;
+        break;
+    case CKPT_SEC_DIRTY_IDS:
+        *p = img->n_dirty ? img->ids_buf.p : nullptr;
+        *bytes = img->n_dirty * 8;
+        break;
+    case CKPT_SEC_DENSE:
+        *p = img->dense;
+        *bytes = img->dense ? img->data_bytes : 0;
+        break;
+    default:
+        return set_error(CKPT_E_INVAL, "unknown section %d", section);
+    }
+    return CKPT_OK;
+}
+
+// Serialized form, all little-endian:
+//   header (kHeaderBytes): magic "CKPTIMG1", version, mode, C, align (16),
+//   n, N, data_bytes, ser_bytes, n_dirty, serial, base_serial, digest
+//   ALLOCS n x 40, CRC N x 4, FLAGS N (padded to 8), DIRTY_IDS n_dirty x 8, DATA
+namespace {
+constexpr char kMagic[8] = {'C', 'K', 'P', 'T', 'I', 'M', 'G', '1'};
+constexpr uint32_t kVersion = 1;
+constexpr size_t kHeaderBytes = 8 + 4 * 4 + 8 * 8;
+size_t pad8(size_t x) { return (x + 7) & ~size_t(7); }
+
+size_t serialized_size(uint64_t n, uint64_t N, uint64_t n_dirty, uint64_t ser)
+{
+    return kHeaderBytes + n * sizeof(ckpt_alloc_rec) + N * 4 + pad8(N) + n_dirty * 8 + ser;
+}
+}  // namespace
+
+extern "C" int ckpt_image_serialize(const ckpt_image *img, void *buf, size_t cap, size_t *need)
+{
+    if (!img || !need)
+        return set_error(CKPT_E_INVAL, "NULL argument");
+    if (!img->drained)
+        return set_error(CKPT_E_INVAL, "image holds no host data");
+    const uint64_t n = img->allocs.size();
+    const size_t total = serialized_size(n, img->N, img->n_dirty, img->ser_bytes);
+    *need = total;
+    if (!buf)
+        return CKPT_OK;
+    if (cap < total)
+        return set_error(CKPT_E_INVAL, "buffer holds %zu of %zu bytes", cap, total);
+    uint8_t *p = (uint8_t *)buf;
+    memcpy(p, kMagic, 8);
+    uint32_t h32[4] = {kVersion, img->mode, img->C, 16};
+    memcpy(p + 8, h32, 16);
+    uint64_t h64[8] = {n, img->N, img->data_bytes, img->ser_bytes, img->n_dirty, img->serial, img->base_serial,
+                       img->digest};
+    memcpy(p + 24, h64, 64);
+    p += kHeaderBytes;
+    if (n)
+        memcpy(p, img->allocs.data(), n * sizeof(ckpt_alloc_rec));
+    p += n * sizeof(ckpt_alloc_rec);
+    if (img->N) {
+        memcpy(p, img->crc_buf.p, img->N * 4);
+        memcpy(p + img->N * 4, img->flags_buf.p, img->N);
+    }
+    memset(p + img->N * 4 + img->N, 0, pad8(img->N) - img->N);
+    p += img->N * 4 + pad8(img->N);
+    if (img->n_dirty)
+        memcpy(p, img->ids_buf.p, img->n_dirty * 8);
+    p += img->n_dirty * 8;
+    if (img->ser_bytes)
+        memcpy(p, img->data.p, img->ser_bytes);
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_image_load(ckpt_ctx *ctx, const void *buf, size_t bytes, ckpt_image **out)
+{
+    if (!buf || !out)
+        return set_error(CKPT_E_INVAL, "NULL argument");
+    if (bytes < kHeaderBytes)
+        return set_error(CKPT_E_INVAL, "truncated image header (%zu bytes)", bytes);
+    const uint8_t *p = (const uint8_t *)buf;
+    if (memcmp(p, kMagic, 8) != 0)
+        return set_error(CKPT_E_INVAL, "bad magic");
+    uint32_t h32[4];
+    uint64_t h64[8];
+    memcpy(h32, p + 8, 16);
+    memcpy(h64, p + 24, 64);
+    if (h32[0] != kVersion || (h32[1] != CKPT_FULL && h32[1] != CKPT_INCREMENTAL) || h32[2] == 0 ||
+        h32[2] % 16 != 0 || h32[3] != 16)
+        return set_error(CKPT_E_INVAL, "bad header fields");
+    const uint64_t n = h64[0], N = h64[1], nd = h64[4], ser = h64[3];
+    // bound every count by the buffer before multiplying
+    if (n > bytes / sizeof(ckpt_alloc_rec) || N > bytes / 5 || nd > bytes / 8 || ser > bytes)
+        return set_error(CKPT_E_INVAL, "truncated image");
+    const size_t total = serialized_size(n, N, nd, ser);
+    if (bytes < total)
+        return set_error(CKPT_E_INVAL, "truncated image: %zu of %zu bytes", bytes, total);
+    auto *img = new ckpt_image();
+    std::unique_ptr<ckpt_image> guard(img);
+    img->device = ctx ? ctx->cfg.device : 0;
+    img->mode = h32[1];
+    img->C = h32[2];
+    img->N = N;
+    img->data_bytes = h64[2];
+    img->ser_bytes = ser;
+    img->n_dirty = nd;
+    img->serial = h64[5];
+    img->base_serial = h64[6];
+    img->digest = h64[7];
+    img->drained = true;
+    p += kHeaderBytes;
+    img->allocs.resize(n);
+    if (n)
+        memcpy(img->allocs.data(), p, n * sizeof(ckpt_alloc_rec));
+    p += n * sizeof(ckpt_alloc_rec);
+    // the table must be self-consistent: offsets and chunk bases are prefix sums
+    uint64_t o = 0, g = 0;
+    for (uint64_t k = 0; k < n; k++) {
+        const ckpt_alloc_rec &r = img->allocs[k];
+        if (r.off != o || r.cb != g || (r.kind != CKPT_DEVICE && r.kind != CKPT_MANAGED))
+            return set_error(CKPT_E_INVAL, "inconsistent allocation table at row %llu", (unsigned long long)k);
+        o += ru16(r.size);
+        g += (r.size + img->C - 1) / img->C;
+    }
+    if (o != img->data_bytes || g != N)
+        return set_error(CKPT_E_INVAL, "allocation table does not match the header totals");
+    CKPT_TRY(img->crc_buf.ensure(std::max<uint64_t>(N, 1) * 4));
+    CKPT_TRY(img->flags_buf.ensure(std::max<uint64_t>(N, 1)));
+    if (N) {
+        memcpy(img->crc_buf.p, p, N * 4);
+        memcpy(img->flags_buf.p, p + N * 4, N);
+    }
+    p += N * 4 + pad8(N);
+    CKPT_TRY(img->ids_buf.ensure(std::max<uint64_t>(nd, 1) * 8));
+    if (nd)
+        memcpy(img->ids_buf.p, p, nd * 8);
+    p += nd * 8;
+    CKPT_TRY(img->data.ensure(std::max<uint64_t>(ser, 1)));
+    if (ser)
+        memcpy(img->data.p, p, ser);
+    if (fnv1a64(img->crc_buf.p, N * 4) != img->digest)
+        return set_error(CKPT_E_INVAL, "CRC section digest mismatch");
+    *out = guard.release();
+    return CKPT_OK;
+}
+
+extern "C" void ckpt_image_free(ckpt_image *img) { delete img; }

@@ -1,0 +1,98 @@
+"""The C ABI library loads and exports every entry point include/ckpt.h
+declares; argument checks that need no GPU behave as documented."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ckpt.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(ckpt_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def ck():
+    from paper_2008_10596_amd import ckpt
+    if not os.path.exists(ckpt.LIB_PATH):
+        from paper_2008_10596_amd import build
+        build.build()
+    return ckpt
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared_functions()
+    for must in ("ckpt_init", "ckpt_destroy", "ckpt_register", "ckpt_unregister", "ckpt_checkpoint",
+                 "ckpt_restore", "ckpt_image_info", "ckpt_image_view", "ckpt_image_serialize",
+                 "ckpt_image_load", "ckpt_image_free", "ckpt_checkpoint_batch", "ckpt_strerror"):
+        assert must in names, must
+
+
+def test_library_exports_every_declared_symbol(ck):
+    lib = ck.lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # and nothing C++-mangled leaks into the boundary's names
+    out = subprocess.run(["nm", "-D", "--defined-only", ck.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    assert set(declared_functions()) <= exported
+
+
+def test_binding_declares_every_symbol(ck):
+    bound = {s[0] for s in ck.SIGNATURES}
+    assert set(declared_functions()) <= bound
+
+
+def test_strerror_covers_every_status(ck):
+    lib = ck.lib()
+    seen = set()
+    for st in range(0, -9, -1):
+        s = lib.ckpt_strerror(st).decode()
+        assert s and s != "unknown status"
+        seen.add(s)
+    assert len(seen) == 9
+    assert lib.ckpt_strerror(-100).decode() == "unknown status"
+
+
+def test_init_rejects_bad_configs_before_touching_a_device(ck):
+    lib = ck.lib()
+    h = ctypes.c_void_p()
+    assert lib.ckpt_init(None, None) == ck.CKPT_E_INVAL
+    for field, value in (("chunk_bytes", 8), ("chunk_bytes", 4100), ("block_threads", 100),
+                         ("waves_per_chunk", 3), ("waves_per_chunk", 8)):
+        cfg = ck.ckpt_config()
+        setattr(cfg, field, value)
+        if field == "waves_per_chunk" and value == 8:
+            cfg.block_threads = 256          # 8 waves do not fit 4-wave workgroups
+        assert lib.ckpt_init(ctypes.byref(cfg), ctypes.byref(h)) == ck.CKPT_E_INVAL, (field, value)
+
+
+def test_image_load_rejects_malformed_buffers(ck):
+    lib = ck.lib()
+    out = ctypes.c_void_p()
+    for buf in (b"", b"CKPTIMG1", b"NOTMAGIC" + bytes(80), b"CKPTIMG1" + bytes(80)):
+        b = (ctypes.c_uint8 * max(len(buf), 1)).from_buffer_copy(buf or b"\0")
+        assert lib.ckpt_image_load(None, b, len(buf), ctypes.byref(out)) == ck.CKPT_E_INVAL
+    # a header that claims more rows than the buffer holds
+    hdr = bytearray(b"CKPTIMG1")
+    hdr += (1).to_bytes(4, "little") + (0).to_bytes(4, "little") + (4096).to_bytes(4, "little") + (16).to_bytes(4, "little")
+    hdr += (1 << 40).to_bytes(8, "little") + bytes(56)
+    b = (ctypes.c_uint8 * len(hdr)).from_buffer_copy(bytes(hdr))
+    assert lib.ckpt_image_load(None, b, len(hdr), ctypes.byref(out)) == ck.CKPT_E_INVAL
+
+
+def test_null_arguments_are_rejected(ck):
+    lib = ck.lib()
+    assert lib.ckpt_register(None, None, 0, 0, None) == ck.CKPT_E_INVAL
+    assert lib.ckpt_unregister(None, None) == ck.CKPT_E_INVAL
+    assert lib.ckpt_checkpoint(None, None, 0, None, None) == ck.CKPT_E_INVAL
+    assert lib.ckpt_restore(None, None, None, None, None, None, 0, None) == ck.CKPT_E_INVAL
+    assert lib.ckpt_image_info(None, None) == ck.CKPT_E_INVAL
+    lib.ckpt_destroy(None)
+    lib.ckpt_image_free(None)

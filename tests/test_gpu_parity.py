@@ -1,0 +1,396 @@
+"""Bit-exact parity of the HIP path with the CPU oracle, through the C ABI.
+
+Every comparison is element by element: allocation table, per-chunk CRC-32C,
+ZERO/DIRTY flags, serialized data, dense device image, dirty-id lists,
+restored memory and verification reports.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import oracle as O
+from paper_2008_10596_amd import ckpt as K
+from tests.gpu_common import (FLAG_ZERO, check_full, check_restored, d2h, host, log, random_allocs,
+                              register_all)
+
+pytestmark = pytest.mark.gpu
+
+
+def full_roundtrip(tensors, C, zero_expect=None, **ctx_kw):
+    ctx = K.Context(chunk_bytes=C, flags=K.CKPT_KEEP_DENSE, **ctx_kw)
+    ids = register_all(ctx, tensors)
+    img = ctx.checkpoint()
+    ref = O.checkpoint([host(t) for t in tensors], C)
+    check_full(img, ref, tensors, C, ids)
+    # dense device image == oracle dense image
+    p, nb = img.dense_ptr
+    assert nb == ref["data_bytes"]
+    assert np.array_equal(d2h(p, nb), ref["dense"][:nb])
+    # restore into fresh buffers
+    dsts = [torch.full((t.numel(),), 0xA5, dtype=torch.uint8, device="cuda") for t in tensors]
+    rc, rep = ctx.restore(img, dsts)
+    assert rc == K.CKPT_OK and rep["n_bad"] == 0
+    check_restored(dsts, tensors)
+    img.close()
+    ctx.close()
+    return ref
+
+
+def test_plain_workload_64_allocations():
+    w = synth.plain()
+    log("plain workload: %d allocations, %d bytes" % (len(w["sizes"]), int(w["sizes"].sum())))
+    tensors = synth.make_device_allocs(w["sizes"], w["zero"], workload=1)
+    full_roundtrip(tensors, 4096)
+
+
+EDGE_SIZES = [0, 1, 2, 3, 4, 5, 7, 15, 16, 17, 31, 33, 63, 64, 65, 1007, 1008, 1009, 1023, 1024,
+              1025, 2047, 2048, 4095, 4096, 4097, 4111, 4112, 8191, 8192, 12289, 65535, 65536, 65537,
+              100003]
+
+
+@pytest.mark.parametrize("C", [16, 32, 48, 256, 1008, 1024, 1040, 4096, 4112, 16384, 65536, 262144])
+def test_edge_sizes_and_chunk_sizes(C):
+    log("edge sizes, C=%d" % C)
+    tensors = random_allocs(EDGE_SIZES, seed=C, zero=(9, 20))
+    # single non-zero bytes inside otherwise-zero allocations, at chunk edges
+    for t, pos in zip(tensors[9:10] + tensors[20:21], (3, 1000)):
+        if pos < t.numel():
+            t[pos] = 7
+    full_roundtrip(tensors, C)
+
+
+@pytest.mark.parametrize("block,wpc", [(64, 1), (256, 1), (256, 2), (256, 4), (512, 8), (1024, 1), (1024, 16)])
+@pytest.mark.parametrize("C", [4096, 65536])
+def test_launch_shapes(block, wpc, C):
+    log("launch shape block=%d waves/chunk=%d C=%d" % (block, wpc, C))
+    sizes = [C * 3 + 5, C, C - 16, 17, C * 2, 1 << 20]
+    tensors = random_allocs(sizes, seed=block * 31 + wpc, zero=(1,))
+    full_roundtrip(tensors, C, block_threads=block, waves_per_chunk=wpc)
+
+
+def test_zero_chunks_inside_random_allocations():
+    C = 4096
+    tensors = random_allocs([C * 10 + 100, C * 3], seed=5)
+    tensors[0][C * 2:C * 4] = 0          # two interior ZERO chunks
+    tensors[0][C * 10:] = 0              # ZERO tail chunk
+    tensors[1][:C] = 0
+    ref = full_roundtrip(tensors, C)
+    assert [int(f) & FLAG_ZERO for f in ref["flags"]] == [0, 0, 1, 1, 0, 0, 0, 0, 0, 0, 1, 1, 0, 0]
+
+
+def test_empty_and_all_zero_contexts():
+    ctx = K.Context()
+    img = ctx.checkpoint()
+    info = img.info()
+    assert info["n_allocs"] == 0 and info["n_chunks"] == 0 and info["serialized_bytes"] == 0
+    rc, rep = ctx.restore(img, [])
+    assert rc == K.CKPT_OK
+    tensors = [torch.zeros(n, dtype=torch.uint8, device="cuda") for n in (0, 5000, 4096)]
+    register_all(ctx, tensors)
+    img = ctx.checkpoint()
+    ref = O.checkpoint([host(t) for t in tensors], 4096)
+    check_full(img, ref, tensors, 4096)
+    assert img.info()["serialized_bytes"] == 0
+
+
+def test_registration_order_and_unregister():
+    ctx = K.Context(chunk_bytes=1024)
+    tensors = random_allocs([3000, 100, 5000, 77, 2048], seed=11)
+    ids = register_all(ctx, tensors)
+    assert ids == [1, 2, 3, 4, 5]
+    ctx.unregister(tensors[1])
+    ctx.unregister(tensors[3])
+    extra = random_allocs([999], seed=12)[0]
+    assert ctx.register(extra) == 6
+    live = [tensors[0], tensors[2], tensors[4], extra]
+    img = ctx.checkpoint()
+    ref = O.checkpoint([host(t) for t in live], 1024)
+    check_full(img, ref, live, 1024, ids=[1, 3, 5, 6])
+
+
+def test_registration_errors():
+    ctx = K.Context()
+    buf = torch.empty(1 << 16, dtype=torch.uint8, device="cuda")
+    base = buf.data_ptr()
+    with pytest.raises(K.CkptError) as e:
+        ctx.register(base + 8, 64)
+    assert e.value.status == K.CKPT_E_INVAL
+    with pytest.raises(K.CkptError) as e:
+        ctx.register(base, 64, kind=7)
+    assert e.value.status == K.CKPT_E_INVAL
+    ctx.register(base, 4096)
+    for start, n in ((base, 16), (base + 4080, 32), (base - 16, 32), (base + 16, 16)):
+        with pytest.raises(K.CkptError) as e:
+            ctx.register(start, n)
+        assert e.value.status == K.CKPT_E_INVAL, (start - base, n)
+    ctx.register(base + 4096, 4096)      # adjacent: fine
+    with pytest.raises(K.CkptError) as e:
+        ctx.unregister(base + 16)
+    assert e.value.status == K.CKPT_E_NOTFOUND
+    ctx.unregister(base)
+    ctx.register(base, 16)               # the range is free again
+    assert ctx.live_count() == 2
+
+
+# ------------------------------------------------------------ incremental
+
+@pytest.mark.parametrize("C", [4096, 65536])
+def test_incremental_matches_oracle_and_restores(C):
+    log("incremental C=%d" % C)
+    sizes = [C * 7 + 123, C * 2, 5000, C * 30, 16]
+    tensors = random_allocs(sizes, seed=C + 1)
+    ctx = K.Context(chunk_bytes=C)
+    register_all(ctx, tensors)
+    base = ctx.checkpoint()
+    base_ref = O.checkpoint([host(t) for t in tensors], C)
+    check_full(base, base_ref, tensors, C)
+    # mutate: rewrite some chunks, zero one, touch a tail byte
+    tensors[0][C:2 * C] = torch.randint(0, 256, (C,), dtype=torch.uint8, device="cuda")
+    tensors[3][5 * C:6 * C] = 0
+    tensors[0][-1] ^= 1
+    tensors[4][3] ^= 0x80
+    hosts = [host(t) for t in tensors]
+    dref = O.delta(hosts, C, base_ref["crc"])
+    delta = ctx.checkpoint(mode=K.CKPT_INCREMENTAL, base=base)
+    info = delta.info()
+    assert info["mode"] == K.CKPT_INCREMENTAL
+    assert info["base_serial"] == base.info()["serial"]
+    assert np.array_equal(delta.crc, dref["crc"])
+    assert np.array_equal(delta.flags, dref["flags"])
+    assert np.array_equal(delta.dirty_ids, dref["dirty_ids"])
+    assert np.array_equal(delta.data, dref["delta"])
+    # restore(base, delta) == current memory
+    dsts = [torch.full((t.numel(),), 0x5A, dtype=torch.uint8, device="cuda") for t in tensors]
+    rc, rep = ctx.restore(base, dsts, delta=delta)
+    assert rc == K.CKPT_OK, rep
+    check_restored(dsts, tensors)
+    # a second increment against the first (the device-resident CRC chain)
+    tensors[1][:10] = 1
+    hosts2 = [host(t) for t in tensors]
+    dref2 = O.delta(hosts2, C, dref["crc"])
+    delta2 = ctx.checkpoint(mode=K.CKPT_INCREMENTAL, base=delta)
+    assert np.array_equal(delta2.dirty_ids, dref2["dirty_ids"])
+    assert np.array_equal(delta2.data, dref2["delta"])
+
+
+def test_incremental_all_dirty_equals_full():
+    C = 4096
+    tensors = random_allocs([C * 5 + 9, 300, C * 2], seed=77, zero=(1,))
+    ctx = K.Context(chunk_bytes=C)
+    register_all(ctx, tensors)
+    base = ctx.checkpoint()
+    for t in tensors:
+        synth.fill_random_(t, t.numel() + 3)
+    tensors[1].zero_()
+    tensors[1][0] = 1                    # the ZERO chunk becomes non-ZERO
+    full = K.Context(chunk_bytes=C)
+    register_all(full, tensors)
+    f = full.checkpoint()
+    d = ctx.checkpoint(mode=K.CKPT_INCREMENTAL, base=base)
+    assert list(d.dirty_ids) == list(range(d.info()["n_chunks"]))
+    assert np.array_equal(d.data, f.data)
+    assert np.array_equal(d.crc, f.crc)
+
+
+def test_incremental_nothing_changed_is_empty():
+    ctx = K.Context()
+    tensors = random_allocs([10000, 5000], seed=3)
+    register_all(ctx, tensors)
+    base = ctx.checkpoint()
+    d = ctx.checkpoint(mode=K.CKPT_INCREMENTAL, base=base)
+    assert d.info()["n_dirty"] == 0 and d.info()["serialized_bytes"] == 0
+    assert not (d.flags & 2).any()
+
+
+def test_incremental_base_mismatch():
+    ctx = K.Context()
+    tensors = random_allocs([10000, 5000], seed=4)
+    register_all(ctx, tensors)
+    base = ctx.checkpoint()
+    ctx.register(random_allocs([64], seed=5)[0])
+    with pytest.raises(K.CkptError) as e:
+        ctx.checkpoint(mode=K.CKPT_INCREMENTAL, base=base)
+    assert e.value.status == K.CKPT_E_MISMATCH
+    other = K.Context(chunk_bytes=8192)
+    with pytest.raises(K.CkptError) as e:
+        other.restore(base, tensors)
+    assert e.value.status == K.CKPT_E_MISMATCH
+
+
+# --------------------------------------------------------------- restore
+
+def test_restore_errors():
+    ctx = K.Context()
+    tensors = random_allocs([10000, 5000], seed=6)
+    register_all(ctx, tensors)
+    img = ctx.checkpoint()
+    with pytest.raises(K.CkptError) as e:
+        ctx.restore(img, tensors[:1])
+    assert e.value.status == K.CKPT_E_MISMATCH
+    small = [torch.empty(10000, dtype=torch.uint8, device="cuda"), torch.empty(4999, dtype=torch.uint8, device="cuda")]
+    with pytest.raises(K.CkptError) as e:
+        ctx.restore(img, small)
+    assert e.value.status == K.CKPT_E_MISMATCH
+    buf = torch.empty(20000, dtype=torch.uint8, device="cuda")
+    with pytest.raises(K.CkptError) as e:
+        ctx.restore(img, [buf.data_ptr() + 8, buf.data_ptr() + 10016], dst_bytes=[10000, 5000])
+    assert e.value.status == K.CKPT_E_INVAL
+    # a delta taken against another image
+    img2 = ctx.checkpoint()
+    d = ctx.checkpoint(mode=K.CKPT_INCREMENTAL, base=img2)
+    with pytest.raises(K.CkptError) as e:
+        ctx.restore(img, tensors, delta=d)
+    assert e.value.status == K.CKPT_E_MISMATCH
+
+
+def test_corruption_is_reported_exactly():
+    C = 1024
+    sizes = [C * 9 + 40, C * 4]
+    tensors = random_allocs(sizes, seed=8)
+    tensors[1][:C] = 0                           # chunk 10 is ZERO
+    ctx = K.Context(chunk_bytes=C)
+    register_all(ctx, tensors)
+    img = ctx.checkpoint()
+    ref = O.checkpoint([host(t) for t in tensors], C)
+    data = img.data                              # writable view of the pinned host image
+    # flip one bit in serialized chunk 3 (all chunks before it are non-ZERO, full size)
+    data[3 * C + 100] ^= 0x10
+    dsts = [torch.empty(s, dtype=torch.uint8, device="cuda") for s in sizes]
+    rc, rep = ctx.restore(img, dsts)
+    assert rc == K.CKPT_E_CORRUPT and rep["n_bad"] == 1 and rep["ids"] == [3]
+    # the data is still written, as stored
+    h = [host(d) for d in dsts]
+    assert h[0][3 * C + 100] == ref["serialized"][3 * C + 100] ^ 0x10
+    data[3 * C + 100] ^= 0x10
+    # a ZERO chunk whose stored CRC was changed
+    img.crc[10] ^= 1
+    rc, rep = ctx.restore(img, dsts)
+    assert rc == K.CKPT_E_CORRUPT and rep["ids"] == [10]
+    img.crc[10] ^= 1
+    rc, rep = ctx.restore(img, dsts)
+    assert rc == K.CKPT_OK
+    # many bad chunks: count and the first 64 ids, ascending
+    crc = img.crc
+    crc ^= np.uint32(0xDEAD)
+    rc, rep = ctx.restore(img, dsts)
+    assert rc == K.CKPT_E_CORRUPT and rep["n_bad"] == img.info()["n_chunks"]
+    assert rep["ids"] == list(range(min(64, img.info()["n_chunks"])))
+
+
+def test_many_bad_report_first_64_of_many():
+    C = 256
+    tensors = random_allocs([C * 500 + 7], seed=9)
+    ctx = K.Context(chunk_bytes=C)
+    register_all(ctx, tensors)
+    img = ctx.checkpoint()
+    bad = [5, 17, 64, 65, 100, 250, 499, 500] + list(range(300, 400))
+    for g in bad:
+        img.crc[g] ^= 0x100
+    rc, rep = ctx.restore(img, [torch.empty_like(tensors[0])])
+    assert rc == K.CKPT_E_CORRUPT
+    assert rep["n_bad"] == len(set(bad))
+    assert rep["ids"] == sorted(set(bad))[:64]
+
+
+# ------------------------------------------------------------ serialization
+
+def test_serialize_load_roundtrip_and_restore():
+    C = 4096
+    tensors = random_allocs([50000, 4096, 123], seed=10, zero=(1,))
+    ctx = K.Context(chunk_bytes=C)
+    register_all(ctx, tensors)
+    img = ctx.checkpoint()
+    blob = img.serialize()
+    img2 = K.Image.load(blob, ctx)
+    assert img2.serialize() == blob
+    for name in ("crc", "flags", "data", "allocs"):
+        assert np.array_equal(getattr(img2, name), getattr(img, name)), name
+    dsts = [torch.empty_like(t) for t in tensors]
+    rc, _ = ctx.restore(img2, dsts)
+    assert rc == K.CKPT_OK
+    check_restored(dsts, tensors)
+    # truncated and bit-flipped (digest) buffers are refused
+    with pytest.raises(K.CkptError) as e:
+        K.Image.load(blob[:-1], ctx)
+    assert e.value.status == K.CKPT_E_INVAL
+    bad = bytearray(blob)
+    bad[88 + 3 * 40 + 2] ^= 1                   # inside the CRC section
+    with pytest.raises(K.CkptError) as e:
+        K.Image.load(bytes(bad), ctx)
+    assert e.value.status == K.CKPT_E_INVAL
+
+
+# ------------------------------------------------------------------ batch
+
+def test_batch_equals_each_context_alone():
+    C = 4096
+    rng = np.random.default_rng(12)
+    ctxs, allocs = [], []
+    for i in range(12):
+        sizes = [int(x) for x in rng.integers(0, 300000, int(rng.integers(1, 6)))]
+        t = random_allocs(sizes, seed=100 + i, zero=(0,) if i % 3 == 0 else ())
+        c = K.Context(chunk_bytes=C)
+        register_all(c, t)
+        ctxs.append(c)
+        allocs.append(t)
+    ctxs.append(K.Context(chunk_bytes=C))       # an empty context in the batch
+    allocs.append([])
+    imgs = K.checkpoint_batch(ctxs)
+    for c, t, img in zip(ctxs, allocs, imgs):
+        ref = O.checkpoint([host(x) for x in t], C)
+        check_full(img, ref, t, C)
+        dsts = [torch.empty_like(x) for x in t]
+        rc, _ = c.restore(img, dsts)
+        assert rc == K.CKPT_OK
+        check_restored(dsts, t)
+
+
+# --------------------------------------------------------------- ordering
+
+def test_checkpoint_sees_work_enqueued_before_it():
+    """A writer enqueued before the checkpoint (same stream, stream-ordered
+    mode; another stream, default device-wide mode) is in the image."""
+    n = 64 << 20
+    for flags, other_stream in ((K.CKPT_STREAM_ORDERED, False), (0, True)):
+        t = torch.zeros(n, dtype=torch.uint8, device="cuda")
+        ctx = K.Context(chunk_bytes=65536, flags=flags)
+        ctx.register(t)
+        s = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            for _ in range(20):                 # long enough to still be running
+                t.add_(1)
+        img = ctx.checkpoint(stream=torch.cuda.current_stream() if other_stream else s)
+        ref = O.checkpoint([np.full(n, 20, np.uint8)], 65536)
+        assert np.array_equal(img.crc, ref["crc"]), "checkpoint missed prior work (flags=%d)" % flags
+        ctx.close()
+
+
+def test_timing_is_reported():
+    ctx = K.Context(flags=K.CKPT_TIMING)
+    tensors = random_allocs([8 << 20, 4 << 20], seed=13)
+    register_all(ctx, tensors)
+    ctx.checkpoint()
+    t = ctx.timing()
+    assert t["pack_ms"] > 0 and t["d2h_ms"] > 0
+    assert t["pack_read_bytes"] == 12 << 20
+
+
+def test_drain_direct_matches():
+    C = 4096
+    tensors = random_allocs([3 << 20, 4096 * 3 + 1], seed=14)
+    tensors[0][: 1 << 20] = 0
+    ctx = K.Context(chunk_bytes=C, flags=K.CKPT_DRAIN_DIRECT)
+    register_all(ctx, tensors)
+    img = ctx.checkpoint()
+    ref = O.checkpoint([host(t) for t in tensors], C)
+    check_full(img, ref, tensors, C)
+
+
+def test_staging_budget():
+    ctx = K.Context(staging_budget=1 << 20)
+    ctx.register(torch.empty(2 << 20, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(K.CkptError) as e:
+        ctx.checkpoint()
+    assert e.value.status == K.CKPT_E_BUDGET
