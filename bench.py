@@ -40,9 +40,14 @@ def parse():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--wpc", type=int, default=0)
     ap.add_argument("--wgs-per-cu", type=int, default=0)
+    ap.add_argument("--lane-pieces", type=int, default=0)
+    ap.add_argument("--load-hint", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed pack steps")
     ap.add_argument("--drain-steps", type=int, default=3)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="after the timed steps, one plain device copy of this many bytes "
+                         "(calibrates hardware byte counters against a known size)")
     return ap.parse_args()
 
 
@@ -118,8 +123,9 @@ def main():
     log("inputs generated on the device in %.1f s" % (time.time() - t0))
 
     S, dense_b, N, alg = algorithmic_bytes(sizes, C)
-    ctx = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN | K.CKPT_TIMING, block_threads=args.block,
-                    waves_per_chunk=args.wpc, wgs_per_cu=args.wgs_per_cu)
+    tune = dict(block_threads=args.block, waves_per_chunk=args.wpc, wgs_per_cu=args.wgs_per_cu,
+                lane_pieces=args.lane_pieces, load_hint=args.load_hint)
+    ctx = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN | K.CKPT_TIMING, **tune)
     for t in tensors:
         ctx.register(t)
     stream = torch.cuda.current_stream()
@@ -144,6 +150,14 @@ def main():
     achieved = alg / (pack_avg * 1e-3)
     log("step %.3f ms, pack kernel %.3f ms (min %.3f max %.3f): %.1f GB/s kernel, %.1f GB/s step"
         % (ms_per_step, pack_avg, min(pack_ms), max(pack_ms), achieved / 1e9, value))
+    if args.copy_probe:
+        a = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
+        b = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: %d bytes read, %d bytes written" % (args.copy_probe, args.copy_probe))
+        del a, b
 
     result = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
@@ -162,8 +176,7 @@ def main():
 
     if not args.no_extras:
         # drain: the same checkpoint with the zero-elided image drained to pinned host memory
-        dctx = K.Context(chunk_bytes=C, flags=K.CKPT_TIMING, block_threads=args.block,
-                         waves_per_chunk=args.wpc, wgs_per_cu=args.wgs_per_cu)
+        dctx = K.Context(chunk_bytes=C, flags=K.CKPT_TIMING, **tune)
         for t in tensors:
             dctx.register(t)
         dctx.checkpoint(stream=stream).close()

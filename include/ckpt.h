@@ -112,6 +112,10 @@ typedef struct ckpt_config {
     uint32_t waves_per_chunk;  /* waves that share one chunk (1, 2, 4, 8 or 16,
                                   at most block_threads / 64); 0 selects 1            */
     uint32_t wgs_per_cu;       /* persistent workgroups per compute unit; 0 = auto    */
+    uint32_t lane_pieces;      /* 16-byte pieces each lane hashes back to back per
+                                  round (1, 2 or 4); 0 selects 1                      */
+    uint32_t load_hint;        /* bulk loads/stores: 1 regular, 2 non-temporal;
+                                  0 selects 2                                         */
 } ckpt_config;
 
 /* One row of an image's allocation table (section CKPT_SEC_ALLOCS). */
@@ -136,7 +140,7 @@ typedef struct ckpt_image_meta {
     uint64_t n_dirty;           /* entries in CKPT_SEC_DIRTY_IDS (incremental)      */
     uint64_t serial;            /* unique per image within the process              */
     uint64_t base_serial;       /* incremental: serial of the base; else 0          */
-    uint64_t crc_digest;        /* 64-bit FNV-1a of the CRC section (checks a load) */
+    uint64_t crc_digest;        /* FNV-1a over the CRC section's 64-bit words       */
     uint32_t has_dense;         /* 1 when CKPT_SEC_DENSE is available               */
     uint32_t drained;           /* 1 when CKPT_SEC_DATA is valid                    */
 } ckpt_image_meta;

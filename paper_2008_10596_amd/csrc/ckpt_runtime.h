@@ -124,7 +124,7 @@ struct ckpt_image {
     uint32_t mode = CKPT_FULL;
     uint32_t C = 0;
     uint64_t N = 0, data_bytes = 0, ser_bytes = 0, n_dirty = 0;
-    uint64_t serial = 0, base_serial = 0, digest = 0;
+    uint64_t serial = 0, base_serial = 0;
     bool drained = false;
     std::vector<ckpt_alloc_rec> allocs;
     ckpt::PinnedBuf crc_buf, flags_buf, ids_buf, data;

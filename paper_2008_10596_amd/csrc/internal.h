@@ -16,16 +16,20 @@ constexpr uint32_t kPolyReflected = 0x82F63B78u;
 // applied to the register value b << 8j, so applying it to v is the XOR of the
 // four entries picked by v's bytes.  The chain step over one 4-byte word w from
 // register s is the 4-byte operator applied to (s ^ w).
+//
+// The chunk kernels read a chunk in rounds: in one round lane l of a wave
+// hashes G consecutive 16-byte pieces (G = lane_pieces), so a round covers
+// 1024 * G bytes.  The operators depend on G and on the rounds per wave:
 constexpr int kTabWords = 1024;                 // one operator, 4 x 256 words
 constexpr int kTabChain = 0;                    // m = 4 (slicing by 4)
-constexpr int kTabGap = 1 * kTabWords;          // m = 1008: between 16-byte pieces one round apart
-constexpr int kTabTree = 2 * kTabWords;         // m = 16 << k, k = 0..5: cross-lane tree
+constexpr int kTabGap = 1 * kTabWords;          // m = 1024 G - 16 G: to the lane's next round
+constexpr int kTabTree = 2 * kTabWords;         // m = 16 G << k, k = 0..5: cross-lane tree
 constexpr int kTreeLevels = 6;
-constexpr int kTabSeg = kTabTree + kTreeLevels * kTabWords;  // m = rounds_per_wave * 1024:
+constexpr int kTabSeg = kTabTree + kTreeLevels * kTabWords;  // m = rounds_per_wave * 1024 G:
                                                               // cross-wave combine
 constexpr int kTabTotalWords = kTabSeg + kTabWords;          // 9 operators, 36 KiB
 
-constexpr int kRoundBytes = 1024;   // one wave64 x 16-byte load
+constexpr int kRoundBytes = 1024;   // one wave64 x 16-byte load; a round is G of these
 constexpr int kFlagZero = 1;
 constexpr int kFlagDirty = 2;
 
@@ -49,6 +53,8 @@ struct ChunkArgs {
     const uint32_t *tables;   // kTabTotalWords words
     uint32_t C;
     uint32_t waves_per_chunk;
+    uint32_t lane_pieces;     // G
+    uint32_t nontemporal;     // 1: streaming loads/stores for the bulk data
     // allocation table (n rows; off and cb have n + 1)
     const uint64_t *src;      // pack/hash: source address of each allocation
     const uint64_t *dst;      // restore: destination address of each allocation
@@ -69,6 +75,34 @@ struct ChunkArgs {
     const uint64_t *ids;      // nullable: item i is chunk ids[i], else chunk i
     uint8_t *bad;             // per chunk, set to 1 when verification fails
     DevPlan *plan_rw;         // bad_count lives here
+};
+
+// Row-mode chunk launch (the serving loop): each row is a run of chunks of
+// one allocation of one request, with its own addresses, so one launch can
+// mix chunks of many requests, some packed and some restored.
+struct StepRow {
+    uint64_t src;        // pack: address of the row's first chunk; restore: staging base
+    uint64_t dst;        // pack: dense-image address of the first chunk; restore: its destination
+    uint64_t rem;        // bytes from the row's first chunk to the end of its allocation
+    uint64_t item0;      // first item of the row in the launch
+    uint64_t crc;        // uint32_t *: pack: CRC out; restore: stored CRC (first chunk)
+    uint64_t flags;      // uint8_t *: pack: flags out; restore: stored flags
+    uint64_t soff;       // const uint64_t *: restore: serialized offset of each chunk
+    uint64_t bad;        // uint8_t *: restore: bad marks
+    uint64_t bad_count;  // unsigned long long *: restore: the request's counter
+    uint32_t mode;       // kModePack or kModeRestore
+    uint32_t pad;
+};
+
+struct RowArgs {
+    const uint32_t *tables;
+    uint32_t C;
+    uint32_t lane_pieces;
+    uint32_t nontemporal;
+    uint32_t pad;
+    uint64_t n_items;
+    const StepRow *rows;
+    const uint32_t *map;   // item -> row
 };
 
 enum SelMode {
@@ -120,6 +154,7 @@ hipError_t launch_layout_scan(hipStream_t s, DevPlan *plan, const uint64_t *size
 hipError_t launch_chunk_map(hipStream_t s, const DevPlan *plan, const uint64_t *cb, uint32_t *map,
                             int grid);
 hipError_t launch_chunks(hipStream_t s, int mode, const ChunkArgs &a, int grid, int block);
+hipError_t launch_rows(hipStream_t s, const RowArgs &a, int grid, int block);
 hipError_t launch_select(hipStream_t s, const SelArgs &a, uint64_t max_items);
 hipError_t launch_gather(hipStream_t s, const GatherArgs &a, int grid);
 hipError_t launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t n_words, uint64_t value);
@@ -127,8 +162,9 @@ hipError_t launch_pick_u64(hipStream_t s, const uint64_t *src, const uint64_t *i
                            uint32_t m);
 
 // Host-side table generation (crc_tables.cpp): fills kTabTotalWords words for
-// a launch in which each wave owns `rounds_per_wave` consecutive 1 KiB rounds.
-void build_tables(uint32_t *out, uint32_t rounds_per_wave);
+// a launch with G pieces per lane per round and `rounds_per_wave` consecutive
+// rounds per wave.
+void build_tables(uint32_t *out, uint32_t G, uint32_t rounds_per_wave);
 // Register after feeding nbytes zero bytes (host, for tests of the tables).
 uint32_t host_shift(uint32_t reg, uint64_t nbytes);
 

@@ -8,21 +8,24 @@
 // work: no MFMA.  The CRC-32C per chunk is the library's own check.
 //
 // CRC scheme (one wave64 per chunk, or `waves_per_chunk` waves):
-//   * The chunk's bytes are read in rounds of 1 KiB: lane l of round r loads
-//     the 16-byte piece r*64 + l (one coalesced 16-byte load per lane).
-//   * A chunk of len bytes is placed at the END of a window of R whole rounds
+//   * The chunk's bytes are read in rounds of 1024 G bytes: in round r, lane l
+//     loads the G consecutive 16-byte pieces r*64G + l*G .. + G-1 (16-byte
+//     loads; across the wave each load instruction covers whole cache lines
+//     after G instructions).
+//   * A chunk of len bytes is placed at the END of a window of whole rounds
 //     (leading zero pieces, and zeros after len up to the next 16 bytes).
 //     Leading zeros leave a zero CRC register unchanged, so the window's raw
 //     CRC (zero init, no final XOR) equals that of the data followed by its
 //     s = roundup16(len) - len zero pad bytes; the pad is undone at the end by
 //     running the register backwards s bytes.
-//   * Each lane folds its pieces into one register: a slicing-by-4 chain over
-//     the piece's four words, with the register moved forward 1008 bytes (the
-//     gap to the same lane's piece in the next round) before each new piece.
+//   * Each lane folds its pieces into one register with a slicing-by-4 chain
+//     over the words of its G contiguous pieces, moving the register forward
+//     1024 G - 16 G bytes (the gap to its pieces in the next round) first.
 //   * A 6-level tree across lanes combines the registers: at level k the left
-//     partner is moved forward 16 << k bytes and XORed with the right one.
+//     partner is moved forward 16 G << k bytes and XORed with the right one;
+//     only the lanes whose result is still needed do the table lookups.
 //   * With several waves per chunk, each wave owns consecutive rounds and the
-//     per-wave results are combined by one more operator (rounds_per_wave KiB).
+//     per-wave results are combined by one more operator.
 //   * CRC-32C's initial value 0xFFFFFFFF is folded in by complementing the
 //     first min(len, 4) data bytes before hashing (and, for len < 4, XORing
 //     the part of the initial value that is still in the register), and the
@@ -187,68 +190,113 @@ struct Desc {
     uint32_t zero;  // restore: the chunk is ZERO
 };
 
-template <int MODE>
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ uint4 ld16(const void *p)
+{
+    if (NT) {
+        const u32x4 t = __builtin_nontemporal_load((const u32x4 *)p);
+        return make_uint4(t.x, t.y, t.z, t.w);
+    }
+    return *(const uint4 *)p;
+}
+
+template <bool NT>
+__device__ __forceinline__ void st16(void *p, uint4 v)
+{
+    if (NT) {
+        const u32x4 t = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(t, (u32x4 *)p);
+    } else {
+        *(uint4 *)p = v;
+    }
+}
+
+template <int MODE, bool NT>
 __device__ __forceinline__ uint4 load_piece(const Desc &d, uint32_t start)
 {
     if (MODE == kModeRestore) {
         if (d.zero)
             return make_uint4(0u, 0u, 0u, 0u);
-        return *(const uint4 *)(d.src + start);   // staging pieces are padded to 16
+        return ld16<NT>((const uint8_t *)d.src + start);   // staging pieces are padded to 16
     }
     const uint8_t *p = (const uint8_t *)d.src + start;
     if (start + 16 <= d.len)
-        return *(const uint4 *)p;
+        return ld16<NT>(p);
     return load_partial(p, d.len - start);
 }
 
-template <int MODE>
+template <int MODE, bool NT>
 __device__ __forceinline__ void store_piece(const Desc &d, uint32_t start, uint4 v)
 {
     if (MODE == kModePack) {
-        *(uint4 *)(d.dst + start) = v;            // dense image keeps the zero pad
+        st16<NT>((uint8_t *)d.dst + start, v);            // dense image keeps the zero pad
     } else if (MODE == kModeRestore) {
         uint8_t *p = (uint8_t *)d.dst + start;
         if (start + 16 <= d.len)
-            *(uint4 *)p = v;
+            st16<NT>(p, v);
         else
             store_partial(p, d.len - start, v);
     }
 }
 
+// 16-byte loads each lane keeps in flight before hashing them.
+constexpr int kLoadsInFlight = 4;
+
 // One wave's share of a chunk: rounds [r_begin, r_end) of a window of r_win
-// rounds.  Returns the raw register of those rounds in lane 0 (as a message
-// ending with the wave's last round) and ORs the data words into *orv.
-template <int MODE>
+// rounds of 1024 G bytes.  Returns the raw register of those rounds in lane 0
+// (as a message ending with the wave's last round) and ORs the data words
+// into *orv.
+template <int MODE, int G, bool NT>
 __device__ __forceinline__ uint32_t wave_rounds(const uint32_t *__restrict__ tabs, const Desc &d, int lane,
                                                 uint32_t r_begin, uint32_t r_end, uint32_t r_win,
                                                 uint32_t *orv)
 {
-    const uint32_t np = (d.len + 15) >> 4;               // data pieces
-    const uint32_t z = r_win * 64 - np;                  // leading zero pieces
-    const uint32_t r0 = max(r_begin, z >> 6);            // earlier rounds are all zero
+    constexpr int B = kLoadsInFlight / G > 0 ? kLoadsInFlight / G : 1;   // rounds per batch
+    constexpr uint32_t per_round = 64 * G;                                // pieces per round
+    const uint32_t np = (d.len + 15) >> 4;                                // data pieces
+    const uint32_t z = r_win * per_round - np;                            // leading zero pieces
+    const uint32_t r0 = max(r_begin, z / per_round);                      // earlier rounds: all zero
     uint32_t acc = 0, o = 0;
-    for (uint32_t r = r0; r < r_end; r++) {
-        const int p = (int)(r * 64 + lane) - (int)z;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (p >= 0) {
-            const uint32_t start = (uint32_t)p * 16;
-            v = load_piece<MODE>(d, start);
-            store_piece<MODE>(d, start, v);
+    for (uint32_t rb = r0; rb < r_end; rb += B) {
+        uint4 v[B][G];
+#pragma unroll
+        for (int b = 0; b < B; b++)
+#pragma unroll
+            for (int j = 0; j < G; j++) {
+                const int p = (int)((rb + b) * per_round + lane * G + j) - (int)z;
+                v[b][j] = make_uint4(0u, 0u, 0u, 0u);
+                if (rb + b < r_end && p >= 0)
+                    v[b][j] = load_piece<MODE, NT>(d, (uint32_t)p * 16);
+            }
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            const uint32_t r = rb + b;
+            if (r >= r_end)
+                break;
+            if (r > r0)
+                acc = apply_op(tabs + kTabGap, acc);
+#pragma unroll
+            for (int j = 0; j < G; j++) {
+                const int p = (int)(r * per_round + lane * G + j) - (int)z;
+                if (p >= 0)
+                    store_piece<MODE, NT>(d, (uint32_t)p * 16, v[b][j]);
+                o |= v[b][j].x | v[b][j].y | v[b][j].z | v[b][j].w;
+                if (p == 0)
+                    v[b][j].x ^= init_mask(d.len);
+                acc = apply_op(tabs + kTabChain, acc ^ v[b][j].x);
+                acc = apply_op(tabs + kTabChain, acc ^ v[b][j].y);
+                acc = apply_op(tabs + kTabChain, acc ^ v[b][j].z);
+                acc = apply_op(tabs + kTabChain, acc ^ v[b][j].w);
+            }
         }
-        o |= v.x | v.y | v.z | v.w;
-        if (p == 0)
-            v.x ^= init_mask(d.len);
-        if (r > r0)
-            acc = apply_op(tabs + kTabGap, acc);
-        acc = apply_op(tabs + kTabChain, acc ^ v.x);
-        acc = apply_op(tabs + kTabChain, acc ^ v.y);
-        acc = apply_op(tabs + kTabChain, acc ^ v.z);
-        acc = apply_op(tabs + kTabChain, acc ^ v.w);
     }
 #pragma unroll
     for (int k = 0; k < kTreeLevels; k++) {
         const uint32_t right = __shfl_down(acc, 1 << k, 64);
-        acc = apply_op(tabs + kTabTree + k * kTabWords, acc) ^ right;
+        if ((lane & ((2 << k) - 1)) == 0)
+            acc = apply_op(tabs + kTabTree + k * kTabWords, acc) ^ right;
     }
     *orv = o;
     return acc;
@@ -272,7 +320,7 @@ __device__ __forceinline__ void finish_chunk(const ChunkArgs &a, const Desc &d, 
     }
 }
 
-template <int MODE>
+template <int MODE, int G, bool NT>
 __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
 {
     __shared__ uint32_t tabs[kTabTotalWords];
@@ -288,7 +336,8 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
     const int W = a.waves_per_chunk;
     const int groups = nwaves / W, group = wave / W, wig = wave % W;
     const uint32_t C = a.C;
-    const uint32_t r_full = (C + kRoundBytes - 1) / kRoundBytes;
+    const uint32_t round_bytes = kRoundBytes * G;
+    const uint32_t r_full = (C + round_bytes - 1) / round_bytes;
     const uint32_t rw = (r_full + W - 1) / W;            // rounds per wave
     const uint32_t r_win = rw * W;
     const uint64_t M = (MODE == kModeRestore) ? a.plan->n_items : a.plan->n_chunks;
@@ -325,7 +374,7 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
             Desc d;
             if (valid) {
                 d = desc[t];
-                raw = wave_rounds<MODE>(tabs, d, lane, wig * rw, (wig + 1) * rw, r_win, &orv);
+                raw = wave_rounds<MODE, G, NT>(tabs, d, lane, wig * rw, (wig + 1) * rw, r_win, &orv);
             }
             const bool nonzero = __ballot(orv != 0) != 0;
             if (W == 1) {
@@ -347,6 +396,87 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
                     finish_chunk<MODE>(a, d, acc, nz);
                 }
                 __syncthreads();
+            }
+        }
+    }
+}
+
+// ------------------------------------------------- row mode (serving loop)
+//
+// Same per-chunk work as k_chunks (one wave per chunk), but each item's
+// addresses come from its row, and each row says whether its chunks are
+// packed or restored; the branch is uniform across a wave.
+
+struct RowDesc {
+    Desc d;
+    uint64_t crc, flags, bad, bad_count;
+    uint32_t mode, c;
+};
+
+template <int G, bool NT>
+__global__ __launch_bounds__(1024) void k_rows(RowArgs a)
+{
+    __shared__ uint32_t tabs[kTabTotalWords];
+    __shared__ RowDesc desc[kTile];
+
+    for (int i = threadIdx.x; i < kTabTotalWords; i += blockDim.x)
+        tabs[i] = a.tables[i];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const uint32_t C = a.C;
+    const uint32_t round_bytes = kRoundBytes * G;
+    const uint32_t r_win = (C + round_bytes - 1) / round_bytes;
+    const uint64_t M = a.n_items;
+
+    for (uint64_t g0 = (uint64_t)blockIdx.x * kTile; g0 < M; g0 += (uint64_t)gridDim.x * kTile) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < kTile; t += blockDim.x) {
+            const uint64_t i = g0 + t;
+            if (i < M) {
+                const StepRow &row = a.rows[a.map[i]];
+                const uint64_t c = i - row.item0;
+                const uint64_t start = c * C;
+                const uint64_t rest = row.rem - start;
+                RowDesc r;
+                r.d.g = i;
+                r.d.len = (uint32_t)(rest < C ? rest : C);
+                r.mode = row.mode;
+                r.c = (uint32_t)c;
+                r.crc = row.crc + 4 * c;
+                r.flags = row.flags + c;
+                r.bad = row.bad + c;
+                r.bad_count = row.bad_count;
+                if (row.mode == kModeRestore) {
+                    r.d.zero = *(const uint8_t *)r.flags & kFlagZero;
+                    r.d.src = r.d.zero ? 0 : row.src + ((const uint64_t *)row.soff)[c];
+                } else {
+                    r.d.zero = 0;
+                    r.d.src = row.src + start;
+                }
+                r.d.dst = row.dst + start;
+                desc[t] = r;
+            }
+        }
+        __syncthreads();
+        for (int t = wave; t < kTile && g0 + t < M; t += nwaves) {
+            const RowDesc r = desc[t];
+            uint32_t raw, orv;
+            if (r.mode == kModeRestore)
+                raw = wave_rounds<kModeRestore, G, NT>(tabs, r.d, lane, 0, r_win, r_win, &orv);
+            else
+                raw = wave_rounds<kModePack, G, NT>(tabs, r.d, lane, 0, r_win, r_win, &orv);
+            const bool nonzero = __ballot(orv != 0) != 0;
+            if (lane == 0) {
+                const uint32_t crc = finish_crc(raw, r.d.len);
+                if (r.mode == kModeRestore) {
+                    if (crc != *(const uint32_t *)r.crc) {
+                        *(uint8_t *)r.bad = 1;
+                        atomicAdd((unsigned long long *)r.bad_count, 1ull);
+                    }
+                } else {
+                    *(uint32_t *)r.crc = crc;
+                    *(uint8_t *)r.flags = (nonzero ? 0 : kFlagZero) | kFlagDirty;
+                }
             }
         }
     }
@@ -572,18 +702,55 @@ hipError_t launch_chunk_map(hipStream_t s, const DevPlan *plan, const uint64_t *
     return hipGetLastError();
 }
 
+template <int MODE, int G>
+static void launch_chunks_g(hipStream_t s, const ChunkArgs &a, int grid, int block)
+{
+    if (a.nontemporal)
+        hipLaunchKernelGGL((k_chunks<MODE, G, true>), dim3(grid), dim3(block), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_chunks<MODE, G, false>), dim3(grid), dim3(block), 0, s, a);
+}
+
+template <int MODE>
+static void launch_chunks_m(hipStream_t s, const ChunkArgs &a, int grid, int block)
+{
+    switch (a.lane_pieces) {
+    case 1: launch_chunks_g<MODE, 1>(s, a, grid, block); break;
+    case 2: launch_chunks_g<MODE, 2>(s, a, grid, block); break;
+    default: launch_chunks_g<MODE, 4>(s, a, grid, block); break;
+    }
+}
+
 hipError_t launch_chunks(hipStream_t s, int mode, const ChunkArgs &a, int grid, int block)
 {
+    if (a.lane_pieces != 1 && a.lane_pieces != 2 && a.lane_pieces != 4)
+        return hipErrorInvalidValue;
     switch (mode) {
-    case kModePack:
-        hipLaunchKernelGGL(k_chunks<kModePack>, dim3(grid), dim3(block), 0, s, a);
+    case kModePack: launch_chunks_m<kModePack>(s, a, grid, block); break;
+    case kModeHash: launch_chunks_m<kModeHash>(s, a, grid, block); break;
+    default: launch_chunks_m<kModeRestore>(s, a, grid, block); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rows(hipStream_t s, const RowArgs &a, int grid, int block)
+{
+    const bool nt = a.nontemporal;
+    switch (a.lane_pieces) {
+    case 1:
+        if (nt) hipLaunchKernelGGL((k_rows<1, true>), dim3(grid), dim3(block), 0, s, a);
+        else hipLaunchKernelGGL((k_rows<1, false>), dim3(grid), dim3(block), 0, s, a);
         break;
-    case kModeHash:
-        hipLaunchKernelGGL(k_chunks<kModeHash>, dim3(grid), dim3(block), 0, s, a);
+    case 2:
+        if (nt) hipLaunchKernelGGL((k_rows<2, true>), dim3(grid), dim3(block), 0, s, a);
+        else hipLaunchKernelGGL((k_rows<2, false>), dim3(grid), dim3(block), 0, s, a);
+        break;
+    case 4:
+        if (nt) hipLaunchKernelGGL((k_rows<4, true>), dim3(grid), dim3(block), 0, s, a);
+        else hipLaunchKernelGGL((k_rows<4, false>), dim3(grid), dim3(block), 0, s, a);
         break;
     default:
-        hipLaunchKernelGGL(k_chunks<kModeRestore>, dim3(grid), dim3(block), 0, s, a);
-        break;
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -166,13 +166,22 @@ uint64_t next_serial()
     return base | (++g_serial & 0xFFFFFFFFull);
 }
 
-uint64_t fnv1a64(const void *p, size_t n)
+// Digest of an image's CRC section: FNV-1a over little-endian 64-bit words
+// (the last word zero-padded).  Computed when asked for, not per checkpoint.
+uint64_t crc_digest(const void *p, size_t n)
 {
     const uint8_t *b = (const uint8_t *)p;
     uint64_t h = 0xcbf29ce484222325ull;
-    for (size_t i = 0; i < n; i++) {
-        h ^= b[i];
-        h *= 0x100000001b3ull;
+    size_t i = 0;
+    for (; i + 8 <= n; i += 8) {
+        uint64_t w;
+        memcpy(&w, b + i, 8);
+        h = (h ^ w) * 0x100000001b3ull;
+    }
+    if (i < n) {
+        uint64_t w = 0;
+        memcpy(&w, b + i, n - i);
+        h = (h ^ w) * 0x100000001b3ull;
     }
     return h;
 }
@@ -247,6 +256,14 @@ extern "C" int ckpt_init(const ckpt_config *cfg_in, ckpt_ctx **out)
     const uint32_t w = cfg.waves_per_chunk;
     if ((w & (w - 1)) != 0 || w > 16 || w > cfg.block_threads / 64)
         return set_error(CKPT_E_INVAL, "waves_per_chunk %u with block_threads %u", w, cfg.block_threads);
+    if (cfg.lane_pieces == 0)
+        cfg.lane_pieces = 1;    // fully coalesced 16-byte loads measured fastest
+    if (cfg.load_hint == 0)
+        cfg.load_hint = 2;      // streaming: every byte is touched once
+    if (cfg.lane_pieces != 1 && cfg.lane_pieces != 2 && cfg.lane_pieces != 4)
+        return set_error(CKPT_E_INVAL, "lane_pieces %u: 1, 2 or 4", cfg.lane_pieces);
+    if (cfg.load_hint > 2)
+        return set_error(CKPT_E_INVAL, "load_hint %u", cfg.load_hint);
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess)
@@ -276,10 +293,11 @@ int ckpt::ctx_setup(ckpt_ctx *ctx)
     HIP_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
     for (auto &ev : ctx->ev)
         HIP_TRY(hipEventCreate(&ev));
-    const uint32_t r_full = (cfg.chunk_bytes + kRoundBytes - 1) / kRoundBytes;
+    const uint32_t round_bytes = kRoundBytes * cfg.lane_pieces;
+    const uint32_t r_full = (cfg.chunk_bytes + round_bytes - 1) / round_bytes;
     const uint32_t rw = (r_full + cfg.waves_per_chunk - 1) / cfg.waves_per_chunk;
     std::vector<uint32_t> tabs(kTabTotalWords);
-    build_tables(tabs.data(), rw);
+    build_tables(tabs.data(), cfg.lane_pieces, rw);
     CKPT_TRY(ctx->d_tables.ensure(tabs.size() * 4));
     HIP_TRY(hipMemcpy(ctx->d_tables.p, tabs.data(), tabs.size() * 4, hipMemcpyHostToDevice));
     CKPT_TRY(ctx->d_plan.ensure(sizeof(DevPlan)));
@@ -475,6 +493,8 @@ ChunkArgs ckpt::chunk_args(ckpt_ctx *ctx)
     a.tables = (const uint32_t *)ctx->d_tables.p;
     a.C = ctx->cfg.chunk_bytes;
     a.waves_per_chunk = ctx->cfg.waves_per_chunk;
+    a.lane_pieces = ctx->cfg.lane_pieces;
+    a.nontemporal = ctx->cfg.load_hint == 2;
     a.size = (const uint64_t *)ctx->d_size.p;
     a.off = (const uint64_t *)ctx->d_off.p;
     a.cb = (const uint64_t *)ctx->d_cb.p;
@@ -809,7 +829,6 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
 
     for (size_t i = 0; i < nout; i++) {
         ckpt_image *img = imgs[i];
-        img->digest = fnv1a64(img->crc_buf.p, img->N * 4);
         if (keep_dense && nout == 1) {
             img->dense = dense_owned;
             img->dense_owned = true;
@@ -1042,7 +1061,7 @@ extern "C" int ckpt_image_info(const ckpt_image *img, ckpt_image_meta *out)
     out->n_dirty = img->n_dirty;
     out->serial = img->serial;
     out->base_serial = img->base_serial;
-    out->crc_digest = img->digest;
+    out->crc_digest = crc_digest(img->crc_buf.p, img->N * 4);
     out->has_dense = img->dense != nullptr;
     out->drained = img->drained;
     return CKPT_OK;
@@ -1117,7 +1136,7 @@ extern "C" int ckpt_image_serialize(const ckpt_image *img, void *buf, size_t cap
     uint32_t h32[4] = {kVersion, img->mode, img->C, 16};
     memcpy(p + 8, h32, 16);
     uint64_t h64[8] = {n, img->N, img->data_bytes, img->ser_bytes, img->n_dirty, img->serial, img->base_serial,
-                       img->digest};
+                       crc_digest(img->crc_buf.p, img->N * 4)};
     memcpy(p + 24, h64, 64);
     p += kHeaderBytes;
     if (n)
@@ -1171,7 +1190,6 @@ extern "C" int ckpt_image_load(ckpt_ctx *ctx, const void *buf, size_t bytes, ckp
     img->n_dirty = nd;
     img->serial = h64[5];
     img->base_serial = h64[6];
-    img->digest = h64[7];
     img->drained = true;
     p += kHeaderBytes;
     img->allocs.resize(n);
@@ -1203,7 +1221,7 @@ extern "C" int ckpt_image_load(ckpt_ctx *ctx, const void *buf, size_t bytes, ckp
     CKPT_TRY(img->data.ensure(std::max<uint64_t>(ser, 1)));
     if (ser)
         memcpy(img->data.p, p, ser);
-    if (fnv1a64(img->crc_buf.p, N * 4) != img->digest)
+    if (crc_digest(img->crc_buf.p, N * 4) != h64[7])
         return set_error(CKPT_E_INVAL, "CRC section digest mismatch");
     *out = guard.release();
     return CKPT_OK;

@@ -69,6 +69,16 @@ def test_launch_shapes(block, wpc, C):
     full_roundtrip(tensors, C, block_threads=block, waves_per_chunk=wpc)
 
 
+@pytest.mark.parametrize("G", [1, 2, 4])
+@pytest.mark.parametrize("hint", [1, 2])
+@pytest.mark.parametrize("C,wpc", [(4096, 1), (65536, 1), (65536, 4), (1040, 1), (262144, 2)])
+def test_lane_pieces_and_load_hints(G, hint, C, wpc):
+    log("lane_pieces=%d load_hint=%d C=%d waves/chunk=%d" % (G, hint, C, wpc))
+    sizes = [C * 3 + 5, C, C - 16, 17, 1, 4, 3 * 1024 + 7, 1 << 20]
+    tensors = random_allocs(sizes, seed=G * 100 + hint * 10 + wpc, zero=(1,))
+    full_roundtrip(tensors, C, lane_pieces=G, load_hint=hint, waves_per_chunk=wpc, block_threads=256)
+
+
 def test_zero_chunks_inside_random_allocations():
     C = 4096
     tensors = random_allocs([C * 10 + 100, C * 3], seed=5)
@@ -135,12 +145,12 @@ def test_registration_errors():
 
 # ------------------------------------------------------------ incremental
 
-@pytest.mark.parametrize("C", [4096, 65536])
-def test_incremental_matches_oracle_and_restores(C):
-    log("incremental C=%d" % C)
+@pytest.mark.parametrize("C,G", [(4096, 4), (65536, 4), (4096, 1), (65536, 2)])
+def test_incremental_matches_oracle_and_restores(C, G):
+    log("incremental C=%d G=%d" % (C, G))
     sizes = [C * 7 + 123, C * 2, 5000, C * 30, 16]
     tensors = random_allocs(sizes, seed=C + 1)
-    ctx = K.Context(chunk_bytes=C)
+    ctx = K.Context(chunk_bytes=C, lane_pieces=G)
     register_all(ctx, tensors)
     base = ctx.checkpoint()
     base_ref = O.checkpoint([host(t) for t in tensors], C)
