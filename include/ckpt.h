@@ -288,6 +288,99 @@ void ckpt_image_free(ckpt_image *img);
  */
 int ckpt_checkpoint_batch(ckpt_ctx *const *ctxs, size_t n, void *stream, ckpt_image **outs);
 
+/* ---------------------------------------------------------------- serving */
+
+/*
+ * A server takes checkpoint and restore requests as they arrive and runs them
+ * with continuous batching on one GPU.  Each request is a set of allocations
+ * like a context's live set (checkpoint) or a set of destination buffers
+ * (restore, like ckpt_restore without a delta).  Requests are admitted in
+ * arrival order while fewer than max_active are admitted and the request's
+ * device staging fits in what is left of staging_budget (checkpoint: dense
+ * image + drain buffer + per-chunk arrays, about 2x its bytes; restore: the
+ * serialized bytes + per-chunk arrays).  Every step is one kernel launch that
+ * processes up to step_bytes of each admitted request, checkpoints and
+ * restores together, so requests overlap on the device; a request that
+ * arrives during a step joins the next one.  Results are the same as a
+ * request run alone (ckpt_checkpoint of the same allocations with CKPT_FULL
+ * and no base, ids 1..n; ckpt_restore).
+ * The caller keeps source/destination memory, and a restore's image, valid
+ * and unmodified until the request completes.  All ckpt_server_* calls are
+ * thread-safe.
+ */
+enum ckpt_req_op { CKPT_REQ_CHECKPOINT = 0, CKPT_REQ_RESTORE = 1 };
+
+typedef struct ckpt_server_config {
+    int32_t device;            /* HIP device ordinal                                    */
+    uint32_t chunk_bytes;      /* C; 0 selects 4096                                     */
+    uint64_t staging_budget;   /* device bytes for admitted requests, reserved at create;
+                                  0 selects 64 GiB                                      */
+    uint64_t step_bytes;       /* bytes of each admitted request per step;
+                                  0 selects 256 MiB                                     */
+    uint32_t max_active;       /* requests admitted at once; 0 selects 16               */
+    uint32_t aux_threads;      /* workers that prepare and finish requests; 0 selects 2 */
+    uint32_t block_threads;    /* 0 selects 256                                         */
+    uint32_t lane_pieces;      /* as in ckpt_config; 0 selects 1                        */
+} ckpt_server_config;
+
+typedef struct ckpt_request {
+    uint32_t op;                /* ckpt_req_op                                          */
+    uint32_t n;                 /* allocations                                          */
+    void *const *ptrs;          /* checkpoint: sources; restore: destinations (device,
+                                   16-byte aligned); the server copies the array       */
+    const uint64_t *sizes;      /* bytes of each; restore: must equal the image's sizes */
+    const uint32_t *kinds;      /* ckpt_kind of each; NULL = all CKPT_DEVICE             */
+    const ckpt_image *image;    /* restore: a drained full image with n allocations     */
+} ckpt_request;
+
+typedef struct ckpt_result {
+    int32_t status;             /* CKPT_OK, CKPT_E_CORRUPT (restore) or an error        */
+    uint32_t op;
+    ckpt_image *image;          /* checkpoint: the new image, now owned by the caller   */
+    double latency_ms;          /* submit to completion: checkpoint = serialized image in
+                                   pinned host memory; restore = destinations written
+                                   and verified                                         */
+    double queue_ms;            /* submit to admission                                  */
+    uint64_t bytes;             /* algorithmic bytes: checkpoint live + dense; restore
+                                   live + serialized                                    */
+    uint64_t n_bad;             /* restore: chunks that failed verification             */
+} ckpt_result;
+
+typedef struct ckpt_stats {
+    uint64_t submitted, completed, failed;
+    uint64_t bytes;             /* live bytes of completed requests                     */
+    double p50_ms, p99_ms;      /* latency percentiles (nearest rank) of completed requests */
+    double mean_ms, max_ms;
+    double makespan_s;          /* first submit to last completion                      */
+    double gbps;                /* bytes / makespan, 1e9 B/s                            */
+    uint64_t steps;             /* step launches                                        */
+    uint32_t max_concurrent;    /* most requests admitted at once                       */
+    uint32_t pad;
+} ckpt_stats;
+
+/* CKPT_E_INVAL: bad config; CKPT_E_NOMEM: the staging budget could not be
+ * reserved. */
+int ckpt_server_create(const ckpt_server_config *cfg, ckpt_server **out);
+
+/* Queue a request; *ticket identifies it.  CKPT_E_INVAL / CKPT_E_MISMATCH on
+ * a malformed request (checked here), CKPT_E_BUDGET if it can never fit. */
+int ckpt_server_submit(ckpt_server *srv, const ckpt_request *req, uint64_t *ticket);
+
+/* CKPT_E_AGAIN until the request is done; then fills *out (out may be NULL to
+ * discard, which frees a checkpoint's image) and retires the ticket.
+ * CKPT_E_NOTFOUND for an unknown or retired ticket. */
+int ckpt_server_poll(ckpt_server *srv, uint64_t ticket, ckpt_result *out);
+
+/* As ckpt_server_poll, but blocks until the request is done. */
+int ckpt_server_wait(ckpt_server *srv, uint64_t ticket, ckpt_result *out);
+
+int ckpt_server_stats(const ckpt_server *srv, ckpt_stats *out);
+int ckpt_server_reset_stats(ckpt_server *srv);
+
+/* Waits for admitted requests to finish, cancels queued ones, frees the
+ * server and the results nobody retrieved.  NULL is a no-op. */
+void ckpt_server_destroy(ckpt_server *srv);
+
 /* --------------------------------------------------------------- timing */
 
 int ckpt_last_timing(const ckpt_ctx *ctx, ckpt_timing *out);

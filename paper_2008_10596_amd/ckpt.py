@@ -80,8 +80,8 @@ class ckpt_timing(ctypes.Structure):
 class ckpt_server_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("chunk_bytes", ctypes.c_uint32),
                 ("staging_budget", ctypes.c_uint64), ("step_bytes", ctypes.c_uint64),
-                ("max_active", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("block_threads", ctypes.c_uint32), ("waves_per_chunk", ctypes.c_uint32)]
+                ("max_active", ctypes.c_uint32), ("aux_threads", ctypes.c_uint32),
+                ("block_threads", ctypes.c_uint32), ("lane_pieces", ctypes.c_uint32)]
 
 
 class ckpt_request(ctypes.Structure):
@@ -353,3 +353,67 @@ def checkpoint_batch(ctxs, stream=None):
     outs = (_vp * n)()
     _check(lib().ckpt_checkpoint_batch(hs, n, _stream_handle(stream), outs), "ckpt_checkpoint_batch")
     return [Image(outs[i]) for i in range(n)]
+
+
+# ---- serving -----------------------------------------------------------------
+
+class Server:
+    """Continuous-batching server (ckpt_server_*)."""
+
+    def __init__(self, device=0, chunk_bytes=4096, staging_budget=0, step_bytes=0, max_active=0,
+                 aux_threads=0, block_threads=0, lane_pieces=0):
+        cfg = ckpt_server_config(device, chunk_bytes, staging_budget, step_bytes, max_active, aux_threads,
+                                 block_threads, lane_pieces)
+        h = _vp()
+        _check(lib().ckpt_server_create(ctypes.byref(cfg), ctypes.byref(h)), "ckpt_server_create")
+        self.handle = h.value
+
+    def close(self):
+        if self.handle:
+            lib().ckpt_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, op, bufs, image=None, sizes=None, kinds=None):
+        """bufs: tensors or device addresses; returns a ticket."""
+        n = len(bufs)
+        ptrs = (_vp * max(n, 1))(*[_ptr(b) for b in bufs])
+        if sizes is None:
+            sizes = [_nbytes(b) for b in bufs]
+        sz = (ctypes.c_uint64 * max(n, 1))(*sizes)
+        kd = (ctypes.c_uint32 * max(n, 1))(*kinds) if kinds is not None else None
+        req = ckpt_request(op, n, ptrs, sz, kd, image.handle if image else None)
+        t = ctypes.c_uint64()
+        _check(lib().ckpt_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)), "ckpt_server_submit")
+        return t.value
+
+    def _result(self, res):
+        out = {f: getattr(res, f) for f, _ in ckpt_result._fields_}
+        out["image"] = Image(res.image) if res.image else None
+        return out
+
+    def poll(self, ticket):
+        res = ckpt_result()
+        rc = lib().ckpt_server_poll(self.handle, ticket, ctypes.byref(res))
+        if rc == CKPT_E_AGAIN:
+            return None
+        _check(rc, "ckpt_server_poll")
+        return self._result(res)
+
+    def wait(self, ticket):
+        res = ckpt_result()
+        _check(lib().ckpt_server_wait(self.handle, ticket, ctypes.byref(res)), "ckpt_server_wait")
+        return self._result(res)
+
+    def stats(self):
+        st = ckpt_stats()
+        _check(lib().ckpt_server_stats(self.handle, ctypes.byref(st)), "ckpt_server_stats")
+        return {f: getattr(st, f) for f, _ in ckpt_stats._fields_ if f != "pad"}
+
+    def reset_stats(self):
+        _check(lib().ckpt_server_reset_stats(self.handle), "ckpt_server_reset_stats")

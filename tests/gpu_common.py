@@ -92,3 +92,53 @@ def check_full(img, ref, tensors, C, ids=None):
 def check_restored(dsts, srcs):
     for k, (d, s) in enumerate(zip(dsts, srcs)):
         assert torch.equal(d, s), "allocation %d differs after restore" % k
+
+
+def _hipapi():
+    import ctypes
+    global _hip
+    if _hip is None:
+        d2h(0, 0)
+    return _hip
+
+
+def managed_alloc(nbytes):
+    """hipMallocManaged (global attach); returns the address."""
+    import ctypes
+    hip = _hipapi()
+    hip.hipMallocManaged.restype = ctypes.c_int
+    hip.hipMallocManaged.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, ctypes.c_uint]
+    p = ctypes.c_void_p()
+    rc = hip.hipMallocManaged(ctypes.byref(p), max(nbytes, 1), 1)   # hipMemAttachGlobal
+    assert rc == 0, "hipMallocManaged failed: %d" % rc
+    return p.value
+
+
+def managed_free(ptr):
+    import ctypes
+    hip = _hipapi()
+    hip.hipFree.restype = ctypes.c_int
+    hip.hipFree.argtypes = [ctypes.c_void_p]
+    assert hip.hipFree(ptr) == 0
+
+
+def h2d(ptr, arr):
+    import ctypes
+    hip = _hipapi()
+    a = np.ascontiguousarray(arr, dtype=np.uint8)
+    if a.size:
+        rc = hip.hipMemcpy(ptr, a.ctypes.data, a.size, 1)   # hipMemcpyHostToDevice
+        assert rc == 0, "hipMemcpy failed: %d" % rc
+
+
+def prefetch_to_host(ptr, nbytes):
+    """Move managed pages host-side (hipCpuDeviceId); returns False when the
+    device does not support it."""
+    import ctypes
+    hip = _hipapi()
+    hip.hipMemPrefetchAsync.restype = ctypes.c_int
+    hip.hipMemPrefetchAsync.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    hip.hipDeviceSynchronize.restype = ctypes.c_int
+    rc = hip.hipMemPrefetchAsync(ptr, nbytes, -1, None)
+    hip.hipDeviceSynchronize()
+    return rc == 0

@@ -30,7 +30,9 @@ def test_header_declares_the_boundary_calls():
     names = declared_functions()
     for must in ("ckpt_init", "ckpt_destroy", "ckpt_register", "ckpt_unregister", "ckpt_checkpoint",
                  "ckpt_restore", "ckpt_image_info", "ckpt_image_view", "ckpt_image_serialize",
-                 "ckpt_image_load", "ckpt_image_free", "ckpt_checkpoint_batch", "ckpt_strerror"):
+                 "ckpt_image_load", "ckpt_image_free", "ckpt_checkpoint_batch", "ckpt_server_create",
+                 "ckpt_server_submit", "ckpt_server_poll", "ckpt_server_wait", "ckpt_server_stats",
+                 "ckpt_server_destroy", "ckpt_strerror"):
         assert must in names, must
 
 
