@@ -100,6 +100,11 @@ enum ckpt_status {
                                      read them with ckpt_last_timing             */
 #define CKPT_DRAIN_DIRECT   0x10u /* drain by kernel stores straight into pinned
                                      host memory instead of gather + copy engine */
+#define CKPT_GRAPH          0x20u /* ckpt_checkpoint: replay a captured hipGraph of
+                                     the table upload, size scan, chunk map and
+                                     pack (full checkpoints without a base)      */
+#define CKPT_NO_GRAPH       0x40u /* ckpt_checkpoint_batch: plain launches instead
+                                     of the captured graph it uses by default    */
 
 typedef struct ckpt_config {
     int32_t device;            /* HIP device ordinal                                  */
@@ -281,10 +286,14 @@ void ckpt_image_free(ckpt_image *img);
 /*
  * Checkpoint (CKPT_FULL) several contexts in one pass: every context's
  * registrations are laid out in one table and packed by one persistent
- * kernel launch.  outs[i] is the image of ctxs[i], identical to what
- * ckpt_checkpoint(ctxs[i], stream, CKPT_FULL, NULL, ...) produces.  All
- * contexts must be on one device with one chunk size (else CKPT_E_INVAL);
- * ctxs[0] provides staging and streams.
+ * kernel launch, replayed from a captured hipGraph (table upload from pinned
+ * memory, size scan, chunk map, pack; captured again only when the table
+ * outgrows the capacities of the last capture).  outs[i] is the image of
+ * ctxs[i], identical to what ckpt_checkpoint(ctxs[i], stream, CKPT_FULL,
+ * NULL, ...) produces.  All contexts must be on one device with one chunk
+ * size (else CKPT_E_INVAL); ctxs[0] provides the launch configuration,
+ * staging and streams, and may not use CKPT_KEEP_DENSE or CKPT_DRAIN_DIRECT.
+ * With CKPT_NO_DRAIN each image's DENSE view points into ctxs[0]'s staging.
  */
 int ckpt_checkpoint_batch(ckpt_ctx *const *ctxs, size_t n, void *stream, ckpt_image **outs);
 

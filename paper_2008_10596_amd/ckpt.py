@@ -29,6 +29,8 @@ CKPT_KEEP_DENSE = 0x2
 CKPT_NO_DRAIN = 0x4
 CKPT_TIMING = 0x8
 CKPT_DRAIN_DIRECT = 0x10
+CKPT_GRAPH = 0x20
+CKPT_NO_GRAPH = 0x40
 CKPT_SEC_ALLOCS, CKPT_SEC_CRC, CKPT_SEC_FLAGS, CKPT_SEC_DATA, CKPT_SEC_DIRTY_IDS, CKPT_SEC_DENSE = range(6)
 CKPT_REPORT_MAX = 64
 CKPT_REQ_CHECKPOINT, CKPT_REQ_RESTORE = 0, 1

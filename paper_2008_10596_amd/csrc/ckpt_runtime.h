@@ -94,8 +94,16 @@ struct ckpt_ctx {
     int grid_chunks = 0;   // persistent workgroups of the chunk kernels
     int grid_small = 0;    // grid of the map / gather kernels
     bool managed_prefetch = false;
-    hipStream_t side = nullptr;
+    bool ready = false;           // streams, events, tables made (ctx_ready)
+    hipStream_t side = nullptr;   // drain stream
+    hipStream_t cap = nullptr;    // graph capture stream
     hipEvent_t ev[8] = {};
+
+    // captured prologue (graph_prologue) and what it was captured for
+    hipGraphExec_t g_exec = nullptr;
+    uint64_t g_n = 0, g_N = 0, g_D = 0;
+    std::vector<void *> g_ptrs;
+    uint64_t graph_captures = 0;
 
     // the log: live registrations in id order, and their ranges by start
     std::vector<ckpt::Reg> live;
@@ -136,6 +144,8 @@ struct ckpt_image {
 namespace ckpt {
 
 int ctx_setup(ckpt_ctx *ctx);
+int ctx_ready(ckpt_ctx *ctx);
+int graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, uint64_t N, uint64_t data_bytes);
 int upload_table(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, bool dst_side, uint64_t N_host,
                  uint64_t n_items);
 int read_plan(ckpt_ctx *ctx, hipStream_t s, DevPlan *out);
@@ -143,6 +153,6 @@ int run_select(ckpt_ctx *ctx, hipStream_t s, int mode, const uint8_t *flags, con
                uint64_t max_items, uint64_t *soff, uint64_t *ids_out, uint64_t ids_cap);
 ChunkArgs chunk_args(ckpt_ctx *ctx);
 int run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_image *base, const std::vector<Row> &rows,
-                   const std::vector<size_t> &parts, std::vector<ckpt_image *> &outs);
+                   const std::vector<size_t> &parts, std::vector<ckpt_image *> &outs, bool use_graph);
 
 }  // namespace ckpt

@@ -290,7 +290,22 @@ int ckpt::ctx_setup(ckpt_ctx *ctx)
     int managed = 0;
     if (hipDeviceGetAttribute(&managed, hipDeviceAttributeConcurrentManagedAccess, cfg.device) == hipSuccess)
         ctx->managed_prefetch = managed != 0;
+    const int per_cu = cfg.wgs_per_cu ? (int)cfg.wgs_per_cu
+                                      : std::max(1, std::min(4, 32 / (int)(cfg.block_threads / 64)));
+    ctx->grid_chunks = ctx->cu_count * per_cu;
+    ctx->grid_small = ctx->cu_count * 4;
+    return CKPT_OK;
+}
+
+// Streams, events and tables are made on first use, so that contexts that
+// only hold registrations (members of a batch) stay cheap.
+int ckpt::ctx_ready(ckpt_ctx *ctx)
+{
+    if (ctx->ready)
+        return CKPT_OK;
+    const ckpt_config &cfg = ctx->cfg;
     HIP_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
     for (auto &ev : ctx->ev)
         HIP_TRY(hipEventCreate(&ev));
     const uint32_t round_bytes = kRoundBytes * cfg.lane_pieces;
@@ -302,10 +317,7 @@ int ckpt::ctx_setup(ckpt_ctx *ctx)
     HIP_TRY(hipMemcpy(ctx->d_tables.p, tabs.data(), tabs.size() * 4, hipMemcpyHostToDevice));
     CKPT_TRY(ctx->d_plan.ensure(sizeof(DevPlan)));
     CKPT_TRY(ctx->h_plan.ensure(sizeof(DevPlan)));
-    const int per_cu = cfg.wgs_per_cu ? (int)cfg.wgs_per_cu
-                                      : std::max(1, std::min(4, 32 / (int)(cfg.block_threads / 64)));
-    ctx->grid_chunks = ctx->cu_count * per_cu;
-    ctx->grid_small = ctx->cu_count * 4;
+    ctx->ready = true;
     return CKPT_OK;
 }
 
@@ -315,10 +327,13 @@ extern "C" void ckpt_destroy(ckpt_ctx *ctx)
         return;
     {
         DeviceGuard g(ctx->cfg.device);
-        if (ctx->side) {
-            (void)hipStreamSynchronize(ctx->side);
-            (void)hipStreamDestroy(ctx->side);
-        }
+        if (ctx->g_exec)
+            (void)hipGraphExecDestroy(ctx->g_exec);
+        for (hipStream_t st : {ctx->side, ctx->cap})
+            if (st) {
+                (void)hipStreamSynchronize(st);
+                (void)hipStreamDestroy(st);
+            }
         for (auto &ev : ctx->ev)
             if (ev)
                 (void)hipEventDestroy(ev);
@@ -551,6 +566,100 @@ bool same_table(const ckpt_image *a, const ckpt_image *b)
 
 }  // namespace
 
+// ------------------------------------------------------------ graph prologue
+//
+// The device part of a full checkpoint without a base -- table upload from
+// pinned memory, size scan, chunk map, pack -- captured once in a hipGraph and
+// replayed.  Every kernel reads its counts from the device plan, so one graph
+// serves any table that fits the capacities it was captured with; the host
+// only rewrites the pinned upload buffer.  A changed buffer address (a
+// buffer grown by another call) forces a new capture.
+
+namespace {
+uint64_t grow(uint64_t x, uint64_t floor) { return std::max<uint64_t>(floor, x + x / 4); }
+}  // namespace
+
+int ckpt::graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, uint64_t N,
+                         uint64_t data_bytes)
+{
+    const uint64_t n = rows.size();
+    std::vector<void *> ptrs = {ctx->d_plan.p, ctx->d_addr.p, ctx->d_size.p, ctx->d_off.p, ctx->d_cb.p,
+                                ctx->d_map.p,  ctx->d_crc.p,  ctx->d_flags.p, ctx->d_dense.p, ctx->h_up.p};
+    const bool fits = ctx->g_exec && n <= ctx->g_n && N <= ctx->g_N && data_bytes <= ctx->g_D &&
+                      ptrs == ctx->g_ptrs;
+    if (!fits) {
+        if (ctx->g_exec) {
+            (void)hipGraphExecDestroy(ctx->g_exec);
+            ctx->g_exec = nullptr;
+        }
+        const uint64_t nc = grow(n, 64), Nc = grow(N, 1024), Dc = grow(data_bytes, 1 << 20);
+        CKPT_TRY(ctx->d_addr.ensure(nc * 8));
+        CKPT_TRY(ctx->d_size.ensure(nc * 8));
+        CKPT_TRY(ctx->d_off.ensure((nc + 1) * 8));
+        CKPT_TRY(ctx->d_cb.ensure((nc + 1) * 8));
+        CKPT_TRY(ctx->d_map.ensure(Nc * 4));
+        CKPT_TRY(ctx->d_crc.ensure(Nc * 4));
+        CKPT_TRY(ctx->d_flags.ensure(Nc));
+        CKPT_TRY(ctx->d_dense.ensure(Dc));
+        CKPT_TRY(ctx->h_up.ensure(sizeof(DevPlan) + 16 * nc));
+        uint8_t *up = (uint8_t *)ctx->h_up.p;
+        hipStream_t c = ctx->cap;
+        HIP_TRY(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
+        hipGraph_t graph = nullptr;
+        auto capture = [&]() -> int {
+            HIP_TRY(hipMemcpyAsync(ctx->d_plan.p, up, sizeof(DevPlan), hipMemcpyHostToDevice, c));
+            HIP_TRY(hipMemcpyAsync(ctx->d_addr.p, up + sizeof(DevPlan), 8 * nc, hipMemcpyHostToDevice, c));
+            HIP_TRY(hipMemcpyAsync(ctx->d_size.p, up + sizeof(DevPlan) + 8 * nc, 8 * nc, hipMemcpyHostToDevice, c));
+            HIP_TRY(launch_layout_scan(c, (DevPlan *)ctx->d_plan.p, (const uint64_t *)ctx->d_size.p,
+                                       ctx->cfg.chunk_bytes, (uint64_t *)ctx->d_off.p, (uint64_t *)ctx->d_cb.p));
+            HIP_TRY(launch_chunk_map(c, (const DevPlan *)ctx->d_plan.p, (const uint64_t *)ctx->d_cb.p,
+                                     (uint32_t *)ctx->d_map.p, ctx->grid_small));
+            ChunkArgs a = chunk_args(ctx);
+            a.src = (const uint64_t *)ctx->d_addr.p;
+            a.dense = (uint8_t *)ctx->d_dense.p;
+            a.crc = (uint32_t *)ctx->d_crc.p;
+            a.flags = (uint8_t *)ctx->d_flags.p;
+            HIP_TRY(launch_chunks(c, kModePack, a, ctx->grid_chunks, ctx->cfg.block_threads));
+            return CKPT_OK;
+        };
+        const int rc = capture();
+        const hipError_t e = hipStreamEndCapture(c, &graph);
+        if (rc != CKPT_OK) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess)
+            return hip_fail(e, "hipStreamEndCapture", __LINE__);
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess)
+            return hip_fail(ei, "hipGraphInstantiate", __LINE__);
+        ctx->g_exec = exec;
+        ctx->g_n = nc;
+        ctx->g_N = Nc;
+        ctx->g_D = Dc;
+        ctx->g_ptrs = {ctx->d_plan.p, ctx->d_addr.p, ctx->d_size.p, ctx->d_off.p, ctx->d_cb.p,
+                       ctx->d_map.p,  ctx->d_crc.p,  ctx->d_flags.p, ctx->d_dense.p, ctx->h_up.p};
+        ctx->graph_captures++;
+    }
+    // New descriptor contents in the captured upload buffer.  The previous
+    // call on this context has finished with it (every call synchronizes).
+    uint8_t *up = (uint8_t *)ctx->h_up.p;
+    auto *plan = (DevPlan *)up;
+    memset(plan, 0, sizeof(DevPlan));
+    plan->n_allocs = n;
+    auto *addr = (uint64_t *)(up + sizeof(DevPlan));
+    auto *size = addr + ctx->g_n;
+    for (uint64_t k = 0; k < n; k++) {
+        addr[k] = rows[k].ptr;
+        size[k] = rows[k].size;
+    }
+    HIP_TRY(hipGraphLaunch(ctx->g_exec, s));
+    return CKPT_OK;
+}
+
 // ---------------------------------------------------------------- checkpoint
 //
 // rows: the table to drain, possibly the concatenation of several contexts'
@@ -558,7 +667,7 @@ bool same_table(const ckpt_image *a, const ckpt_image *b)
 // number of outputs).  Each output's image is the one its rows alone give.
 
 int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_image *base, const std::vector<Row> &rows,
-                         const std::vector<size_t> &parts, std::vector<ckpt_image *> &outs)
+                         const std::vector<size_t> &parts, std::vector<ckpt_image *> &outs, bool use_graph)
 {
     const ckpt_config &cfg = ctx->cfg;
     const uint32_t C = cfg.chunk_bytes;
@@ -591,8 +700,23 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
             if (r.kind == CKPT_MANAGED && r.size)
                 HIP_TRY(hipMemPrefetchAsync((const void *)r.ptr, r.size, cfg.device, s));
 
+    const bool graph = use_graph && !incremental && !base && !keep_dense;
+    uint8_t *dense = nullptr;
+    void *dense_owned = nullptr;
+    struct DenseGuard {
+        void *p;
+        ~DenseGuard() { if (p) (void)hipFree(p); }
+    } dense_guard{nullptr};
     if (timing)
         HIP_TRY(hipEventRecord(ctx->ev[0], s));
+    if (graph) {
+        CKPT_TRY(graph_prologue(ctx, s, rows, N, L.data_bytes));
+        dense = (uint8_t *)ctx->d_dense.p;
+        if (timing) {
+            HIP_TRY(hipEventRecord(ctx->ev[1], s));
+            HIP_TRY(hipEventRecord(ctx->ev[2], s));
+        }
+    } else {
     CKPT_TRY(upload_table(ctx, s, rows, false, N, 0));
     CKPT_TRY(ctx->d_crc.ensure(std::max<uint64_t>(N, 1) * 4));
     CKPT_TRY(ctx->d_flags.ensure(std::max<uint64_t>(N, 1)));
@@ -612,13 +736,12 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     }
 
     // Dense image: the context's staging, or a buffer the image will own.
-    uint8_t *dense = nullptr;
-    void *dense_owned = nullptr;
     if (!incremental) {
         if (keep_dense) {
             hipError_t e = hipMalloc(&dense_owned, std::max<uint64_t>(L.data_bytes, 16));
             if (e != hipSuccess)
                 return hip_fail(e, "hipMalloc(dense image)", __LINE__);
+            dense_guard.p = dense_owned;
             dense = (uint8_t *)dense_owned;
         } else {
             int rc = ctx->d_dense.ensure(std::max<uint64_t>(L.data_bytes, 16));
@@ -627,11 +750,6 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
             dense = (uint8_t *)ctx->d_dense.p;
         }
     }
-    struct DenseGuard {
-        void *p;
-        ~DenseGuard() { if (p) (void)hipFree(p); }
-    } dense_guard{dense_owned};
-
     if (timing)
         HIP_TRY(hipEventRecord(ctx->ev[1], s));
     ChunkArgs a = chunk_args(ctx);
@@ -644,6 +762,9 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
         HIP_TRY(launch_chunks(s, incremental ? kModeHash : kModePack, a, ctx->grid_chunks, cfg.block_threads));
     if (timing)
         HIP_TRY(hipEventRecord(ctx->ev[2], s));
+    }
+    ChunkArgs a = chunk_args(ctx);
+    a.flags = (uint8_t *)ctx->d_flags.p;
     T.pack_read_bytes = 0;
     for (const Row &r : rows)
         T.pack_read_bytes += r.size;
@@ -833,8 +954,9 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
             img->dense = dense_owned;
             img->dense_owned = true;
             dense_guard.p = nullptr;
-        } else if (no_drain && nout == 1) {
-            img->dense = dense;   // the context's staging: valid until its next checkpoint
+        } else if (no_drain) {
+            // the context's staging: valid until its next checkpoint
+            img->dense = dense + L.off[part_row[i]];
         }
         outs[i] = img;
     }
@@ -853,10 +975,12 @@ extern "C" int ckpt_checkpoint(ckpt_ctx *ctx, void *stream, int mode, const ckpt
     DeviceGuard g(ctx->cfg.device);
     if (!g.ok())
         return set_error(CKPT_E_HIP, "cannot select device %d", ctx->cfg.device);
+    CKPT_TRY(ctx_ready(ctx));
     std::vector<Row> rows(ctx->live.begin(), ctx->live.end());
     std::vector<size_t> parts{0};
     std::vector<ckpt_image *> outs(1, nullptr);
-    int rc = run_checkpoint(ctx, (hipStream_t)stream, mode, base, rows, parts, outs);
+    int rc = run_checkpoint(ctx, (hipStream_t)stream, mode, base, rows, parts, outs,
+                            (ctx->cfg.flags & CKPT_GRAPH) != 0);
     if (rc == CKPT_OK)
         *out = outs[0];
     return rc;
@@ -873,9 +997,10 @@ extern "C" int ckpt_checkpoint_batch(ckpt_ctx *const *ctxs, size_t n, void *stre
         if (ctxs[i]->cfg.device != c0->cfg.device || ctxs[i]->cfg.chunk_bytes != c0->cfg.chunk_bytes)
             return set_error(CKPT_E_INVAL, "batched contexts differ in device or chunk size");
     }
-    if (c0->cfg.flags & (CKPT_KEEP_DENSE | CKPT_NO_DRAIN | CKPT_DRAIN_DIRECT))
+    if (c0->cfg.flags & (CKPT_KEEP_DENSE | CKPT_DRAIN_DIRECT))
         return set_error(CKPT_E_INVAL, "batches keep no dense image and drain through staging");
     DeviceGuard g(c0->cfg.device);
+    CKPT_TRY(ctx_ready(c0));
     std::vector<Row> rows;
     std::vector<size_t> parts(n);
     for (size_t i = 0; i < n; i++) {
@@ -883,7 +1008,8 @@ extern "C" int ckpt_checkpoint_batch(ckpt_ctx *const *ctxs, size_t n, void *stre
         rows.insert(rows.end(), ctxs[i]->live.begin(), ctxs[i]->live.end());
     }
     std::vector<ckpt_image *> o(n, nullptr);
-    int rc = run_checkpoint(c0, (hipStream_t)stream, CKPT_FULL, nullptr, rows, parts, o);
+    int rc = run_checkpoint(c0, (hipStream_t)stream, CKPT_FULL, nullptr, rows, parts, o,
+                            !(c0->cfg.flags & CKPT_NO_GRAPH));
     if (rc == CKPT_OK)
         for (size_t i = 0; i < n; i++)
             outs[i] = o[i];
@@ -937,6 +1063,7 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
         return set_error(CKPT_E_BUDGET, "restore staging %llu B exceeds the budget", (unsigned long long)stage);
 
     DeviceGuard g(ctx->cfg.device);
+    CKPT_TRY(ctx_ready(ctx));
     hipStream_t s = (hipStream_t)stream;
     const bool timing = ctx->cfg.flags & CKPT_TIMING;
     ckpt_timing &T = ctx->timing;

@@ -404,3 +404,85 @@ def test_staging_budget():
     with pytest.raises(K.CkptError) as e:
         ctx.checkpoint()
     assert e.value.status == K.CKPT_E_BUDGET
+
+
+# ------------------------------------------------------------------- graphs
+
+def test_graph_replays_match_eager_and_oracle():
+    """CKPT_GRAPH: the captured prologue is replayed with new tables; every
+    replay equals the eager path and the oracle, with eager torch work and
+    synchronizations between replays and recaptures when the table grows."""
+    C = 4096
+    ctx_g = K.Context(chunk_bytes=C, flags=K.CKPT_GRAPH)
+    ctx_e = K.Context(chunk_bytes=C)
+    tensors = random_allocs([100000, 4096 * 5 + 3, 77], seed=41)
+    for t in tensors:
+        ctx_g.register(t)
+        ctx_e.register(t)
+    for rep in range(6):
+        log("graph replay %d: %d allocations" % (rep, len(tensors)))
+        synth.fill_random_(tensors[rep % len(tensors)], 1000 + rep)      # eager work between replays
+        if rep == 2:
+            tensors[0][:8192] = 0
+        torch.cuda.synchronize()
+        g = ctx_g.checkpoint()
+        e = ctx_e.checkpoint()
+        ref = O.checkpoint([host(t) for t in tensors], C)
+        check_full(g, ref, tensors, C)
+        for key in ("crc", "flags", "data", "allocs"):
+            assert np.array_equal(getattr(g, key), getattr(e, key)), (rep, key)
+        if rep in (1, 3):                  # grow the table past the captured capacity
+            extra = random_allocs([300000 * (rep + 1)] * 40, seed=500 + rep)
+            for t in extra:
+                ctx_g.register(t)
+                ctx_e.register(t)
+            tensors += extra
+        if rep == 4:
+            ctx_g.unregister(tensors[1])
+            ctx_e.unregister(tensors[1])
+            tensors.pop(1)
+
+
+def test_batch_replays_and_no_graph_agree():
+    C = 4096
+    rng = np.random.default_rng(44)
+    leader_g = K.Context(chunk_bytes=C)
+    leader_n = K.Context(chunk_bytes=C, flags=K.CKPT_NO_GRAPH)
+    for rep in range(3):
+        members, allocs = [], []
+        for i in range(5 + 4 * rep):
+            sizes = [int(x) for x in rng.integers(1, 200000, int(rng.integers(1, 5)))]
+            t = random_allocs(sizes, seed=rep * 100 + i)
+            c = K.Context(chunk_bytes=C)
+            for x in t:
+                c.register(x)
+            members.append(c)
+            allocs.append(t)
+        a = K.checkpoint_batch([leader_g] + members)
+        b = K.checkpoint_batch([leader_n] + members)
+        assert a[0].info()["n_allocs"] == 0
+        for img_a, img_b, t in zip(a[1:], b[1:], allocs):
+            ref = O.checkpoint([host(x) for x in t], C)
+            check_full(img_a, ref, t, C)
+            for key in ("crc", "flags", "data", "allocs"):
+                assert np.array_equal(getattr(img_a, key), getattr(img_b, key)), key
+
+
+def test_batch_no_drain_dense_views():
+    C = 4096
+    leader = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN)
+    members, allocs = [], []
+    for i in range(4):
+        t = random_allocs([5000 * (i + 1), 4096, 17], seed=70 + i)
+        c = K.Context(chunk_bytes=C)
+        for x in t:
+            c.register(x)
+        members.append(c)
+        allocs.append(t)
+    imgs = K.checkpoint_batch([leader] + members)
+    for img, t in zip(imgs[1:], allocs):
+        ref = O.checkpoint([host(x) for x in t], C)
+        assert img.info()["serialized_bytes"] == 0 and img.info()["drained"] == 0
+        assert np.array_equal(img.crc, ref["crc"]) and np.array_equal(img.flags, ref["flags"])
+        p, nb = img.dense_ptr
+        assert np.array_equal(d2h(p, nb), ref["dense"])
