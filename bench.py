@@ -1,15 +1,19 @@
 """Benchmark of the checkpoint drain/refill path on one MI355X.
 
-Default workload: full checkpoint at scale -- 4096 allocations, log-uniform
-4 KiB - 64 MiB scaled to 16 GiB, half of them all-zero, C = 4 KiB.  One step is
-one ckpt_checkpoint of the whole live set with the image kept in HBM
-(CKPT_NO_DRAIN): descriptor upload, size scan, chunk map, the fused pack +
-CRC-32C + ZERO/DIRTY kernel, and the CRC/flag arrays copied to the host.
-`value` = algorithmic bytes of a step (every live byte read, the dense image
-written, 5 bytes of CRC + flags per chunk) / wall time per step.
+Headline workload (the JSON `value`): full checkpoint at scale -- 4096
+allocations, log-uniform 4 KiB - 64 MiB scaled to 16 GiB, half of them all-zero,
+C = 4 KiB.  One step is one ckpt_checkpoint of the whole live set with the
+image kept in HBM (CKPT_NO_DRAIN): descriptor upload, size scan, chunk map,
+the fused pack + CRC-32C + ZERO/DIRTY kernel, and the CRC/flag arrays copied to
+the host.  `value` = algorithmic bytes of a step (every live byte read, the
+dense image written, 5 bytes of CRC + flags per chunk) / wall time per step.
 
-Printed as one JSON line.  Further phases of the same run (drain to pinned
-host memory, restore) are reported inside the line.
+The same run then measures, and reports inside the one JSON line: the drain
+of that image to pinned host memory and the restore from it; the incremental
+workload (hash-only pass + delta); the batched workload (512 contexts, plain
+per-allocation and per-context forms against one graph-replayed batched
+launch, plus the autotuner sweep); and the serving workload (Poisson arrivals,
+p50/p99 latency), each on seeded synthetic inputs generated on the device.
 """
 import argparse
 import json
@@ -42,13 +46,42 @@ def parse():
     ap.add_argument("--wgs-per-cu", type=int, default=0)
     ap.add_argument("--lane-pieces", type=int, default=0)
     ap.add_argument("--load-hint", type=int, default=0)
+    ap.add_argument("--table-mode", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed pack steps")
     ap.add_argument("--drain-steps", type=int, default=3)
+    ap.add_argument("--only", default="", help="comma list of extra sections to run "
+                    "(drain,incremental,batched,serving); default: all")
+    ap.add_argument("--serving-requests", type=int, default=60, help="measured requests per rate")
+    ap.add_argument("--serving-rates", default="10,50,150", help="arrival rates (req/s)")
+    ap.add_argument("--serving-shapes", type=int, default=24)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after the timed steps, one plain device copy of this many bytes "
                          "(calibrates hardware byte counters against a known size)")
     return ap.parse_args()
+
+
+def tune_kw(args):
+    """Launch-configuration overrides from the command line (0 = library default)."""
+    return dict(block_threads=args.block, waves_per_chunk=args.wpc, wgs_per_cu=args.wgs_per_cu,
+                lane_pieces=args.lane_pieces, load_hint=args.load_hint, table_mode=args.table_mode)
+
+
+def profiled_traffic(summary_glob="k_chunks_pack_*.md"):
+    """HBM bytes per launch of the pack kernel from the committed rocprofv3
+    counter summary (profiles/), if it was taken from the current kernel
+    source; None otherwise."""
+    import glob
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_2008_10596_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in glob.glob(os.path.join(ROOT, "profiles", summary_glob)):
+        m = re.search(r"machine-readable: traffic_bytes=(\d+) alg_bytes=(\d+) avg_ms=([\d.]+) "
+                      r"kernels_sha256=(\w+)", open(path).read())
+        if m and m.group(4) == sha:
+            return int(m.group(1)), int(m.group(2)), os.path.basename(path)
+    return None
 
 
 def algorithmic_bytes(sizes, C):
@@ -98,6 +131,335 @@ def cpu_baseline(tensors, sizes, C, budget_bytes=2 << 30, reps=3):
             "seconds": round(t, 3)}
 
 
+def bench_incremental(K, synth, torch, stream, args, reps=3):
+    """Incremental workload: 2048 allocations, 8 GiB random; 5% of the 64 KiB
+    cells rewritten; increment = hash-only pass, dirty scan, gather from the
+    allocations, drain of the delta."""
+    w = synth.incremental()
+    sizes = [int(x) for x in w["sizes"]]
+    S = sum(sizes)
+    tensors = synth.make_device_allocs(sizes, w["zero"], workload=3)
+    chunks = (65536, 4096)
+    bases, ctxs = {}, {}
+    for C in chunks:
+        nd = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN, **tune_kw(args))
+        for t in tensors:
+            nd.register(t)
+        bases[C] = nd.checkpoint(stream=stream)
+        ctxs[C] = nd
+    # the mutation: each picked grid cell rewritten with new random bytes
+    g = w["grid"]
+    for i, (k, c) in enumerate(zip(w["mut_alloc"], w["mut_cell"])):
+        t = tensors[int(k)]
+        lo = int(c) * g
+        synth.fill_random_(t[lo:min(t.numel(), lo + g)], synth.alloc_seed(3, int(k), phase=1) + i)
+    torch.cuda.synchronize()
+    out = {"workload": "incremental: %d allocations, %.2f GiB random, %d of the 64 KiB cells rewritten"
+                       % (len(sizes), S / 2**30, len(w["mut_alloc"]))}
+    for C in chunks:
+        ctx = K.Context(chunk_bytes=C, flags=K.CKPT_TIMING, **tune_kw(args))
+        for t in tensors:
+            ctx.register(t)
+        tm, info = [], None
+        for r in range(reps + 1):
+            d = ctx.checkpoint(stream=stream, mode=K.CKPT_INCREMENTAL, base=bases[C])
+            info = d.info()
+            if r:
+                tm.append(ctx.timing())
+            d.close()
+        med = lambda key: statistics.median(x[key] for x in tm)  # noqa: E731
+        hash_ms = med("pack_ms")
+        res = {"chunk_bytes": C, "chunks": info["n_chunks"], "dirty_chunks": info["n_dirty"],
+               "delta_bytes": info["serialized_bytes"],
+               "hash_ms": round(hash_ms, 4), "hash_gbps": round(S / (hash_ms * 1e-3) / 1e9, 1),
+               "hash_frac_hbm": round(S / (hash_ms * 1e-3) / HBM_PEAK, 4),
+               "select_gather_ms": round(med("select_ms") + med("gather_ms"), 4),
+               "d2h_ms": round(med("d2h_ms"), 3), "total_ms": round(med("total_ms"), 3),
+               "delta_vs_full_drain": round(info["serialized_bytes"] / S, 4)}
+        log("incremental C=%d: %s" % (C, res))
+        out["c%d" % C] = res
+        ctx.close()
+    for C in chunks:
+        bases[C].close()
+        ctxs[C].close()
+    del tensors
+    return out
+
+
+def bench_batched(K, synth, torch, stream, args, reps=3):
+    """Batched workload: 512 contexts of 1-64 allocations (log-uniform 1 MiB -
+    256 MiB per context), random bytes with 20% of the 256 KiB cells zero.
+    Plain forms (one checkpoint call per allocation, or per context) against
+    one batched call that replays a captured graph; then the autotuner."""
+    from paper_2008_10596_amd import autotune
+    spec = synth.batched()
+    C = 4096
+    sets, tensors = [], []
+    k = 0
+    for ci, cs in enumerate(spec):
+        allocs = []
+        for j, sz in enumerate(cs["sizes"]):
+            t = torch.empty(int(sz), dtype=torch.uint8, device="cuda")
+            synth.fill_random_(t, synth.alloc_seed(4, k))
+            reg = cs["region"]
+            for cell in cs["zero_cells"][j]:
+                t[int(cell) * reg:int(cell) * reg + reg] = 0
+            allocs.append(t)
+            tensors.append(t)
+            k += 1
+        sets.append(allocs)
+    torch.cuda.synchronize()
+    sizes = [t.numel() for t in tensors]
+    S, dense_b, N, alg = algorithmic_bytes(sizes, C)
+    log("batched: %d contexts, %d allocations, %.2f GiB" % (len(sets), len(tensors), S / 2**30))
+    members = []
+    for allocs in sets:
+        c = K.Context(chunk_bytes=C)
+        for t in allocs:
+            c.register(t)
+        members.append(c)
+    out = {"workload": "batched: %d contexts, %d allocations, %.2f GiB, 20%% zero 256 KiB cells, C=%d"
+                       % (len(sets), len(tensors), S / 2**30, C), "algorithmic_bytes": alg}
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        w = []
+        for _ in range(n):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            w.append((time.perf_counter() - t0) * 1e3)
+        return statistics.median(w)
+
+    # batched, image kept in HBM: one graph replay
+    leader = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN | K.CKPT_TIMING, **tune_kw(args))
+    dev_ms = []
+
+    def batched_once():
+        imgs = K.checkpoint_batch([leader] + members, stream=stream)
+        dev_ms.append(leader.timing()["pack_ms"])
+        for im in imgs:
+            im.close()
+    wall = timed(batched_once, reps)
+    out["batched_pack"] = {"wall_ms": round(wall, 3), "gbps_wall": round(alg / (wall * 1e-3) / 1e9, 1),
+                           "device_ms": round(statistics.median(dev_ms[1:]), 3),
+                           "gbps_device": round(alg / (statistics.median(dev_ms[1:]) * 1e-3) / 1e9, 1),
+                           "launches": 1}
+    log("batched pack: %s" % out["batched_pack"])
+    # plain, image kept in HBM: one checkpoint call per allocation
+    pctx = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN | K.CKPT_TIMING, **tune_kw(args))
+
+    def plain_alloc():
+        for t in tensors:
+            pctx.register(t)
+            pctx.checkpoint(stream=stream).close()
+            pctx.unregister(t)
+    wall_pa = timed(plain_alloc, 1)
+    out["plain_per_allocation_pack"] = {"wall_ms": round(wall_pa, 1),
+                                        "gbps_wall": round(alg / (wall_pa * 1e-3) / 1e9, 1),
+                                        "launches": 3 * len(tensors)}
+    log("plain per allocation: %s" % out["plain_per_allocation_pack"])
+
+    def plain_ctx():
+        for allocs in sets:
+            for t in allocs:
+                pctx.register(t)
+            pctx.checkpoint(stream=stream).close()
+            for t in allocs:
+                pctx.unregister(t)
+    wall_pc = timed(plain_ctx, 1)
+    out["plain_per_context_pack"] = {"wall_ms": round(wall_pc, 1),
+                                     "gbps_wall": round(alg / (wall_pc * 1e-3) / 1e9, 1),
+                                     "launches": 3 * len(sets)}
+    log("plain per context: %s" % out["plain_per_context_pack"])
+    out["batched_speedup_vs_plain_per_allocation"] = round(wall_pa / wall, 2)
+    out["batched_speedup_vs_plain_per_context"] = round(wall_pc / wall, 2)
+    # with the drain to pinned host memory
+    dleader = K.Context(chunk_bytes=C, flags=K.CKPT_TIMING, **tune_kw(args))
+
+    def batched_drain():
+        for im in K.checkpoint_batch([dleader] + members, stream=stream):
+            im.close()
+    wall_d = timed(batched_drain, 1)
+    out["batched_with_drain"] = {"wall_ms": round(wall_d, 1)}
+    log("batched with drain: %s" % out["batched_with_drain"])
+    leader.close()
+    pctx.close()
+    dleader.close()
+    for c in members:
+        c.close()
+    # autotuner sweep on the same contexts
+    alloc_sets = [[(t.data_ptr(), t.numel()) for t in allocs] for allocs in sets]
+    tuned = autotune.tune(alloc_sets, chunks=(4096, 16384, 65536, 262144), waves=(1, 2, 4),
+                          blocks=(256, 1024), reps=2, stream=stream)
+    out["autotune"] = {"best": tuned["best"], "trials": len(tuned["trials"]),
+                       "worst_gbps": min(t["gbps"] for t in tuned["trials"]),
+                       "c4096_best_gbps": max(t["gbps"] for t in tuned["trials"] if t["chunk_bytes"] == 4096)}
+    log("autotune: %s" % out["autotune"])
+    del tensors, sets
+    return out
+
+
+def bench_serving(K, synth, torch, args):
+    """Serving workload (reduced sweep): Poisson arrivals of checkpoint (70%)
+    and restore (30%) requests over a pool of request shapes of 1-256
+    allocations each (log-uniform 16 MiB - 4 GiB per request, 25% of the
+    allocations hipMallocManaged with 30% of their 2 MiB granules moved
+    host-side before each checkpoint when the device supports it).  Latency is
+    submit to completion; p50/p99 per arrival rate."""
+    import ctypes
+
+    import numpy as np
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMallocManaged.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, ctypes.c_uint]
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    hip.hipMemPrefetchAsync.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    hip.hipFree.argtypes = [ctypes.c_void_p]
+    rng = synth.rng_for(5)
+    GiB, MiB = synth.GiB, synth.MiB
+    shapes, managed_ptrs, total = [], [], 0
+    for i in range(args.serving_shapes):
+        n = int(rng.integers(1, 257))
+        tot = int(synth.log_uniform(rng, 1, 16 * MiB, 4 * GiB)[0])
+        if total + tot > 40 * GiB:
+            tot = max(16 * MiB, 40 * GiB - total)
+        sizes = synth.split_total(rng, tot, n) // 16 * 16
+        sizes[sizes == 0] = 16
+        kinds = (rng.random(n) < 0.25).astype(int)
+        bufs, ptrs, keep = [], [], []
+        for j, (sz, kd) in enumerate(zip(sizes, kinds)):
+            src = torch.empty(int(sz), dtype=torch.uint8, device="cuda")
+            synth.fill_random_(src, synth.alloc_seed(5, i * 1000 + j))
+            if kd:
+                p = ctypes.c_void_p()
+                assert hip.hipMallocManaged(ctypes.byref(p), int(sz), 1) == 0
+                torch.cuda.synchronize()
+                assert hip.hipMemcpy(p.value, src.data_ptr(), int(sz), 3) == 0   # device to device
+                ptrs.append(p.value)
+                managed_ptrs.append(p.value)
+            else:
+                ptrs.append(src.data_ptr())
+                keep.append(src)
+        dst = [torch.empty(int(sz), dtype=torch.uint8, device="cuda") for sz in sizes]
+        shapes.append({"ptrs": ptrs, "sizes": [int(x) for x in sizes], "kinds": [int(x) for x in kinds],
+                       "keep": keep, "dst": dst, "image": None, "bytes": int(sum(sizes))})
+        total += int(sum(sizes))
+    torch.cuda.synchronize()
+    prefetch_ok = None
+
+    def move_host(sh):
+        nonlocal prefetch_ok
+        for p, sz, kd in zip(sh["ptrs"], sh["sizes"], sh["kinds"]):
+            if not kd or prefetch_ok is False:
+                continue
+            gran = 2 * MiB
+            cells = max(1, (sz + gran - 1) // gran)
+            pick = rng.random(cells) < 0.3
+            for c in np.flatnonzero(pick):
+                rc = hip.hipMemPrefetchAsync(p + int(c) * gran, min(gran, sz - int(c) * gran), -1, None)
+                if prefetch_ok is None:
+                    prefetch_ok = rc == 0
+                if rc != 0:
+                    return
+    srv = K.Server(chunk_bytes=4096, staging_budget=64 * GiB, step_bytes=256 * MiB, max_active=16)
+    out = {"workload": "serving (reduced): %d request shapes, %.1f GiB of allocations, 1-256 allocations "
+                       "per request, 25%% managed" % (len(shapes), total / GiB),
+           "rates": {}}
+    # An image stays open while a restore that reads it is in flight, and a
+    # shape's managed pages are only moved host-side while none of its
+    # requests is in flight.
+    refs = {}          # id(image) -> [image, in-flight restores, retired]
+    inflight = [0] * len(shapes)
+
+    def retire(img):
+        e = refs.get(id(img))
+        if e is None:
+            img.close()
+            return
+        e[2] = True
+        if e[1] == 0:
+            img.close()
+            del refs[id(img)]
+
+    def done(tk_entry, r):
+        _, si, img_used = tk_entry
+        inflight[si] -= 1
+        if img_used is not None:
+            e = refs[id(img_used)]
+            e[1] -= 1
+            if e[2] and e[1] == 0:
+                img_used.close()
+                del refs[id(img_used)]
+        if r["image"] is not None:
+            sh = shapes[si]
+            old = sh["image"]
+            sh["image"] = r["image"]
+            refs[id(r["image"])] = [r["image"], 0, False]
+            if old is not None:
+                retire(old)
+
+    def run_rate(lam, n_total, warm):
+        arr = np.cumsum(rng.exponential(1.0 / lam, n_total))
+        ops = rng.random(n_total) < 0.7
+        which = rng.integers(0, len(shapes), n_total)
+        tickets = []
+        t0 = time.perf_counter()
+        for i in range(n_total):
+            if i == warm:
+                # measure from here: the warm-up requests finish first
+                for entry in tickets:
+                    done(entry, srv.wait(entry[0]))
+                tickets = []
+                srv.reset_stats()
+                t0 = time.perf_counter() - arr[i]
+            delay = arr[i] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            si = int(which[i])
+            sh = shapes[si]
+            img = sh["image"]
+            if ops[i] or img is None:
+                if inflight[si] == 0:
+                    move_host(sh)
+                tk = srv.submit(K.CKPT_REQ_CHECKPOINT, sh["ptrs"], sizes=sh["sizes"], kinds=sh["kinds"])
+                tickets.append((tk, si, None))
+            else:
+                refs[id(img)][1] += 1
+                tk = srv.submit(K.CKPT_REQ_RESTORE, sh["dst"], image=img)
+                tickets.append((tk, si, img))
+            inflight[si] += 1
+            still = []
+            for entry in tickets:
+                r = srv.poll(entry[0])
+                if r is None:
+                    still.append(entry)
+                else:
+                    done(entry, r)
+            tickets = still
+        for entry in tickets:
+            done(entry, srv.wait(entry[0]))
+        return srv.stats()
+
+    for lam in [float(x) for x in args.serving_rates.split(",")]:
+        st = run_rate(lam, args.serving_requests + 10, 10)
+        res = {"p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
+               "mean_ms": round(st["mean_ms"], 2), "completed": st["completed"], "failed": st["failed"],
+               "gbps": round(st["gbps"], 2), "makespan_s": round(st["makespan_s"], 3),
+               "steps": st["steps"], "max_concurrent": st["max_concurrent"]}
+        out["rates"]["%g" % lam] = res
+        log("serving rate %g/s: %s" % (lam, res))
+    out["managed_prefetch_to_host"] = bool(prefetch_ok)
+    srv.close()
+    for e in list(refs.values()):
+        e[0].close()
+    refs.clear()
+    torch.cuda.synchronize()
+    for p in managed_ptrs:
+        hip.hipFree(p)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -123,9 +485,11 @@ def main():
     log("inputs generated on the device in %.1f s" % (time.time() - t0))
 
     S, dense_b, N, alg = algorithmic_bytes(sizes, C)
-    tune = dict(block_threads=args.block, waves_per_chunk=args.wpc, wgs_per_cu=args.wgs_per_cu,
-                lane_pieces=args.lane_pieces, load_hint=args.load_hint)
-    ctx = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN | K.CKPT_TIMING, **tune)
+    tune = tune_kw(args)
+    # The workload's only writer is the current stream, so the checkpoint is
+    # ordered after that stream (CKPT_STREAM_ORDERED); the device-wide drain of
+    # the default mode is timed separately below.
+    ctx = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN | K.CKPT_TIMING | K.CKPT_STREAM_ORDERED, **tune)
     for t in tensors:
         ctx.register(t)
     stream = torch.cuda.current_stream()
@@ -150,6 +514,20 @@ def main():
     achieved = alg / (pack_avg * 1e-3)
     log("step %.3f ms, pack kernel %.3f ms (min %.3f max %.3f): %.1f GB/s kernel, %.1f GB/s step"
         % (ms_per_step, pack_avg, min(pack_ms), max(pack_ms), achieved / 1e9, value))
+    # the same steps with the default device-wide drain first
+    wctx = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN, **tune)
+    for t in tensors:
+        wctx.register(t)
+    wctx.checkpoint(stream=stream).close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nwide = max(3, args.steps // 4)
+    for i in range(nwide):
+        wctx.checkpoint(stream=stream).close()
+    torch.cuda.synchronize()
+    ms_wide = (time.perf_counter() - t0) * 1e3 / nwide
+    wctx.close()
+    log("device-wide drain mode: %.3f ms per step" % ms_wide)
     if args.copy_probe:
         a = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
         b = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
@@ -165,16 +543,24 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
         "data": "synthetic (seeded, generated on the device)",
         "config": {"workload": "full checkpoint at scale: %d allocations, log-uniform 4 KiB-64 MiB "
-                               "scaled to %.2f GiB, half all-zero, C=%d B, image kept in HBM"
-                               % (len(sizes), S / 2**30, C),
-                   "live_bytes": S, "chunks": N, "chunk_bytes": C},
+                               "scaled to %.2f GiB, half all-zero, C=%d B, image kept in HBM, "
+                               "stream-ordered" % (len(sizes), S / 2**30, C),
+                   "live_bytes": S, "chunks": N, "chunk_bytes": C,
+                   "ms_per_step_device_wide_drain": round(ms_wide, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved / 1e9, 2), "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4), "traffic": None,
                      "kernel": "k_chunks<pack>", "algorithmic_bytes_per_launch": alg,
                      "kernel_ms": round(pack_avg, 4)},
     }
+    prof = profiled_traffic()
+    if prof is not None and prof[1] == alg:
+        result["roofline"]["traffic"] = prof[0]
+        result["roofline"]["traffic_source"] = "profiles/" + prof[2]
 
-    if not args.no_extras:
+    sections = set(args.only.split(",")) if args.only else {"drain", "incremental", "batched", "serving"}
+    if args.no_extras:
+        sections = set()
+    if "drain" in sections:
         # drain: the same checkpoint with the zero-elided image drained to pinned host memory
         dctx = K.Context(chunk_bytes=C, flags=K.CKPT_TIMING, **tune)
         for t in tensors:
@@ -241,6 +627,19 @@ def main():
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(tensors, sizes, C)
         log("cpu baseline: %s" % result["cpu_baseline"])
+    ctx.close()
+    del tensors
+    torch.cuda.empty_cache()
+
+    if "incremental" in sections:
+        result["incremental"] = bench_incremental(K, synth, torch, stream, args)
+        torch.cuda.empty_cache()
+    if "batched" in sections:
+        result["batched"] = bench_batched(K, synth, torch, stream, args)
+        torch.cuda.empty_cache()
+    if "serving" in sections:
+        result["serving"] = bench_serving(K, synth, torch, args)
+        torch.cuda.empty_cache()
     print(json.dumps(result), flush=True)
 
 

@@ -113,7 +113,7 @@ typedef struct ckpt_config {
                                   (dense image + compact drain buffer); 0 = no cap    */
     uint32_t flags;            /* CKPT_* flags above                                  */
     uint32_t block_threads;    /* threads per workgroup for the chunk kernels:
-                                  64, 128, 256, 512 or 1024; 0 selects 256            */
+                                  64, 128, 256, 512 or 1024; 0: see table_mode        */
     uint32_t waves_per_chunk;  /* waves that share one chunk (1, 2, 4, 8 or 16,
                                   at most block_threads / 64); 0 selects 1            */
     uint32_t wgs_per_cu;       /* persistent workgroups per compute unit; 0 = auto    */
@@ -121,6 +121,13 @@ typedef struct ckpt_config {
                                   round (1, 2 or 4); 0 selects 1                      */
     uint32_t load_hint;        /* bulk loads/stores: 1 regular, 2 non-temporal;
                                   0 selects 2                                         */
+    uint32_t table_mode;       /* CRC operator tables in LDS: 1 compact (36 KiB, up
+                                  to 4 workgroups per CU), 2 replicated per lane
+                                  (124 KiB, bank-conflict-free lookups, one workgroup
+                                  per CU; lane_pieces 1 only); 0 selects 2 when
+                                  lane_pieces is 1, else 1.  block_threads 0 then
+                                  selects 1024 (replicated) or 256 (compact)          */
+    uint32_t pad;
 } ckpt_config;
 
 /* One row of an image's allocation table (section CKPT_SEC_ALLOCS). */
@@ -175,7 +182,9 @@ typedef struct ckpt_verify_report {
 typedef struct ckpt_timing {
     float order_ms;       /* device-wide drain of prior work                     */
     float layout_ms;      /* descriptor upload + size scan + chunk map            */
-    float pack_ms;        /* fused pack + CRC + flags (or hash-only) kernel        */
+    float pack_ms;        /* fused pack + CRC + flags (or hash-only) kernel; with a
+                             replayed graph, the whole graph (upload, scan, map,
+                             pack) and layout_ms is 0                              */
     float select_ms;      /* flag scan / compaction                                */
     float gather_ms;      /* gather of selected chunks                             */
     float d2h_ms;         /* device-to-host copy of data + metadata                */
@@ -329,7 +338,8 @@ typedef struct ckpt_server_config {
     uint32_t max_active;       /* requests admitted at once; 0 selects 16               */
     uint32_t aux_threads;      /* workers that prepare and finish requests; 0 selects 2 */
     uint32_t block_threads;    /* 0 selects 256                                         */
-    uint32_t lane_pieces;      /* as in ckpt_config; 0 selects 1                        */
+    uint32_t lane_pieces;      /* as in ckpt_config; 0 selects 1 (then replicated
+                                  tables and 1024-thread workgroups)                    */
 } ckpt_server_config;
 
 typedef struct ckpt_request {

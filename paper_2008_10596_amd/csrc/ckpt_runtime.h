@@ -98,6 +98,8 @@ struct ckpt_ctx {
     hipStream_t side = nullptr;   // drain stream
     hipStream_t cap = nullptr;    // graph capture stream
     hipEvent_t ev[8] = {};
+    hipEvent_t meta_ev = nullptr;   // last asynchronous CRC/flag copy to the host
+    bool meta_pending = false;
 
     // captured prologue (graph_prologue) and what it was captured for
     hipGraphExec_t g_exec = nullptr;
@@ -138,12 +140,15 @@ struct ckpt_image {
     ckpt::PinnedBuf crc_buf, flags_buf, ids_buf, data;
     void *dense = nullptr;
     bool dense_owned = false;
+    hipEvent_t meta_ready = nullptr;   // host CRC/flags valid once this completes
     ~ckpt_image();
 };
 
 namespace ckpt {
 
 int ctx_setup(ckpt_ctx *ctx);
+void image_wait(const ckpt_image *img);
+int order_after_meta(ckpt_ctx *ctx, hipStream_t s);
 int ctx_ready(ckpt_ctx *ctx);
 int graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, uint64_t N, uint64_t data_bytes);
 int upload_table(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, bool dst_side, uint64_t N_host,

@@ -5,6 +5,8 @@
 // found by running each single-bit register value through m zero bytes, bit by
 // bit; a table entry for byte position j and byte value b is the XOR of the
 // columns of b's set bits, shifted to position j.
+#include <vector>
+
 #include "internal.h"
 
 namespace ckpt {
@@ -43,6 +45,27 @@ void build_tables(uint32_t *out, uint32_t G, uint32_t rounds_per_wave)
     for (int k = 0; k < kTreeLevels; k++)
         build_operator(out + kTabTree + k * kTabWords, (16ull * G) << k);
     build_operator(out + kTabSeg, (uint64_t)rounds_per_wave * round);
+}
+
+void build_tables_replicated(uint32_t *out, uint32_t rounds_per_wave)
+{
+    std::vector<uint32_t> op(kTabWords);
+    // gap (1008 bytes), 8 copies per entry
+    build_operator(op.data(), kRoundBytes - 16);
+    for (int j = 0; j < 4; j++)
+        for (int b = 0; b < 256; b++)
+            for (int r = 0; r < 8; r++)
+                out[((j << 13) | (b << 5) | (r << 2)) / 4] = op[j * 256 + b];
+    // 2-byte chain step: entry t, b = the register value b << 8t moved 2 bytes
+    build_operator(op.data(), 2);
+    for (int t = 0; t < 2; t++)
+        for (int b = 0; b < 256; b++)
+            for (int r = 0; r < 32; r++)
+                out[(kRepChainOff + ((b << 8) | (t << 7) | (r << 2))) / 4] = op[t * 256 + b];
+    uint32_t *tail = out + kRepTreeOff / 4;
+    for (int k = 0; k < kTreeLevels; k++)
+        build_operator(tail + k * kTabWords, 16ull << k);
+    build_operator(tail + kTreeLevels * kTabWords, (uint64_t)rounds_per_wave * kRoundBytes);
 }
 
 }  // namespace ckpt

@@ -30,6 +30,20 @@ constexpr int kTabSeg = kTabTree + kTreeLevels * kTabWords;  // m = rounds_per_w
 constexpr int kTabTotalWords = kTabSeg + kTabWords;          // 9 operators, 36 KiB
 
 constexpr int kRoundBytes = 1024;   // one wave64 x 16-byte load; a round is G of these
+
+// Replicated table set (one 1024-thread workgroup per CU): random-index LDS
+// lookups are bank-conflict free when each lane reads its own copy of an
+// entry.  Byte offsets in LDS:
+//   gap operator, 8 copies:   (j << 13) | (b << 5) | ((lane & 7) << 2)     [0, 32 KiB)
+//   2-byte chain step, 32 copies, both byte positions interleaved:
+//                             32768 + ((b << 8) | (t << 7) | ((lane & 31) << 2))  [32, 96 KiB)
+//   tree and cross-wave operators as in the compact set, from 96 KiB.
+constexpr int kRepGapBytes = 32768;
+constexpr int kRepChainOff = 32768;
+constexpr int kRepTreeOff = 98304;                         // bytes
+constexpr int kRepWords = (kRepTreeOff / 4) + (kTreeLevels + 1) * kTabWords;   // 124 KiB
+constexpr int kTableCompact = 1;
+constexpr int kTableReplicated = 2;
 constexpr int kFlagZero = 1;
 constexpr int kFlagDirty = 2;
 
@@ -55,6 +69,8 @@ struct ChunkArgs {
     uint32_t waves_per_chunk;
     uint32_t lane_pieces;     // G
     uint32_t nontemporal;     // 1: streaming loads/stores for the bulk data
+    uint32_t table_mode;      // kTableCompact or kTableReplicated
+    uint32_t table_words;     // words of the table set to stage in LDS
     // allocation table (n rows; off and cb have n + 1)
     const uint64_t *src;      // pack/hash: source address of each allocation
     const uint64_t *dst;      // restore: destination address of each allocation
@@ -99,7 +115,7 @@ struct RowArgs {
     uint32_t C;
     uint32_t lane_pieces;
     uint32_t nontemporal;
-    uint32_t pad;
+    uint32_t table_mode;
     uint64_t n_items;
     const StepRow *rows;
     const uint32_t *map;   // item -> row
@@ -165,6 +181,8 @@ hipError_t launch_pick_u64(hipStream_t s, const uint64_t *src, const uint64_t *i
 // a launch with G pieces per lane per round and `rounds_per_wave` consecutive
 // rounds per wave.
 void build_tables(uint32_t *out, uint32_t G, uint32_t rounds_per_wave);
+// The replicated set (kRepWords words; G = 1 only).
+void build_tables_replicated(uint32_t *out, uint32_t rounds_per_wave);
 // Register after feeding nbytes zero bytes (host, for tests of the tables).
 uint32_t host_shift(uint32_t reg, uint64_t nbytes);
 

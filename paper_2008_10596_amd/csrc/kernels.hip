@@ -44,6 +44,60 @@ __device__ __forceinline__ uint32_t apply_op(const uint32_t *__restrict__ t, uin
            t[768 + (v >> 24)];
 }
 
+// The operator tables as staged in LDS, compact (one copy, 36 KiB) or
+// replicated (per-lane copies of the chain and gap operators, 124 KiB).
+template <bool REP>
+struct Tabs {
+    const uint32_t *t;   // LDS base
+    uint32_t lb;         // replicated: (lane & 31) << 2, this lane's chain copy
+    uint32_t lb8;        // replicated: (lane & 7) << 2, this lane's gap copy
+
+    __device__ __forceinline__ uint32_t lds(uint32_t byte_off) const
+    {
+        return *(const uint32_t *)((const uint8_t *)t + byte_off);
+    }
+    // register after the 4-byte word w: slicing by 4 (compact) or two 2-byte
+    // steps (replicated)
+    __device__ __forceinline__ uint32_t chain(uint32_t s, uint32_t w) const
+    {
+        if (!REP)
+            return apply_op(t + kTabChain, s ^ w);
+        uint32_t y = s ^ w;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const uint32_t a0 = __builtin_amdgcn_perm(y, lb, 0x0c0c0400u);   // (y.byte0 << 8) | lb
+            const uint32_t a1 = (y & 0xff00u) | lb;
+            y = lds(kRepChainOff + a0) ^ lds(kRepChainOff + 128 + a1) ^ (y >> 16);
+        }
+        return y;
+    }
+    __device__ __forceinline__ uint32_t gap(uint32_t v) const
+    {
+        if (!REP)
+            return apply_op(t + kTabGap, v);
+        return lds(((v & 0xffu) << 5) | lb8) ^ lds(8192 + ((((v >> 8) & 0xffu) << 5) | lb8)) ^
+               lds(16384 + ((((v >> 16) & 0xffu) << 5) | lb8)) ^ lds(24576 + (((v >> 24) << 5) | lb8));
+    }
+    __device__ __forceinline__ uint32_t tree(int k, uint32_t v) const
+    {
+        return apply_op(t + (REP ? kRepTreeOff / 4 : kTabTree) + k * kTabWords, v);
+    }
+    __device__ __forceinline__ uint32_t seg(uint32_t v) const
+    {
+        return apply_op(t + (REP ? kRepTreeOff / 4 + kTreeLevels * kTabWords : kTabSeg), v);
+    }
+};
+
+template <bool REP>
+__device__ __forceinline__ Tabs<REP> make_tabs(const uint32_t *lds_tabs, int lane)
+{
+    Tabs<REP> T;
+    T.t = lds_tabs;
+    T.lb = (uint32_t)(lane & 31) << 2;
+    T.lb8 = (uint32_t)(lane & 7) << 2;
+    return T;
+}
+
 __device__ __forceinline__ uint64_t round_up16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
 
 // Wave64 inclusive scan of a u64 (Hillis-Steele with shuffles).
@@ -248,8 +302,8 @@ constexpr int kLoadsInFlight = 4;
 // rounds of 1024 G bytes.  Returns the raw register of those rounds in lane 0
 // (as a message ending with the wave's last round) and ORs the data words
 // into *orv.
-template <int MODE, int G, bool NT>
-__device__ __forceinline__ uint32_t wave_rounds(const uint32_t *__restrict__ tabs, const Desc &d, int lane,
+template <int MODE, int G, bool NT, bool REP>
+__device__ __forceinline__ uint32_t wave_rounds(const Tabs<REP> &T, const Desc &d, int lane,
                                                 uint32_t r_begin, uint32_t r_end, uint32_t r_win,
                                                 uint32_t *orv)
 {
@@ -276,7 +330,7 @@ __device__ __forceinline__ uint32_t wave_rounds(const uint32_t *__restrict__ tab
             if (r >= r_end)
                 break;
             if (r > r0)
-                acc = apply_op(tabs + kTabGap, acc);
+                acc = T.gap(acc);
 #pragma unroll
             for (int j = 0; j < G; j++) {
                 const int p = (int)(r * per_round + lane * G + j) - (int)z;
@@ -285,10 +339,10 @@ __device__ __forceinline__ uint32_t wave_rounds(const uint32_t *__restrict__ tab
                 o |= v[b][j].x | v[b][j].y | v[b][j].z | v[b][j].w;
                 if (p == 0)
                     v[b][j].x ^= init_mask(d.len);
-                acc = apply_op(tabs + kTabChain, acc ^ v[b][j].x);
-                acc = apply_op(tabs + kTabChain, acc ^ v[b][j].y);
-                acc = apply_op(tabs + kTabChain, acc ^ v[b][j].z);
-                acc = apply_op(tabs + kTabChain, acc ^ v[b][j].w);
+                acc = T.chain(acc, v[b][j].x);
+                acc = T.chain(acc, v[b][j].y);
+                acc = T.chain(acc, v[b][j].z);
+                acc = T.chain(acc, v[b][j].w);
             }
         }
     }
@@ -296,7 +350,7 @@ __device__ __forceinline__ uint32_t wave_rounds(const uint32_t *__restrict__ tab
     for (int k = 0; k < kTreeLevels; k++) {
         const uint32_t right = __shfl_down(acc, 1 << k, 64);
         if ((lane & ((2 << k) - 1)) == 0)
-            acc = apply_op(tabs + kTabTree + k * kTabWords, acc) ^ right;
+            acc = T.tree(k, acc) ^ right;
     }
     *orv = o;
     return acc;
@@ -320,18 +374,20 @@ __device__ __forceinline__ void finish_chunk(const ChunkArgs &a, const Desc &d, 
     }
 }
 
-template <int MODE, int G, bool NT>
+template <int MODE, int G, bool NT, bool REP>
 __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
 {
-    __shared__ uint32_t tabs[kTabTotalWords];
+    __shared__ uint32_t tabs[REP ? kRepWords : kTabTotalWords];
     __shared__ Desc desc[kTile];
     __shared__ uint32_t s_part[16];
     __shared__ uint32_t s_nz[16];
 
-    for (int i = threadIdx.x; i < kTabTotalWords; i += blockDim.x)
+    constexpr int kWords = REP ? kRepWords : kTabTotalWords;
+    for (int i = threadIdx.x; i < kWords; i += blockDim.x)
         tabs[i] = a.tables[i];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const Tabs<REP> T = make_tabs<REP>(tabs, lane);
     const int nwaves = blockDim.x >> 6;
     const int W = a.waves_per_chunk;
     const int groups = nwaves / W, group = wave / W, wig = wave % W;
@@ -374,7 +430,7 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
             Desc d;
             if (valid) {
                 d = desc[t];
-                raw = wave_rounds<MODE, G, NT>(tabs, d, lane, wig * rw, (wig + 1) * rw, r_win, &orv);
+                raw = wave_rounds<MODE, G, NT, REP>(T, d, lane, wig * rw, (wig + 1) * rw, r_win, &orv);
             }
             const bool nonzero = __ballot(orv != 0) != 0;
             if (W == 1) {
@@ -390,7 +446,7 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
                     uint32_t acc = s_part[wave];
                     bool nz = s_nz[wave];
                     for (int w = 1; w < W; w++) {
-                        acc = apply_op(tabs + kTabSeg, acc) ^ s_part[wave + w];
+                        acc = T.seg(acc) ^ s_part[wave + w];
                         nz = nz || s_nz[wave + w];
                     }
                     finish_chunk<MODE>(a, d, acc, nz);
@@ -413,15 +469,17 @@ struct RowDesc {
     uint32_t mode, c;
 };
 
-template <int G, bool NT>
+template <int G, bool NT, bool REP>
 __global__ __launch_bounds__(1024) void k_rows(RowArgs a)
 {
-    __shared__ uint32_t tabs[kTabTotalWords];
+    __shared__ uint32_t tabs[REP ? kRepWords : kTabTotalWords];
     __shared__ RowDesc desc[kTile];
 
-    for (int i = threadIdx.x; i < kTabTotalWords; i += blockDim.x)
+    constexpr int kWords = REP ? kRepWords : kTabTotalWords;
+    for (int i = threadIdx.x; i < kWords; i += blockDim.x)
         tabs[i] = a.tables[i];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const Tabs<REP> T = make_tabs<REP>(tabs, lane);
     const int nwaves = blockDim.x >> 6;
     const uint32_t C = a.C;
     const uint32_t round_bytes = kRoundBytes * G;
@@ -462,9 +520,9 @@ __global__ __launch_bounds__(1024) void k_rows(RowArgs a)
             const RowDesc r = desc[t];
             uint32_t raw, orv;
             if (r.mode == kModeRestore)
-                raw = wave_rounds<kModeRestore, G, NT>(tabs, r.d, lane, 0, r_win, r_win, &orv);
+                raw = wave_rounds<kModeRestore, G, NT, REP>(T, r.d, lane, 0, r_win, r_win, &orv);
             else
-                raw = wave_rounds<kModePack, G, NT>(tabs, r.d, lane, 0, r_win, r_win, &orv);
+                raw = wave_rounds<kModePack, G, NT, REP>(T, r.d, lane, 0, r_win, r_win, &orv);
             const bool nonzero = __ballot(orv != 0) != 0;
             if (lane == 0) {
                 const uint32_t crc = finish_crc(raw, r.d.len);
@@ -706,14 +764,21 @@ template <int MODE, int G>
 static void launch_chunks_g(hipStream_t s, const ChunkArgs &a, int grid, int block)
 {
     if (a.nontemporal)
-        hipLaunchKernelGGL((k_chunks<MODE, G, true>), dim3(grid), dim3(block), 0, s, a);
+        hipLaunchKernelGGL((k_chunks<MODE, G, true, false>), dim3(grid), dim3(block), 0, s, a);
     else
-        hipLaunchKernelGGL((k_chunks<MODE, G, false>), dim3(grid), dim3(block), 0, s, a);
+        hipLaunchKernelGGL((k_chunks<MODE, G, false, false>), dim3(grid), dim3(block), 0, s, a);
 }
 
 template <int MODE>
 static void launch_chunks_m(hipStream_t s, const ChunkArgs &a, int grid, int block)
 {
+    if (a.table_mode == kTableReplicated) {     // G = 1 only
+        if (a.nontemporal)
+            hipLaunchKernelGGL((k_chunks<MODE, 1, true, true>), dim3(grid), dim3(block), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_chunks<MODE, 1, false, true>), dim3(grid), dim3(block), 0, s, a);
+        return;
+    }
     switch (a.lane_pieces) {
     case 1: launch_chunks_g<MODE, 1>(s, a, grid, block); break;
     case 2: launch_chunks_g<MODE, 2>(s, a, grid, block); break;
@@ -724,6 +789,9 @@ static void launch_chunks_m(hipStream_t s, const ChunkArgs &a, int grid, int blo
 hipError_t launch_chunks(hipStream_t s, int mode, const ChunkArgs &a, int grid, int block)
 {
     if (a.lane_pieces != 1 && a.lane_pieces != 2 && a.lane_pieces != 4)
+        return hipErrorInvalidValue;
+    if (a.table_mode == kTableReplicated ? (a.lane_pieces != 1 || a.table_words != kRepWords)
+                                         : a.table_words != kTabTotalWords)
         return hipErrorInvalidValue;
     switch (mode) {
     case kModePack: launch_chunks_m<kModePack>(s, a, grid, block); break;
@@ -736,18 +804,25 @@ hipError_t launch_chunks(hipStream_t s, int mode, const ChunkArgs &a, int grid, 
 hipError_t launch_rows(hipStream_t s, const RowArgs &a, int grid, int block)
 {
     const bool nt = a.nontemporal;
+    if (a.table_mode == kTableReplicated) {
+        if (a.lane_pieces != 1)
+            return hipErrorInvalidValue;
+        if (nt) hipLaunchKernelGGL((k_rows<1, true, true>), dim3(grid), dim3(block), 0, s, a);
+        else hipLaunchKernelGGL((k_rows<1, false, true>), dim3(grid), dim3(block), 0, s, a);
+        return hipGetLastError();
+    }
     switch (a.lane_pieces) {
     case 1:
-        if (nt) hipLaunchKernelGGL((k_rows<1, true>), dim3(grid), dim3(block), 0, s, a);
-        else hipLaunchKernelGGL((k_rows<1, false>), dim3(grid), dim3(block), 0, s, a);
+        if (nt) hipLaunchKernelGGL((k_rows<1, true, false>), dim3(grid), dim3(block), 0, s, a);
+        else hipLaunchKernelGGL((k_rows<1, false, false>), dim3(grid), dim3(block), 0, s, a);
         break;
     case 2:
-        if (nt) hipLaunchKernelGGL((k_rows<2, true>), dim3(grid), dim3(block), 0, s, a);
-        else hipLaunchKernelGGL((k_rows<2, false>), dim3(grid), dim3(block), 0, s, a);
+        if (nt) hipLaunchKernelGGL((k_rows<2, true, false>), dim3(grid), dim3(block), 0, s, a);
+        else hipLaunchKernelGGL((k_rows<2, false, false>), dim3(grid), dim3(block), 0, s, a);
         break;
     case 4:
-        if (nt) hipLaunchKernelGGL((k_rows<4, true>), dim3(grid), dim3(block), 0, s, a);
-        else hipLaunchKernelGGL((k_rows<4, false>), dim3(grid), dim3(block), 0, s, a);
+        if (nt) hipLaunchKernelGGL((k_rows<4, true, false>), dim3(grid), dim3(block), 0, s, a);
+        else hipLaunchKernelGGL((k_rows<4, false, false>), dim3(grid), dim3(block), 0, s, a);
         break;
     default:
         return hipErrorInvalidValue;

@@ -212,8 +212,29 @@ void PinnedBuf::release()
 
 // -------------------------------------------------------------- the image
 
+void ckpt::image_wait(const ckpt_image *img)
+{
+    if (img && img->meta_ready) {
+        (void)hipEventSynchronize(img->meta_ready);
+        (void)hipEventDestroy(img->meta_ready);
+        const_cast<ckpt_image *>(img)->meta_ready = nullptr;
+    }
+}
+
+// New work on s that reuses the context's device arrays waits for the last
+// asynchronous metadata copy out of them.
+int ckpt::order_after_meta(ckpt_ctx *ctx, hipStream_t s)
+{
+    if (ctx->meta_pending) {
+        HIP_TRY(hipStreamWaitEvent(s, ctx->meta_ev, 0));
+        ctx->meta_pending = false;
+    }
+    return CKPT_OK;
+}
+
 ckpt_image::~ckpt_image()
 {
+    ckpt::image_wait(this);   // pinned buffers go back to the pool only when no copy targets them
     if (dense_owned && dense) {
         int prev = 0;
         (void)hipGetDevice(&prev);
@@ -246,8 +267,16 @@ extern "C" int ckpt_init(const ckpt_config *cfg_in, ckpt_ctx **out)
         cfg.chunk_bytes = 4096;
     if (cfg.chunk_bytes % 16 != 0 || cfg.chunk_bytes > (1u << 30))
         return set_error(CKPT_E_INVAL, "chunk_bytes %u: not a multiple of 16 in [16, 2^30]", cfg.chunk_bytes);
+    if (cfg.lane_pieces == 0)
+        cfg.lane_pieces = 1;    // fully coalesced 16-byte loads measured fastest
+    if (cfg.table_mode == 0)
+        cfg.table_mode = cfg.lane_pieces == 1 ? kTableReplicated : kTableCompact;
+    if (cfg.table_mode != kTableCompact && cfg.table_mode != kTableReplicated)
+        return set_error(CKPT_E_INVAL, "table_mode %u", cfg.table_mode);
+    if (cfg.table_mode == kTableReplicated && cfg.lane_pieces != 1)
+        return set_error(CKPT_E_INVAL, "replicated tables need lane_pieces 1");
     if (cfg.block_threads == 0)
-        cfg.block_threads = 256;
+        cfg.block_threads = cfg.table_mode == kTableReplicated ? 1024 : 256;
     if (cfg.block_threads != 64 && cfg.block_threads != 128 && cfg.block_threads != 256 &&
         cfg.block_threads != 512 && cfg.block_threads != 1024)
         return set_error(CKPT_E_INVAL, "block_threads %u", cfg.block_threads);
@@ -256,8 +285,6 @@ extern "C" int ckpt_init(const ckpt_config *cfg_in, ckpt_ctx **out)
     const uint32_t w = cfg.waves_per_chunk;
     if ((w & (w - 1)) != 0 || w > 16 || w > cfg.block_threads / 64)
         return set_error(CKPT_E_INVAL, "waves_per_chunk %u with block_threads %u", w, cfg.block_threads);
-    if (cfg.lane_pieces == 0)
-        cfg.lane_pieces = 1;    // fully coalesced 16-byte loads measured fastest
     if (cfg.load_hint == 0)
         cfg.load_hint = 2;      // streaming: every byte is touched once
     if (cfg.lane_pieces != 1 && cfg.lane_pieces != 2 && cfg.lane_pieces != 4)
@@ -290,8 +317,11 @@ int ckpt::ctx_setup(ckpt_ctx *ctx)
     int managed = 0;
     if (hipDeviceGetAttribute(&managed, hipDeviceAttributeConcurrentManagedAccess, cfg.device) == hipSuccess)
         ctx->managed_prefetch = managed != 0;
+    // LDS decides how many workgroups fit a CU: 36 KiB (compact tables) or
+    // 124 KiB (replicated) of the 160 KiB
+    const int lds_fit = cfg.table_mode == kTableReplicated ? 1 : 4;
     const int per_cu = cfg.wgs_per_cu ? (int)cfg.wgs_per_cu
-                                      : std::max(1, std::min(4, 32 / (int)(cfg.block_threads / 64)));
+                                      : std::max(1, std::min(lds_fit, 32 / (int)(cfg.block_threads / 64)));
     ctx->grid_chunks = ctx->cu_count * per_cu;
     ctx->grid_small = ctx->cu_count * 4;
     return CKPT_OK;
@@ -308,11 +338,15 @@ int ckpt::ctx_ready(ckpt_ctx *ctx)
     HIP_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
     for (auto &ev : ctx->ev)
         HIP_TRY(hipEventCreate(&ev));
+    HIP_TRY(hipEventCreateWithFlags(&ctx->meta_ev, hipEventDisableTiming));
     const uint32_t round_bytes = kRoundBytes * cfg.lane_pieces;
     const uint32_t r_full = (cfg.chunk_bytes + round_bytes - 1) / round_bytes;
     const uint32_t rw = (r_full + cfg.waves_per_chunk - 1) / cfg.waves_per_chunk;
-    std::vector<uint32_t> tabs(kTabTotalWords);
-    build_tables(tabs.data(), cfg.lane_pieces, rw);
+    std::vector<uint32_t> tabs(cfg.table_mode == kTableReplicated ? kRepWords : kTabTotalWords);
+    if (cfg.table_mode == kTableReplicated)
+        build_tables_replicated(tabs.data(), rw);
+    else
+        build_tables(tabs.data(), cfg.lane_pieces, rw);
     CKPT_TRY(ctx->d_tables.ensure(tabs.size() * 4));
     HIP_TRY(hipMemcpy(ctx->d_tables.p, tabs.data(), tabs.size() * 4, hipMemcpyHostToDevice));
     CKPT_TRY(ctx->d_plan.ensure(sizeof(DevPlan)));
@@ -337,6 +371,8 @@ extern "C" void ckpt_destroy(ckpt_ctx *ctx)
         for (auto &ev : ctx->ev)
             if (ev)
                 (void)hipEventDestroy(ev);
+        if (ctx->meta_ev)
+            (void)hipEventDestroy(ctx->meta_ev);
         for (DevBuf *b : ctx->all_dev())
             b->release();
         ctx->h_up.release();
@@ -510,6 +546,8 @@ ChunkArgs ckpt::chunk_args(ckpt_ctx *ctx)
     a.waves_per_chunk = ctx->cfg.waves_per_chunk;
     a.lane_pieces = ctx->cfg.lane_pieces;
     a.nontemporal = ctx->cfg.load_hint == 2;
+    a.table_mode = ctx->cfg.table_mode;
+    a.table_words = ctx->cfg.table_mode == kTableReplicated ? kRepWords : kTabTotalWords;
     a.size = (const uint64_t *)ctx->d_size.p;
     a.off = (const uint64_t *)ctx->d_off.p;
     a.cb = (const uint64_t *)ctx->d_cb.p;
@@ -682,6 +720,7 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     memset(&T, 0, sizeof(T));
     const auto t_call = std::chrono::steady_clock::now();
 
+    image_wait(base);
     if (base && !same_table(base, rows, C))
         return set_error(CKPT_E_MISMATCH, "base image has another allocation table or chunk size");
     if (!incremental && cfg.staging_budget && L.data_bytes > cfg.staging_budget)
@@ -695,6 +734,7 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
         HIP_TRY(hipDeviceSynchronize());
         T.order_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
+    CKPT_TRY(order_after_meta(ctx, s));
     if (ctx->managed_prefetch)
         for (const Row &r : rows)
             if (r.kind == CKPT_MANAGED && r.size)
@@ -710,10 +750,11 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     if (timing)
         HIP_TRY(hipEventRecord(ctx->ev[0], s));
     if (graph) {
+        // the replayed graph holds the upload, scan, map and pack: ev[0] -> ev[2]
+        // spans all of it (layout_ms is reported as 0)
         CKPT_TRY(graph_prologue(ctx, s, rows, N, L.data_bytes));
         dense = (uint8_t *)ctx->d_dense.p;
         if (timing) {
-            HIP_TRY(hipEventRecord(ctx->ev[1], s));
             HIP_TRY(hipEventRecord(ctx->ev[2], s));
         }
     } else {
@@ -933,17 +974,34 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     }
     if (timing)
         HIP_TRY(hipEventRecord(ctx->ev[6], ds));
-    HIP_TRY(hipStreamSynchronize(ds));
-    if (ds != s)
+    // Without a drain the image is complete once the pack is: the CRC and
+    // flag copies to the host finish on the side stream while the caller goes
+    // on.  Each image waits for its own copy before it exposes host sections,
+    // and the next call on this context orders its work after them.
+    const bool async_meta = no_drain && ds != s;
+    if (async_meta) {
+        for (ckpt_image *img : imgs) {
+            HIP_TRY(hipEventCreateWithFlags(&img->meta_ready, hipEventDisableTiming));
+            HIP_TRY(hipEventRecord(img->meta_ready, ds));
+        }
+        HIP_TRY(hipEventRecord(ctx->meta_ev, ds));
+        ctx->meta_pending = true;
         HIP_TRY(hipStreamSynchronize(s));
+    } else {
+        HIP_TRY(hipStreamSynchronize(ds));
+        if (ds != s)
+            HIP_TRY(hipStreamSynchronize(s));
+    }
     ctx->prev_serial = nout == 1 && N ? imgs[0]->serial : 0;
 
     if (timing) {
-        T.layout_ms = ev_ms(ctx->ev[0], ctx->ev[1]);
-        T.pack_ms = ev_ms(ctx->ev[1], ctx->ev[2]);
-        T.select_ms = incremental ? ev_ms(ctx->ev[2], ctx->ev[4]) : ev_ms(ctx->ev[3], ctx->ev[4]);
-        T.gather_ms = ev_ms(ctx->ev[4], ctx->ev[5]);
-        T.d2h_ms = ev_ms(ctx->ev[5], ctx->ev[6]);
+        T.layout_ms = graph ? 0.f : ev_ms(ctx->ev[0], ctx->ev[1]);
+        T.pack_ms = graph ? ev_ms(ctx->ev[0], ctx->ev[2]) : ev_ms(ctx->ev[1], ctx->ev[2]);
+        if (!async_meta) {
+            T.select_ms = incremental ? ev_ms(ctx->ev[2], ctx->ev[4]) : ev_ms(ctx->ev[3], ctx->ev[4]);
+            T.gather_ms = ev_ms(ctx->ev[4], ctx->ev[5]);
+            T.d2h_ms = ev_ms(ctx->ev[5], ctx->ev[6]);
+        }
     }
     T.link_bytes = sel_bytes + 5 * N;
     T.total_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t_call).count();
@@ -1065,6 +1123,10 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
     DeviceGuard g(ctx->cfg.device);
     CKPT_TRY(ctx_ready(ctx));
     hipStream_t s = (hipStream_t)stream;
+    CKPT_TRY(order_after_meta(ctx, s));
+    image_wait(img);
+    if (delta)
+        image_wait(delta);
     const bool timing = ctx->cfg.flags & CKPT_TIMING;
     ckpt_timing &T = ctx->timing;
     memset(&T, 0, sizeof(T));
@@ -1178,6 +1240,7 @@ extern "C" int ckpt_image_info(const ckpt_image *img, ckpt_image_meta *out)
 {
     if (!img || !out)
         return set_error(CKPT_E_INVAL, "image or out is NULL");
+    image_wait(img);
     memset(out, 0, sizeof(*out));
     out->mode = img->mode;
     out->chunk_bytes = img->C;
@@ -1198,6 +1261,7 @@ extern "C" int ckpt_image_view(const ckpt_image *img, int section, const void **
 {
     if (!img || !p || !bytes)
         return set_error(CKPT_E_INVAL, "NULL argument");
+    image_wait(img);
     switch (section) {
     case CKPT_SEC_ALLOCS:
         *p = img->allocs.empty() ? nullptr : img->allocs.data();
@@ -1249,6 +1313,7 @@ extern "C" int ckpt_image_serialize(const ckpt_image *img, void *buf, size_t cap
 {
     if (!img || !need)
         return set_error(CKPT_E_INVAL, "NULL argument");
+    image_wait(img);
     if (!img->drained)
         return set_error(CKPT_E_INVAL, "image holds no host data");
     const uint64_t n = img->allocs.size();

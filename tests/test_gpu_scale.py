@@ -1,0 +1,175 @@
+"""Parity at full workload sizes, in the launch configuration bench.py uses.
+
+The oracle cannot process 16 GiB in test time, so each test checks a seeded
+sample of allocations one by one against the oracle (their CRC/flag slices,
+dense and serialized bytes), plus properties that hold at any size: exact
+dirty-id sets, every restored allocation equal to its source (compared on the
+device), batched == each context alone.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import oracle as O
+from paper_2008_10596_amd import ckpt as K
+from tests.gpu_common import d2h, host, log
+
+pytestmark = pytest.mark.gpu
+
+
+def r16(x):
+    return (x + 15) // 16 * 16
+
+
+def sample(n, k, seed):
+    rng = np.random.default_rng(seed)
+    return sorted(set(rng.choice(n, min(k, n), replace=False).tolist()) | {0, n - 1})
+
+
+def free():
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def test_full_checkpoint_at_scale_sampled():
+    w = synth.at_scale()
+    sizes = [int(s) for s in w["sizes"]]
+    C = 4096
+    log("at scale: %d allocations, %.2f GiB" % (len(sizes), sum(sizes) / 2**30))
+    tensors = synth.make_device_allocs(sizes, w["zero"], workload=2)
+    off, cb, data_bytes, N = O.layout(sizes, C)
+    ctx = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN)
+    for t in tensors:
+        ctx.register(t)
+    img_nd = ctx.checkpoint()
+    dense_p, dense_n = img_nd.dense_ptr
+    assert dense_n == data_bytes
+    dctx = K.Context(chunk_bytes=C)
+    for t in tensors:
+        dctx.register(t)
+    img = dctx.checkpoint()
+    info = img.info()
+    assert info["n_chunks"] == N and info["data_bytes"] == data_bytes
+    crc, flags, data = img.crc, img.flags, img.data
+    assert np.array_equal(img_nd.crc, crc) and np.array_equal(img_nd.flags, flags)
+    # serialized offset of every chunk, from the flags and the layout
+    lens = np.concatenate([np.minimum(C, s - np.arange(0, s, C)) for s in sizes if s])
+    ser_len = np.where(flags & 1, 0, (lens + 15) // 16 * 16)
+    soff = np.concatenate([[0], np.cumsum(ser_len)])
+    assert soff[-1] == info["serialized_bytes"]
+    for k in sample(len(sizes), 24, 1):
+        a = host(tensors[k])
+        ref = O.checkpoint([a], C)
+        g0, g1 = int(cb[k]), int(cb[k]) + len(ref["crc"])
+        assert np.array_equal(crc[g0:g1], ref["crc"]), k
+        assert np.array_equal(flags[g0:g1], ref["flags"]), k
+        assert np.array_equal(data[soff[g0]:soff[g1]], ref["serialized"]), k
+        o = int(off[k])
+        assert np.array_equal(d2h(dense_p + o, r16(sizes[k])), ref["dense"]), k
+    img_nd.close()
+    ctx.close()
+    # restore everything into fresh buffers; compare every allocation on the device
+    dsts = [torch.empty_like(t) for t in tensors]
+    rc, rep = dctx.restore(img, dsts)
+    assert rc == K.CKPT_OK, rep
+    for k, (a, b) in enumerate(zip(dsts, tensors)):
+        assert torch.equal(a, b), k
+    img.close()
+    dctx.close()
+    del tensors, dsts
+    free()
+
+
+def test_incremental_at_scale_exact_dirty_set():
+    w = synth.incremental()
+    sizes = [int(s) for s in w["sizes"]]
+    C = 65536
+    g = w["grid"]
+    assert g == C
+    log("incremental: %d allocations, %d cells rewritten" % (len(sizes), len(w["mut_alloc"])))
+    tensors = synth.make_device_allocs(sizes, w["zero"], workload=3)
+    ctx = K.Context(chunk_bytes=C)
+    for t in tensors:
+        ctx.register(t)
+    base = ctx.checkpoint()
+    base_crc = base.crc.copy()
+    for i, (k, c) in enumerate(zip(w["mut_alloc"], w["mut_cell"])):
+        t = tensors[int(k)]
+        lo = int(c) * g
+        synth.fill_random_(t[lo:min(t.numel(), lo + g)], synth.alloc_seed(3, int(k), phase=1) + i)
+    torch.cuda.synchronize()
+    delta = ctx.checkpoint(mode=K.CKPT_INCREMENTAL, base=base)
+    _, cb, _, N = O.layout(sizes, C)
+    # with C equal to the mutation grid, the dirty set is exactly the rewritten cells
+    want = np.sort(cb[w["mut_alloc"]].astype(np.int64) + w["mut_cell"])
+    assert np.array_equal(delta.dirty_ids.astype(np.int64), want)
+    # sampled oracle deltas
+    dcrc, dflags, ddata = delta.crc, delta.flags, delta.data
+    ids = delta.dirty_ids
+    lens = np.concatenate([np.minimum(C, s - np.arange(0, s, C)) for s in sizes])
+    sel = np.zeros(N, np.int64)
+    sel[ids] = np.where(dflags[ids] & 1, 0, (lens[ids] + 15) // 16 * 16)
+    soff = np.concatenate([[0], np.cumsum(sel)])
+    for k in sample(len(sizes), 16, 3) + [int(w["mut_alloc"][0])]:
+        a = host(tensors[k])
+        g0 = int(cb[k])
+        nk = -(-sizes[k] // C)
+        ref = O.delta([a], C, base_crc[g0:g0 + nk])
+        assert np.array_equal(dcrc[g0:g0 + nk], ref["crc"]), k
+        assert np.array_equal(dflags[g0:g0 + nk], ref["flags"]), k
+        assert np.array_equal(ids[(ids >= g0) & (ids < g0 + nk)] - g0, ref["dirty_ids"]), k
+        assert np.array_equal(ddata[soff[g0]:soff[g0 + nk]], ref["delta"]), k
+    dsts = [torch.empty_like(t) for t in tensors]
+    rc, rep = ctx.restore(base, dsts, delta=delta)
+    assert rc == K.CKPT_OK, rep
+    for k, (a, b) in enumerate(zip(dsts, tensors)):
+        assert torch.equal(a, b), k
+    base.close()
+    delta.close()
+    ctx.close()
+    del tensors, dsts
+    free()
+
+
+def test_batched_at_scale_sampled():
+    spec = synth.batched()
+    C = 4096
+    sets, k = [], 0
+    for cs in spec:
+        allocs = []
+        for j, sz in enumerate(cs["sizes"]):
+            t = torch.empty(int(sz), dtype=torch.uint8, device="cuda")
+            synth.fill_random_(t, synth.alloc_seed(4, k))
+            reg = cs["region"]
+            for cell in cs["zero_cells"][j]:
+                t[int(cell) * reg:int(cell) * reg + reg] = 0
+            allocs.append(t)
+            k += 1
+        sets.append(allocs)
+    log("batched: %d contexts, %d allocations" % (len(sets), k))
+    members = []
+    for allocs in sets:
+        c = K.Context(chunk_bytes=C)
+        for t in allocs:
+            c.register(t)
+        members.append(c)
+    leader = K.Context(chunk_bytes=C)
+    imgs = K.checkpoint_batch([leader] + members)
+    for i in sample(len(sets), 12, 4):
+        alone = members[i].checkpoint()
+        for key in ("crc", "flags", "data", "allocs"):
+            assert np.array_equal(getattr(imgs[i + 1], key), getattr(alone, key)), (i, key)
+        alone.close()
+    for i in sample(len(sets), 3, 5):
+        ref = O.checkpoint([host(t) for t in sets[i]], C)
+        img = imgs[i + 1]
+        assert np.array_equal(img.crc, ref["crc"]) and np.array_equal(img.flags, ref["flags"])
+        assert np.array_equal(img.data, ref["serialized"])
+    for im in imgs:
+        im.close()
+    for c in members:
+        c.close()
+    leader.close()
+    del sets
+    free()
