@@ -1,6 +1,7 @@
 // ckpt_runtime.h -- host-side types of libckpt (not part of the public ABI).
 #pragma once
 
+#include <atomic>
 #include <cstddef>
 #include <map>
 #include <memory>
@@ -59,6 +60,26 @@ struct PinnedBuf {
     ~PinnedBuf() { release(); }
     int ensure(size_t bytes);
     void release();
+};
+
+// Completion of an asynchronous copy into host memory, shared by the images
+// it fills.
+struct MetaEvent {
+    hipEvent_t e = nullptr;
+    std::atomic<bool> done{false};
+    void wait()
+    {
+        if (e && !done.load()) {
+            (void)hipEventSynchronize(e);
+            done.store(true);
+        }
+    }
+    ~MetaEvent()
+    {
+        wait();
+        if (e)
+            (void)hipEventDestroy(e);
+    }
 };
 
 class DeviceGuard {
@@ -137,16 +158,23 @@ struct ckpt_image {
     uint64_t serial = 0, base_serial = 0;
     bool drained = false;
     std::vector<ckpt_alloc_rec> allocs;
-    ckpt::PinnedBuf crc_buf, flags_buf, ids_buf, data;
+    // CRC and flag sections: slices of a pinned block that the images of one
+    // batch share (one copy from the device for all of them)
+    std::shared_ptr<ckpt::PinnedBuf> meta;
+    uint32_t *crc = nullptr;
+    uint8_t *flags = nullptr;
+    ckpt::PinnedBuf ids_buf, data;
     void *dense = nullptr;
     bool dense_owned = false;
-    hipEvent_t meta_ready = nullptr;   // host CRC/flags valid once this completes
+    std::shared_ptr<ckpt::MetaEvent> meta_ready;   // host CRC/flags valid once this completes
     ~ckpt_image();
 };
 
 namespace ckpt {
 
 int ctx_setup(ckpt_ctx *ctx);
+// A private pinned block for an image's CRC (4N bytes) and flags (N bytes).
+int alloc_meta(ckpt_image *img, uint64_t N);
 void image_wait(const ckpt_image *img);
 int order_after_meta(ckpt_ctx *ctx, hipStream_t s);
 int ctx_ready(ckpt_ctx *ctx);

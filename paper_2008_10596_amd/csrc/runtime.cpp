@@ -212,13 +212,20 @@ void PinnedBuf::release()
 
 // -------------------------------------------------------------- the image
 
+int ckpt::alloc_meta(ckpt_image *img, uint64_t N)
+{
+    auto blk = std::make_shared<PinnedBuf>();
+    CKPT_TRY(blk->ensure(std::max<uint64_t>(5 * N, 8)));
+    img->meta = blk;
+    img->crc = (uint32_t *)blk->p;
+    img->flags = (uint8_t *)blk->p + 4 * N;
+    return CKPT_OK;
+}
+
 void ckpt::image_wait(const ckpt_image *img)
 {
-    if (img && img->meta_ready) {
-        (void)hipEventSynchronize(img->meta_ready);
-        (void)hipEventDestroy(img->meta_ready);
-        const_cast<ckpt_image *>(img)->meta_ready = nullptr;
-    }
+    if (img && img->meta_ready)
+        img->meta_ready->wait();
 }
 
 // New work on s that reuses the context's device arrays waits for the last
@@ -771,7 +778,7 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
         } else {
             CKPT_TRY(ctx->d_base_crc.ensure(std::max<uint64_t>(N, 1) * 4));
             if (N)
-                HIP_TRY(hipMemcpyAsync(ctx->d_base_crc.p, base->crc_buf.p, N * 4, hipMemcpyHostToDevice, s));
+                HIP_TRY(hipMemcpyAsync(ctx->d_base_crc.p, base->crc, N * 4, hipMemcpyHostToDevice, s));
             d_base = (const uint32_t *)ctx->d_base_crc.p;
         }
     }
@@ -928,6 +935,13 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
         bool keep = false;
         ~ImgGuard() { if (!keep) for (auto *p : v) delete p; }
     } img_guard{imgs};
+    // one pinned block for every output's CRC and flags, filled by two copies
+    auto meta = std::make_shared<PinnedBuf>();
+    CKPT_TRY(meta->ensure(std::max<uint64_t>(5 * N, 8)));
+    if (N) {
+        HIP_TRY(hipMemcpyAsync(meta->p, ctx->d_crc.p, N * 4, hipMemcpyDeviceToHost, ds));
+        HIP_TRY(hipMemcpyAsync((uint8_t *)meta->p + 4 * N, ctx->d_flags.p, N, hipMemcpyDeviceToHost, ds));
+    }
     for (size_t i = 0; i < nout; i++) {
         auto *img = new ckpt_image();
         imgs[i] = img;
@@ -940,14 +954,9 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
         img->serial = next_serial();
         img->base_serial = base ? base->serial : 0;
         img->drained = !no_drain;
-        CKPT_TRY(img->crc_buf.ensure(std::max<uint64_t>(img->N, 1) * 4));
-        CKPT_TRY(img->flags_buf.ensure(std::max<uint64_t>(img->N, 1)));
-        if (img->N) {
-            HIP_TRY(hipMemcpyAsync(img->crc_buf.p, (uint32_t *)ctx->d_crc.p + part_chunk[i], img->N * 4,
-                                   hipMemcpyDeviceToHost, ds));
-            HIP_TRY(hipMemcpyAsync(img->flags_buf.p, (uint8_t *)ctx->d_flags.p + part_chunk[i], img->N,
-                                   hipMemcpyDeviceToHost, ds));
-        }
+        img->meta = meta;
+        img->crc = (uint32_t *)meta->p + part_chunk[i];
+        img->flags = (uint8_t *)meta->p + 4 * N + part_chunk[i];
         img->data = std::move(data[i]);
         const uint64_t r0 = part_row[i], r1 = part_row[i + 1];
         img->allocs.resize(r1 - r0);
@@ -980,10 +989,11 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     // and the next call on this context orders its work after them.
     const bool async_meta = no_drain && ds != s;
     if (async_meta) {
-        for (ckpt_image *img : imgs) {
-            HIP_TRY(hipEventCreateWithFlags(&img->meta_ready, hipEventDisableTiming));
-            HIP_TRY(hipEventRecord(img->meta_ready, ds));
-        }
+        auto ev = std::make_shared<MetaEvent>();
+        HIP_TRY(hipEventCreateWithFlags(&ev->e, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(ev->e, ds));
+        for (ckpt_image *img : imgs)
+            img->meta_ready = ev;
         HIP_TRY(hipEventRecord(ctx->meta_ev, ds));
         ctx->meta_pending = true;
         HIP_TRY(hipStreamSynchronize(s));
@@ -1142,8 +1152,8 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
     CKPT_TRY(ctx->d_compact.ensure(std::max<uint64_t>(stage, 16)));
     uint8_t *staging = (uint8_t *)ctx->d_compact.p;
     if (N) {
-        HIP_TRY(hipMemcpyAsync(ctx->d_crc.p, img->crc_buf.p, N * 4, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(ctx->d_flags.p, img->flags_buf.p, N, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ctx->d_crc.p, img->crc, N * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ctx->d_flags.p, img->flags, N, hipMemcpyHostToDevice, s));
         HIP_TRY(launch_fill_u64(s, (uint64_t *)ctx->d_bad.p, (N + 7) / 8, 0));
     }
     if (img->ser_bytes)
@@ -1179,8 +1189,8 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
         CKPT_TRY(ctx->d_ids.ensure(nd * 8));
         CKPT_TRY(ctx->d_soff2.ensure(nd * 8));
         uint8_t *staging2 = staging + img->ser_bytes;
-        HIP_TRY(hipMemcpyAsync(ctx->d_crc2.p, delta->crc_buf.p, N * 4, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(ctx->d_flags2.p, delta->flags_buf.p, N, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ctx->d_crc2.p, delta->crc, N * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ctx->d_flags2.p, delta->flags, N, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(ctx->d_ids.p, delta->ids_buf.p, nd * 8, hipMemcpyHostToDevice, s));
         if (delta->ser_bytes)
             HIP_TRY(hipMemcpyAsync(staging2, delta->data.p, delta->ser_bytes, hipMemcpyHostToDevice, s));
@@ -1251,7 +1261,7 @@ extern "C" int ckpt_image_info(const ckpt_image *img, ckpt_image_meta *out)
     out->n_dirty = img->n_dirty;
     out->serial = img->serial;
     out->base_serial = img->base_serial;
-    out->crc_digest = crc_digest(img->crc_buf.p, img->N * 4);
+    out->crc_digest = crc_digest(img->crc, img->N * 4);
     out->has_dense = img->dense != nullptr;
     out->drained = img->drained;
     return CKPT_OK;
@@ -1268,11 +1278,11 @@ extern "C" int ckpt_image_view(const ckpt_image *img, int section, const void **
         *bytes = img->allocs.size() * sizeof(ckpt_alloc_rec);
         break;
     case CKPT_SEC_CRC:
-        *p = img->N ? img->crc_buf.p : nullptr;
+        *p = img->N ? img->crc : nullptr;
         *bytes = img->N * 4;
         break;
     case CKPT_SEC_FLAGS:
-        *p = img->N ? img->flags_buf.p : nullptr;
+        *p = img->N ? img->flags : nullptr;
         *bytes = img->N;
         break;
     case CKPT_SEC_DATA:
@@ -1328,15 +1338,15 @@ extern "C" int ckpt_image_serialize(const ckpt_image *img, void *buf, size_t cap
     uint32_t h32[4] = {kVersion, img->mode, img->C, 16};
     memcpy(p + 8, h32, 16);
     uint64_t h64[8] = {n, img->N, img->data_bytes, img->ser_bytes, img->n_dirty, img->serial, img->base_serial,
-                       crc_digest(img->crc_buf.p, img->N * 4)};
+                       crc_digest(img->crc, img->N * 4)};
     memcpy(p + 24, h64, 64);
     p += kHeaderBytes;
     if (n)
         memcpy(p, img->allocs.data(), n * sizeof(ckpt_alloc_rec));
     p += n * sizeof(ckpt_alloc_rec);
     if (img->N) {
-        memcpy(p, img->crc_buf.p, img->N * 4);
-        memcpy(p + img->N * 4, img->flags_buf.p, img->N);
+        memcpy(p, img->crc, img->N * 4);
+        memcpy(p + img->N * 4, img->flags, img->N);
     }
     memset(p + img->N * 4 + img->N, 0, pad8(img->N) - img->N);
     p += img->N * 4 + pad8(img->N);
@@ -1399,11 +1409,10 @@ extern "C" int ckpt_image_load(ckpt_ctx *ctx, const void *buf, size_t bytes, ckp
     }
     if (o != img->data_bytes || g != N)
         return set_error(CKPT_E_INVAL, "allocation table does not match the header totals");
-    CKPT_TRY(img->crc_buf.ensure(std::max<uint64_t>(N, 1) * 4));
-    CKPT_TRY(img->flags_buf.ensure(std::max<uint64_t>(N, 1)));
+    CKPT_TRY(alloc_meta(img, N));
     if (N) {
-        memcpy(img->crc_buf.p, p, N * 4);
-        memcpy(img->flags_buf.p, p + N * 4, N);
+        memcpy(img->crc, p, N * 4);
+        memcpy(img->flags, p + N * 4, N);
     }
     p += N * 4 + pad8(N);
     CKPT_TRY(img->ids_buf.ensure(std::max<uint64_t>(nd, 1) * 8));
@@ -1413,7 +1422,7 @@ extern "C" int ckpt_image_load(ckpt_ctx *ctx, const void *buf, size_t bytes, ckp
     CKPT_TRY(img->data.ensure(std::max<uint64_t>(ser, 1)));
     if (ser)
         memcpy(img->data.p, p, ser);
-    if (crc_digest(img->crc_buf.p, N * 4) != h64[7])
+    if (crc_digest(img->crc, N * 4) != h64[7])
         return set_error(CKPT_E_INVAL, "CRC section digest mismatch");
     *out = guard.release();
     return CKPT_OK;

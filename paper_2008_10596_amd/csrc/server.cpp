@@ -246,8 +246,8 @@ int prep_request(ckpt_server *sv, Req *r, hipStream_t s, PinnedBuf &up)
     } else {
         const ckpt_image *img = r->image;
         if (N) {
-            REQ_HIP(r, hipMemcpyAsync(r->d_crc, img->crc_buf.p, 4 * N, hipMemcpyHostToDevice, s));
-            REQ_HIP(r, hipMemcpyAsync(r->d_flags, img->flags_buf.p, N, hipMemcpyHostToDevice, s));
+            REQ_HIP(r, hipMemcpyAsync(r->d_crc, img->crc, 4 * N, hipMemcpyHostToDevice, s));
+            REQ_HIP(r, hipMemcpyAsync(r->d_flags, img->flags, N, hipMemcpyHostToDevice, s));
             REQ_HIP(r, hipMemsetAsync(r->d_bad, 0, N, s));
         }
         if (r->ser_bytes)
@@ -311,8 +311,7 @@ int finish_request(ckpt_server *sv, Req *r, hipStream_t s, PinnedBuf &up)
         sel = plan->sel_bytes;
     }
     img->ser_bytes = sel;
-    if (img->crc_buf.ensure(std::max<uint64_t>(N, 1) * 4) || img->flags_buf.ensure(std::max<uint64_t>(N, 1)) ||
-        img->data.ensure(std::max<uint64_t>(sel, 1))) {
+    if (alloc_meta(img.get(), N) || img->data.ensure(std::max<uint64_t>(sel, 1))) {
         r->result.status = CKPT_E_NOMEM;
         return CKPT_E_NOMEM;
     }
@@ -336,8 +335,8 @@ int finish_request(ckpt_server *sv, Req *r, hipStream_t s, PinnedBuf &up)
         REQ_HIP(r, hipMemcpyAsync(img->data.p, r->d_compact, sel, hipMemcpyDeviceToHost, s));
     }
     if (N) {
-        REQ_HIP(r, hipMemcpyAsync(img->crc_buf.p, r->d_crc, 4 * N, hipMemcpyDeviceToHost, s));
-        REQ_HIP(r, hipMemcpyAsync(img->flags_buf.p, r->d_flags, N, hipMemcpyDeviceToHost, s));
+        REQ_HIP(r, hipMemcpyAsync(img->crc, r->d_crc, 4 * N, hipMemcpyDeviceToHost, s));
+        REQ_HIP(r, hipMemcpyAsync(img->flags, r->d_flags, N, hipMemcpyDeviceToHost, s));
     }
     REQ_HIP(r, hipStreamSynchronize(s));
     static std::atomic<uint64_t> serial{0};
