@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="only the timed pack steps")
     ap.add_argument("--drain-steps", type=int, default=3)
     ap.add_argument("--only", default="", help="comma list of extra sections to run "
-                    "(drain,incremental,batched,serving); default: all")
+                    "(drain,restore_at,incremental,batched,serving); default: all")
     ap.add_argument("--serving-requests", type=int, default=60, help="measured requests per rate")
     ap.add_argument("--serving-rates", default="10,50,150", help="arrival rates (req/s)")
     ap.add_argument("--serving-shapes", type=int, default=24)
@@ -298,6 +298,46 @@ def bench_batched(K, synth, torch, stream, args, reps=3):
                        "c4096_best_gbps": max(t["gbps"] for t in tuned["trials"] if t["chunk_bytes"] == 4096)}
     log("autotune: %s" % out["autotune"])
     del tensors, sets
+    return out
+
+
+def bench_restore_at(K, torch, tensors, sizes, C, stream, reps=3):
+    """Restore at the recorded addresses: the at-scale allocations as
+    address-stable memory, drained once; then the image is restored in place
+    (allocations live) and after every allocation was released (re-created
+    at its address, then refilled), both timed on the host around the call."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    vctx = K.Context(chunk_bytes=C)
+    ptrs = []
+    for t, s in zip(tensors, sizes):
+        p, _ = vctx.vmm_alloc(s)
+        assert hip.hipMemcpy(p, t.data_ptr(), s, 3) == 0   # device to device
+        ptrs.append(p)
+    img = vctx.checkpoint(stream=stream)
+    vctx.restore_at(img, stream=stream)   # warm
+    inplace, recreate = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        rc, _, _ = vctx.restore_at(img, stream=stream)
+        inplace.append((time.perf_counter() - t0) * 1e3)
+        assert rc == K.CKPT_OK
+        for p in ptrs:
+            vctx.vmm_free(p)
+        t0 = time.perf_counter()
+        rc, _, addrs = vctx.restore_at(img, stream=stream)
+        recreate.append((time.perf_counter() - t0) * 1e3)
+        assert rc == K.CKPT_OK and addrs == ptrs
+    a, b = statistics.median(inplace), statistics.median(recreate)
+    out = {"allocations": len(sizes), "live_bytes": sum(sizes),
+           "serialized_bytes": img.info()["serialized_bytes"],
+           "in_place_ms": round(a, 3), "recreate_ms": round(b, 3),
+           "recreate_overhead_ms": round(b - a, 3),
+           "recreate_overhead_us_per_allocation": round((b - a) * 1e3 / max(len(sizes), 1), 2),
+           "verified": "every chunk's CRC on every restore (status CKPT_OK)"}
+    img.close()
+    vctx.close()
     return out
 
 
@@ -557,7 +597,8 @@ def main():
         result["roofline"]["traffic"] = prof[0]
         result["roofline"]["traffic_source"] = "profiles/" + prof[2]
 
-    sections = set(args.only.split(",")) if args.only else {"drain", "incremental", "batched", "serving"}
+    sections = set(args.only.split(",")) if args.only else {"drain", "restore_at", "incremental", "batched",
+                                                             "serving"}
     if args.no_extras:
         sections = set()
     if "drain" in sections:
@@ -622,6 +663,11 @@ def main():
         img.close()
         del dsts
         dctx.close()
+
+    if "restore_at" in sections:
+        result["restore_at"] = bench_restore_at(K, torch, tensors, sizes, C, stream)
+        log("restore_at: %s" % result["restore_at"])
+        torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -81,7 +81,8 @@ enum ckpt_status {
     CKPT_E_MISMATCH = -5,  /* image / base / destination shapes disagree         */
     CKPT_E_CORRUPT = -6,   /* restore: some chunk's CRC did not verify           */
     CKPT_E_AGAIN = -7,     /* server: request not finished yet                   */
-    CKPT_E_BUDGET = -8     /* request larger than the staging budget              */
+    CKPT_E_BUDGET = -8,    /* request larger than the staging budget              */
+    CKPT_E_ADDR = -9       /* the address range asked for is not free               */
 };
 
 /* ckpt_config.flags */
@@ -166,8 +167,11 @@ enum ckpt_section {
                             /* chunks in ascending id; incremental = DIRTY non-ZERO     */
                             /* chunks; each chunk padded with zeros to a multiple of 16 */
     CKPT_SEC_DIRTY_IDS = 4, /* host, uint64_t[n_dirty]: ascending ids of DIRTY chunks   */
-    CKPT_SEC_DENSE = 5      /* DEVICE pointer, data_bytes: allocation k at off_k,       */
+    CKPT_SEC_DENSE = 5,     /* DEVICE pointer, data_bytes: allocation k at off_k,       */
                             /* pad bytes zero (with CKPT_KEEP_DENSE or CKPT_NO_DRAIN)    */
+    CKPT_SEC_ADDRS = 6      /* host, uint64_t[n_allocs]: device address of allocation k */
+                            /* when the image was taken (0 if loaded from version-1     */
+                            /* serialized data); used by ckpt_restore_at                 */
 };
 
 #define CKPT_REPORT_MAX 64
@@ -268,6 +272,111 @@ int ckpt_checkpoint(ckpt_ctx *ctx, void *stream, int mode, const ckpt_image *bas
 int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, const ckpt_image *delta,
                  void *const *dst, const size_t *dst_bytes, size_t n_dst,
                  ckpt_verify_report *rep);
+
+/* ------------------------------------------------ address-stable memory
+ *
+ * On restart every allocation has to come back at the device address the
+ * application knew, because the application's own data holds those pointers
+ * (Sec. 3.1 and Sec. 3.2, "restoring the CUDA library-allocated regions").
+ * The paper gets the addresses back by replaying the logged allocation calls
+ * in order against a deterministic allocator with address randomization off,
+ * and names address virtualization, or a fixed-address allocation flag like
+ * mmap's, as the way to drop that dependence.  HIP's virtual memory management
+ * is such a mechanism: a virtual range is reserved at a requested address and
+ * physical device memory is mapped into it.  These calls use it.
+ *
+ * Memory made by ckpt_vmm_alloc or ckpt_restore_at belongs to the context
+ * (unlike memory the caller registers): it is registered as CKPT_DEVICE, is
+ * released by ckpt_vmm_free or ckpt_destroy, and ckpt_unregister refuses it.
+ * The caller must have finished every use of it before releasing it.
+ */
+
+/* Granularity of address-stable ranges on the context's device (bytes). */
+int ckpt_vmm_granularity(ckpt_ctx *ctx, size_t *out);
+
+/*
+ * Reserve a virtual range of `bytes` rounded up to the granularity -- at
+ * `addr` if it is not NULL, else where the runtime chooses -- back it with
+ * device memory, make it readable and writable on the device, and register
+ * [*out, *out + bytes) as CKPT_DEVICE.
+ * CKPT_E_INVAL: bytes is 0, or addr is not a multiple of the granularity.
+ * CKPT_E_ADDR: the range at addr is not free.  CKPT_E_NOMEM: no device memory.
+ */
+int ckpt_vmm_alloc(ckpt_ctx *ctx, size_t bytes, void *addr, void **out, ckpt_id *id);
+
+/* Unregister an allocation made by ckpt_vmm_alloc or ckpt_restore_at and
+ * release its range once no registration is left in it.
+ * CKPT_E_NOTFOUND: ptr is not such an allocation. */
+int ckpt_vmm_free(ckpt_ctx *ctx, void *ptr);
+
+/*
+ * Restore an image at the addresses it was taken from (section
+ * CKPT_SEC_ADDRS), as the restart of Sec. 3.2 does, then verify every chunk as
+ * ckpt_restore does (optionally overlaying an incremental image `delta`).
+ * For each allocation k, in id order:
+ *   - a live registration of the context with the same start, size and kind
+ *     is refilled in place (rolling back memory that still exists);
+ *   - otherwise the allocation is re-created: allocations sharing a
+ *     granule are grouped, each group's granule-aligned range is reserved at
+ *     its original address and backed with device memory, and the allocation
+ *     is registered at its original address.  Its registration id is the
+ *     image's id when the context has not issued that id yet (a fresh
+ *     context keeps every id, so an incremental checkpoint against `img` can
+ *     follow), else the next free id.
+ * addrs_out (optional, n_allocs entries) receives the addresses, which equal
+ * section CKPT_SEC_ADDRS on success.
+ * CKPT_E_ADDR: a range is taken (by memory outside the context, or by a live
+ *   registration that overlaps without matching exactly); nothing is created.
+ * CKPT_E_INVAL: the image has no addresses, or a managed allocation would have
+ *   to be re-created (managed memory cannot be placed at a fixed address).
+ * Other errors as ckpt_restore; on any error but CKPT_E_CORRUPT the memory
+ * this call created is released again.
+ */
+int ckpt_restore_at(ckpt_ctx *ctx, void *stream, const ckpt_image *img, const ckpt_image *delta,
+                    void **addrs_out, ckpt_verify_report *rep);
+
+/* ------------------------------------------------- automatic registration
+ *
+ * The paper interposes on the cudaMalloc family, so every allocation and
+ * free is logged without the application's help (Sec. 3.1, "Log-and-replay";
+ * Sec. 3.2, "Issue of library-allocated memory").  ckpt_hook_malloc and
+ * ckpt_hook_free are that interposition for allocators that call out to a
+ * pair of C functions: their signatures are the ones PyTorch's pluggable
+ * allocator (torch.cuda.memory.CUDAPluggableAllocator) calls, and a caller's
+ * own hipMalloc wrapper can call them too.  Each allocation on the installed
+ * context's device is registered there (CKPT_DEVICE) when it is made and
+ * unregistered when it is freed, so the context's live set is the active
+ * allocations, in allocation order.
+ *
+ * One context at a time is installed, process-wide.  While a context is
+ * installed, its calls and the hook functions are serialized by one lock, so
+ * a checkpoint sees no half-made allocation; allocations from other threads
+ * wait while it runs.  ckpt_destroy of the installed context uninstalls it;
+ * memory made through the hook stays valid (address-stable memory aside,
+ * which the context owns and releases).
+ */
+#define CKPT_HOOK_ADDRESS_STABLE 0x1u   /* allocate with ckpt_vmm_alloc, so that
+                                           ckpt_restore_at can bring every
+                                           allocation back at its address      */
+
+/* Install ctx (NULL: none) as the context the hook logs into.  Resets the
+ * hook counters.  CKPT_E_INVAL: unknown flags. */
+int ckpt_hook_install(ckpt_ctx *ctx, uint32_t flags);
+
+/* Allocate `bytes` on `device` (hipMalloc, or ckpt_vmm_alloc with
+ * CKPT_HOOK_ADDRESS_STABLE) and register it when `device` is the installed
+ * context's; other devices get plain unregistered hipMalloc memory.  NULL on
+ * failure or for 0 bytes.  `stream` is not used: the memory is usable on any
+ * stream. */
+void *ckpt_hook_malloc(size_t bytes, int device, void *stream);
+
+/* Unregister and free memory from ckpt_hook_malloc.  Waits for the device's
+ * queued work before the memory is released.  bytes and stream are not used. */
+void ckpt_hook_free(void *ptr, size_t bytes, int device, void *stream);
+
+/* Registered allocations and frees since ckpt_hook_install, and allocations
+ * that failed. */
+int ckpt_hook_stats(uint64_t *allocs, uint64_t *frees, uint64_t *failures);
 
 /* ----------------------------------------------------------------- image */
 

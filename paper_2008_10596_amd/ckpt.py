@@ -24,6 +24,7 @@ CKPT_FULL, CKPT_INCREMENTAL = 0, 1
 CKPT_OK = 0
 CKPT_E_INVAL, CKPT_E_NOTFOUND, CKPT_E_NOMEM, CKPT_E_HIP = -1, -2, -3, -4
 CKPT_E_MISMATCH, CKPT_E_CORRUPT, CKPT_E_AGAIN, CKPT_E_BUDGET = -5, -6, -7, -8
+CKPT_E_ADDR = -9
 CKPT_STREAM_ORDERED = 0x1
 CKPT_KEEP_DENSE = 0x2
 CKPT_NO_DRAIN = 0x4
@@ -31,13 +32,15 @@ CKPT_TIMING = 0x8
 CKPT_DRAIN_DIRECT = 0x10
 CKPT_GRAPH = 0x20
 CKPT_NO_GRAPH = 0x40
+CKPT_HOOK_ADDRESS_STABLE = 0x1
 CKPT_SEC_ALLOCS, CKPT_SEC_CRC, CKPT_SEC_FLAGS, CKPT_SEC_DATA, CKPT_SEC_DIRTY_IDS, CKPT_SEC_DENSE = range(6)
+CKPT_SEC_ADDRS = 6
 CKPT_REPORT_MAX = 64
 CKPT_REQ_CHECKPOINT, CKPT_REQ_RESTORE = 0, 1
 
 STATUS_NAMES = {0: "CKPT_OK", -1: "CKPT_E_INVAL", -2: "CKPT_E_NOTFOUND", -3: "CKPT_E_NOMEM",
                 -4: "CKPT_E_HIP", -5: "CKPT_E_MISMATCH", -6: "CKPT_E_CORRUPT", -7: "CKPT_E_AGAIN",
-                -8: "CKPT_E_BUDGET"}
+                -8: "CKPT_E_BUDGET", -9: "CKPT_E_ADDR"}
 
 
 class ckpt_config(ctypes.Structure):
@@ -128,6 +131,14 @@ SIGNATURES = [
     ("ckpt_image_load", ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]),
     ("ckpt_image_free", None, [_vp]),
     ("ckpt_checkpoint_batch", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    ("ckpt_vmm_granularity", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    ("ckpt_vmm_alloc", ctypes.c_int, [_vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_uint64)]),
+    ("ckpt_vmm_free", ctypes.c_int, [_vp, _vp]),
+    ("ckpt_restore_at", ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_vp), ctypes.POINTER(ckpt_verify_report)]),
+    ("ckpt_hook_install", ctypes.c_int, [_vp, ctypes.c_uint32]),
+    ("ckpt_hook_malloc", _vp, [ctypes.c_size_t, ctypes.c_int, _vp]),
+    ("ckpt_hook_free", None, [_vp, ctypes.c_size_t, ctypes.c_int, _vp]),
+    ("ckpt_hook_stats", ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64)] * 3),
     ("ckpt_last_timing", ctypes.c_int, [_vp, ctypes.POINTER(ckpt_timing)]),
     ("ckpt_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("ckpt_last_hip_error", ctypes.c_int, []),
@@ -259,6 +270,10 @@ class Image:
         return self._arr(CKPT_SEC_DIRTY_IDS, np.uint64)
 
     @property
+    def addrs(self):
+        return self._arr(CKPT_SEC_ADDRS, np.uint64)
+
+    @property
     def dense_ptr(self):
         return self.view(CKPT_SEC_DENSE)
 
@@ -343,6 +358,34 @@ class Context:
         if rc not in (CKPT_OK, CKPT_E_CORRUPT) or (rc == CKPT_E_CORRUPT and raise_on_corrupt):
             raise CkptError(rc, "ckpt_restore")
         return rc, {"n_bad": rep.n_bad, "ids": [rep.ids[i] for i in range(rep.n_ids)]}
+
+    def vmm_granularity(self):
+        g = ctypes.c_size_t()
+        _check(lib().ckpt_vmm_granularity(self.handle, ctypes.byref(g)), "ckpt_vmm_granularity")
+        return g.value
+
+    def vmm_alloc(self, nbytes, addr=0):
+        """Address-stable device memory of the context: returns (address, id)."""
+        p, i = _vp(), ctypes.c_uint64()
+        _check(lib().ckpt_vmm_alloc(self.handle, nbytes, addr or None, ctypes.byref(p), ctypes.byref(i)),
+               "ckpt_vmm_alloc")
+        return p.value, i.value
+
+    def vmm_free(self, ptr):
+        _check(lib().ckpt_vmm_free(self.handle, _ptr(ptr)), "ckpt_vmm_free")
+
+    def restore_at(self, image, delta=None, stream=None, raise_on_corrupt=False):
+        """Restore image at its recorded addresses (re-creating what is gone).
+        Returns (status, report dict, addresses)."""
+        n = image.info()["n_allocs"]
+        out = (_vp * max(n, 1))()
+        rep = ckpt_verify_report()
+        rc = lib().ckpt_restore_at(self.handle, _stream_handle(stream), image.handle,
+                                   delta.handle if delta else None, out, ctypes.byref(rep))
+        if rc not in (CKPT_OK, CKPT_E_CORRUPT) or (rc == CKPT_E_CORRUPT and raise_on_corrupt):
+            raise CkptError(rc, "ckpt_restore_at")
+        return rc, {"n_bad": rep.n_bad, "ids": [rep.ids[i] for i in range(rep.n_ids)]}, \
+            [out[k] or 0 for k in range(n)]
 
     def timing(self):
         t = ckpt_timing()

@@ -5,6 +5,7 @@
 #include <cstddef>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "ckpt.h"
@@ -107,6 +108,26 @@ struct RangeEnd {
     uint64_t id;
 };
 
+// A virtual range the context reserved and backed with device memory
+// (ckpt_vmm_alloc, ckpt_restore_at); released when its last registration goes.
+struct VmmRange {
+    uint64_t bytes = 0;                    // multiple of the allocation granularity
+    hipMemGenericAllocationHandle_t h{};   // the physical memory mapped there
+    uint32_t refs = 0;                     // live registrations inside the range
+};
+
+// Registration with a given id when it is still unissued in the context (at or
+// above next_id), else with the next id; fails on overlap as ckpt_register does.
+int add_registration(ckpt_ctx *ctx, uint64_t start, uint64_t bytes, uint32_t kind, uint64_t want_id,
+                     uint64_t *id);
+int drop_registration(ckpt_ctx *ctx, uint64_t start);
+void vmm_release_all(ckpt_ctx *ctx);
+
+// The allocation hook (ckpt_hook_*) and the calls on the context it logs into
+// are serialized by one process-wide lock, held only for a hooked context.
+std::recursive_mutex &hook_mutex();
+void hook_forget(ckpt_ctx *ctx);
+
 }  // namespace ckpt
 
 struct ckpt_ctx {
@@ -133,6 +154,12 @@ struct ckpt_ctx {
     std::map<uint64_t, ckpt::RangeEnd> ranges;
     uint64_t next_id = 1;
 
+    // address-stable memory the context owns: ranges by base, and the range
+    // base of each registration made inside one
+    std::map<uint64_t, ckpt::VmmRange> vmm;
+    std::map<uint64_t, uint64_t> vmm_of;
+    std::atomic<bool> hooked{false};   // the allocation hook logs into this context
+
     // device buffers
     ckpt::DevBuf d_tables, d_plan, d_addr, d_size, d_off, d_cb, d_map;
     ckpt::DevBuf d_crc, d_flags, d_base_crc, d_prev_crc, d_soff, d_ids, d_tile_b, d_tile_c;
@@ -158,6 +185,7 @@ struct ckpt_image {
     uint64_t serial = 0, base_serial = 0;
     bool drained = false;
     std::vector<ckpt_alloc_rec> allocs;
+    std::vector<uint64_t> addrs;   // device address of each allocation when taken
     // CRC and flag sections: slices of a pinned block that the images of one
     // batch share (one copy from the device for all of them)
     std::shared_ptr<ckpt::PinnedBuf> meta;
@@ -188,4 +216,19 @@ ChunkArgs chunk_args(ckpt_ctx *ctx);
 int run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_image *base, const std::vector<Row> &rows,
                    const std::vector<size_t> &parts, std::vector<ckpt_image *> &outs, bool use_graph);
 
+}  // namespace ckpt
+
+namespace ckpt {
+// Holds the hook lock while a call works on a hooked context.
+class HookGuard {
+public:
+    explicit HookGuard(const ckpt_ctx *ctx)
+    {
+        if (ctx && ctx->hooked.load())
+            lk_ = std::unique_lock<std::recursive_mutex>(hook_mutex());
+    }
+
+private:
+    std::unique_lock<std::recursive_mutex> lk_;
+};
 }  // namespace ckpt

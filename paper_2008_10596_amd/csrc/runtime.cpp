@@ -56,6 +56,7 @@ extern "C" const char *ckpt_strerror(int status)
     case CKPT_E_CORRUPT: return "checksum mismatch";
     case CKPT_E_AGAIN: return "not finished";
     case CKPT_E_BUDGET: return "staging budget exceeded";
+    case CKPT_E_ADDR: return "address range not free";
     default: return "unknown status";
     }
 }
@@ -366,6 +367,7 @@ extern "C" void ckpt_destroy(ckpt_ctx *ctx)
 {
     if (!ctx)
         return;
+    hook_forget(ctx);
     {
         DeviceGuard g(ctx->cfg.device);
         if (ctx->g_exec)
@@ -384,53 +386,51 @@ extern "C" void ckpt_destroy(ckpt_ctx *ctx)
             b->release();
         ctx->h_up.release();
         ctx->h_plan.release();
+        vmm_release_all(ctx);
     }
     delete ctx;
 }
 
 // ------------------------------------------------------------ registration
 
-extern "C" int ckpt_register(ckpt_ctx *ctx, void *ptr, size_t bytes, int kind, ckpt_id *out)
+int ckpt::add_registration(ckpt_ctx *ctx, uint64_t start, uint64_t bytes, uint32_t kind, uint64_t want_id,
+                           uint64_t *id)
 {
-    if (!ctx || !out)
-        return set_error(CKPT_E_INVAL, "ctx or out is NULL");
-    if (kind != CKPT_DEVICE && kind != CKPT_MANAGED)
-        return set_error(CKPT_E_INVAL, "unknown kind %d", kind);
-    const uint64_t start = (uint64_t)(uintptr_t)ptr;
     if (start % 16 != 0)
-        return set_error(CKPT_E_INVAL, "pointer %p is not 16-byte aligned", ptr);
+        return set_error(CKPT_E_INVAL, "pointer 0x%llx is not 16-byte aligned", (unsigned long long)start);
     if (start == 0 && bytes != 0)
-        return set_error(CKPT_E_INVAL, "NULL pointer with %zu bytes", bytes);
+        return set_error(CKPT_E_INVAL, "NULL pointer with %llu bytes", (unsigned long long)bytes);
     if (start + bytes < start)
         return set_error(CKPT_E_INVAL, "range wraps the address space");
     // Overlap: a live range [s, e) with s < start + bytes and start < e, or the
     // same start (starts identify registrations).
     auto it = ctx->ranges.lower_bound(start);
     if (it != ctx->ranges.end() && (it->first == start || it->first < start + bytes))
-        return set_error(CKPT_E_INVAL, "[%p, +%zu) overlaps a live registration", ptr, bytes);
+        return set_error(CKPT_E_INVAL, "[0x%llx, +%llu) overlaps a live registration", (unsigned long long)start,
+                         (unsigned long long)bytes);
     if (it != ctx->ranges.begin()) {
         auto pv = std::prev(it);
         if (start < pv->second.end)
-            return set_error(CKPT_E_INVAL, "[%p, +%zu) overlaps a live registration", ptr, bytes);
+            return set_error(CKPT_E_INVAL, "[0x%llx, +%llu) overlaps a live registration",
+                             (unsigned long long)start, (unsigned long long)bytes);
     }
     Reg r;
-    r.id = ctx->next_id++;
-    r.kind = (uint32_t)kind;
+    r.id = want_id >= ctx->next_id ? want_id : ctx->next_id;
+    ctx->next_id = r.id + 1;
+    r.kind = kind;
     r.ptr = start;
     r.size = bytes;
-    ctx->live.push_back(r);
+    ctx->live.push_back(r);   // the largest id so far: live stays in id order
     ctx->ranges.emplace(start, RangeEnd{start + bytes, r.id});
-    *out = r.id;
+    *id = r.id;
     return CKPT_OK;
 }
 
-extern "C" int ckpt_unregister(ckpt_ctx *ctx, void *ptr)
+int ckpt::drop_registration(ckpt_ctx *ctx, uint64_t start)
 {
-    if (!ctx)
-        return set_error(CKPT_E_INVAL, "ctx is NULL");
-    auto it = ctx->ranges.find((uint64_t)(uintptr_t)ptr);
+    auto it = ctx->ranges.find(start);
     if (it == ctx->ranges.end())
-        return set_error(CKPT_E_NOTFOUND, "%p is not a live registration", ptr);
+        return set_error(CKPT_E_NOTFOUND, "0x%llx is not a live registration", (unsigned long long)start);
     const uint64_t id = it->second.id;
     ctx->ranges.erase(it);
     // live is in id order; ids are unique, so a binary search finds the row
@@ -441,10 +441,31 @@ extern "C" int ckpt_unregister(ckpt_ctx *ctx, void *ptr)
     return CKPT_OK;
 }
 
+extern "C" int ckpt_register(ckpt_ctx *ctx, void *ptr, size_t bytes, int kind, ckpt_id *out)
+{
+    if (!ctx || !out)
+        return set_error(CKPT_E_INVAL, "ctx or out is NULL");
+    HookGuard hg(ctx);
+    if (kind != CKPT_DEVICE && kind != CKPT_MANAGED)
+        return set_error(CKPT_E_INVAL, "unknown kind %d", kind);
+    return add_registration(ctx, (uint64_t)(uintptr_t)ptr, bytes, (uint32_t)kind, 0, out);
+}
+
+extern "C" int ckpt_unregister(ckpt_ctx *ctx, void *ptr)
+{
+    if (!ctx)
+        return set_error(CKPT_E_INVAL, "ctx is NULL");
+    HookGuard hg(ctx);
+    if (ctx->vmm_of.count((uint64_t)(uintptr_t)ptr))
+        return set_error(CKPT_E_INVAL, "%p is memory of the context; release it with ckpt_vmm_free", ptr);
+    return drop_registration(ctx, (uint64_t)(uintptr_t)ptr);
+}
+
 extern "C" int ckpt_live_count(const ckpt_ctx *ctx, size_t *out)
 {
     if (!ctx || !out)
         return set_error(CKPT_E_INVAL, "ctx or out is NULL");
+    HookGuard hg(ctx);
     *out = ctx->live.size();
     return CKPT_OK;
 }
@@ -960,7 +981,9 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
         img->data = std::move(data[i]);
         const uint64_t r0 = part_row[i], r1 = part_row[i + 1];
         img->allocs.resize(r1 - r0);
+        img->addrs.resize(r1 - r0);
         for (uint64_t k = r0; k < r1; k++) {
+            img->addrs[k - r0] = rows[k].ptr;
             ckpt_alloc_rec &rec = img->allocs[k - r0];
             rec.id = rows[k].id;
             rec.kind = rows[k].kind;
@@ -1040,6 +1063,7 @@ extern "C" int ckpt_checkpoint(ckpt_ctx *ctx, void *stream, int mode, const ckpt
         return set_error(CKPT_E_INVAL, "unknown mode %d", mode);
     if (mode == CKPT_INCREMENTAL && !base)
         return set_error(CKPT_E_INVAL, "an incremental checkpoint needs a base image");
+    HookGuard hg(ctx);
     DeviceGuard g(ctx->cfg.device);
     if (!g.ok())
         return set_error(CKPT_E_HIP, "cannot select device %d", ctx->cfg.device);
@@ -1059,6 +1083,11 @@ extern "C" int ckpt_checkpoint_batch(ckpt_ctx *const *ctxs, size_t n, void *stre
     if (!ctxs || !outs || n == 0)
         return set_error(CKPT_E_INVAL, "empty batch");
     ckpt_ctx *c0 = ctxs[0];
+    const ckpt_ctx *hooked = nullptr;
+    for (size_t i = 0; i < n; i++)
+        if (ctxs[i] && ctxs[i]->hooked.load())
+            hooked = ctxs[i];
+    HookGuard hg(hooked);
     for (size_t i = 0; i < n; i++) {
         if (!ctxs[i])
             return set_error(CKPT_E_INVAL, "ctxs[%zu] is NULL", i);
@@ -1297,6 +1326,10 @@ extern "C" int ckpt_image_view(const ckpt_image *img, int section, const void **
         *p = img->dense;
         *bytes = img->dense ? img->data_bytes : 0;
         break;
+    case CKPT_SEC_ADDRS:
+        *p = img->addrs.empty() ? nullptr : img->addrs.data();
+        *bytes = img->addrs.size() * 8;
+        break;
     default:
         return set_error(CKPT_E_INVAL, "unknown section %d", section);
     }
@@ -1306,16 +1339,19 @@ extern "C" int ckpt_image_view(const ckpt_image *img, int section, const void **
 // Serialized form, all little-endian:
 //   header (kHeaderBytes): magic "CKPTIMG1", version, mode, C, align (16),
 //   n, N, data_bytes, ser_bytes, n_dirty, serial, base_serial, digest
-//   ALLOCS n x 40, CRC N x 4, FLAGS N (padded to 8), DIRTY_IDS n_dirty x 8, DATA
+//   ALLOCS n x 40, ADDRS n x 8 (version 2 on), CRC N x 4, FLAGS N (padded
+//   to 8), DIRTY_IDS n_dirty x 8, DATA.  Version 1 data (no ADDRS) still loads,
+//   with every address 0.
 namespace {
 constexpr char kMagic[8] = {'C', 'K', 'P', 'T', 'I', 'M', 'G', '1'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 constexpr size_t kHeaderBytes = 8 + 4 * 4 + 8 * 8;
 size_t pad8(size_t x) { return (x + 7) & ~size_t(7); }
 
-size_t serialized_size(uint64_t n, uint64_t N, uint64_t n_dirty, uint64_t ser)
+size_t serialized_size(uint32_t version, uint64_t n, uint64_t N, uint64_t n_dirty, uint64_t ser)
 {
-    return kHeaderBytes + n * sizeof(ckpt_alloc_rec) + N * 4 + pad8(N) + n_dirty * 8 + ser;
+    return kHeaderBytes + n * sizeof(ckpt_alloc_rec) + (version >= 2 ? n * 8 : 0) + N * 4 + pad8(N) +
+           n_dirty * 8 + ser;
 }
 }  // namespace
 
@@ -1327,7 +1363,7 @@ extern "C" int ckpt_image_serialize(const ckpt_image *img, void *buf, size_t cap
     if (!img->drained)
         return set_error(CKPT_E_INVAL, "image holds no host data");
     const uint64_t n = img->allocs.size();
-    const size_t total = serialized_size(n, img->N, img->n_dirty, img->ser_bytes);
+    const size_t total = serialized_size(kVersion, n, img->N, img->n_dirty, img->ser_bytes);
     *need = total;
     if (!buf)
         return CKPT_OK;
@@ -1344,6 +1380,11 @@ extern "C" int ckpt_image_serialize(const ckpt_image *img, void *buf, size_t cap
     if (n)
         memcpy(p, img->allocs.data(), n * sizeof(ckpt_alloc_rec));
     p += n * sizeof(ckpt_alloc_rec);
+    for (uint64_t k = 0; k < n; k++) {
+        const uint64_t a = k < img->addrs.size() ? img->addrs[k] : 0;
+        memcpy(p + 8 * k, &a, 8);
+    }
+    p += n * 8;
     if (img->N) {
         memcpy(p, img->crc, img->N * 4);
         memcpy(p + img->N * 4, img->flags, img->N);
@@ -1371,14 +1412,15 @@ extern "C" int ckpt_image_load(ckpt_ctx *ctx, const void *buf, size_t bytes, ckp
     uint64_t h64[8];
     memcpy(h32, p + 8, 16);
     memcpy(h64, p + 24, 64);
-    if (h32[0] != kVersion || (h32[1] != CKPT_FULL && h32[1] != CKPT_INCREMENTAL) || h32[2] == 0 ||
+    if ((h32[0] != 1 && h32[0] != 2) || (h32[1] != CKPT_FULL && h32[1] != CKPT_INCREMENTAL) || h32[2] == 0 ||
         h32[2] % 16 != 0 || h32[3] != 16)
         return set_error(CKPT_E_INVAL, "bad header fields");
     const uint64_t n = h64[0], N = h64[1], nd = h64[4], ser = h64[3];
     // bound every count by the buffer before multiplying
     if (n > bytes / sizeof(ckpt_alloc_rec) || N > bytes / 5 || nd > bytes / 8 || ser > bytes)
         return set_error(CKPT_E_INVAL, "truncated image");
-    const size_t total = serialized_size(n, N, nd, ser);
+    const uint32_t version = h32[0];
+    const size_t total = serialized_size(version, n, N, nd, ser);
     if (bytes < total)
         return set_error(CKPT_E_INVAL, "truncated image: %zu of %zu bytes", bytes, total);
     auto *img = new ckpt_image();
@@ -1409,6 +1451,12 @@ extern "C" int ckpt_image_load(ckpt_ctx *ctx, const void *buf, size_t bytes, ckp
     }
     if (o != img->data_bytes || g != N)
         return set_error(CKPT_E_INVAL, "allocation table does not match the header totals");
+    img->addrs.assign(n, 0);
+    if (version >= 2) {
+        if (n)
+            memcpy(img->addrs.data(), p, n * 8);
+        p += n * 8;
+    }
     CKPT_TRY(alloc_meta(img, N));
     if (N) {
         memcpy(img->crc, p, N * 4);

@@ -292,7 +292,9 @@ int finish_request(ckpt_server *sv, Req *r, hipStream_t s, PinnedBuf &up)
     img->data_bytes = r->data_bytes;
     img->drained = true;
     img->allocs.resize(r->rows.size());
+    img->addrs.resize(r->rows.size());
     for (size_t k = 0; k < r->rows.size(); k++) {
+        img->addrs[k] = r->rows[k].ptr;
         ckpt_alloc_rec &a = img->allocs[k];
         a.id = k + 1;
         a.kind = r->rows[k].kind;

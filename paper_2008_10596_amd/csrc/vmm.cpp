@@ -1,0 +1,340 @@
+// vmm.cpp -- address-stable device memory and restore at the original
+// addresses (Sec. 3.1 and Sec. 3.2, "restoring the CUDA library-allocated
+// regions"): HIP virtual memory management reserves a virtual range at a
+// requested address and maps physical device memory into it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "ckpt_runtime.h"
+
+using namespace ckpt;
+
+namespace {
+
+hipMemAllocationProp device_prop(int device)
+{
+    hipMemAllocationProp prop;
+    memset(&prop, 0, sizeof(prop));
+    prop.type = hipMemAllocationTypePinned;
+    prop.location.type = hipMemLocationTypeDevice;
+    prop.location.id = device;
+    return prop;
+}
+
+int granularity(int device, uint64_t *out)
+{
+    hipMemAllocationProp prop = device_prop(device);
+    size_t g = 0;
+    HIP_TRY(hipMemGetAllocationGranularity(&g, &prop, hipMemAllocationGranularityMinimum));
+    if (g == 0 || (g & (g - 1)) != 0)
+        return set_error(CKPT_E_HIP, "allocation granularity %zu is not a power of two", g);
+    *out = g;
+    return CKPT_OK;
+}
+
+// Reserve [want, want + bytes) (anywhere when want is 0), map fresh device
+// memory there and allow reads and writes from the device.  Nothing is left
+// behind on failure.
+int map_range(ckpt_ctx *ctx, uint64_t want, uint64_t bytes, uint64_t *base)
+{
+    const int dev = ctx->cfg.device;
+    void *p = nullptr;
+    hipError_t e = hipMemAddressReserve(&p, bytes, 0, (void *)(uintptr_t)want, 0);
+    if (e != hipSuccess) {
+        if (want)
+            return set_error(CKPT_E_ADDR, "cannot reserve [0x%llx, +%llu): %s", (unsigned long long)want,
+                             (unsigned long long)bytes, hipGetErrorString(e));
+        return hip_fail(e, "hipMemAddressReserve", __LINE__);
+    }
+    if (want && (uint64_t)(uintptr_t)p != want) {
+        (void)hipMemAddressFree(p, bytes);
+        return set_error(CKPT_E_ADDR, "[0x%llx, +%llu) is not free (the runtime offered %p)",
+                         (unsigned long long)want, (unsigned long long)bytes, p);
+    }
+    hipMemAllocationProp prop = device_prop(dev);
+    hipMemGenericAllocationHandle_t h{};
+    e = hipMemCreate(&h, bytes, &prop, 0);
+    if (e != hipSuccess) {
+        (void)hipMemAddressFree(p, bytes);
+        return set_error(CKPT_E_NOMEM, "hipMemCreate of %llu bytes: %s", (unsigned long long)bytes,
+                         hipGetErrorString(e));
+    }
+    e = hipMemMap(p, bytes, 0, h, 0);
+    if (e == hipSuccess) {
+        hipMemAccessDesc acc;
+        memset(&acc, 0, sizeof(acc));
+        acc.location.type = hipMemLocationTypeDevice;
+        acc.location.id = dev;
+        acc.flags = hipMemAccessFlagsProtReadWrite;
+        e = hipMemSetAccess(p, bytes, &acc, 1);
+        if (e != hipSuccess)
+            (void)hipMemUnmap(p, bytes);
+    }
+    if (e != hipSuccess) {
+        (void)hipMemRelease(h);
+        (void)hipMemAddressFree(p, bytes);
+        return hip_fail(e, "hipMemMap / hipMemSetAccess", __LINE__);
+    }
+    VmmRange r;
+    r.bytes = bytes;
+    r.h = h;
+    ctx->vmm.emplace((uint64_t)(uintptr_t)p, r);
+    *base = (uint64_t)(uintptr_t)p;
+    return CKPT_OK;
+}
+
+void unmap_range(ckpt_ctx *ctx, std::map<uint64_t, VmmRange>::iterator it)
+{
+    void *p = (void *)(uintptr_t)it->first;
+    (void)hipMemUnmap(p, it->second.bytes);
+    (void)hipMemRelease(it->second.h);
+    (void)hipMemAddressFree(p, it->second.bytes);
+    ctx->vmm.erase(it);
+}
+
+// Drop a registration inside a context range; release the range with its last.
+void vmm_drop(ckpt_ctx *ctx, uint64_t start)
+{
+    auto of = ctx->vmm_of.find(start);
+    if (of == ctx->vmm_of.end())
+        return;
+    const uint64_t base = of->second;
+    ctx->vmm_of.erase(of);
+    (void)drop_registration(ctx, start);
+    auto it = ctx->vmm.find(base);
+    if (it != ctx->vmm.end() && --it->second.refs == 0)
+        unmap_range(ctx, it);
+}
+
+// The live registration that overlaps [a, a + n), if any (n 0: starts at a).
+const RangeEnd *overlapping(const ckpt_ctx *ctx, uint64_t a, uint64_t n, uint64_t *start)
+{
+    auto it = ctx->ranges.lower_bound(a);
+    if (it != ctx->ranges.end() && (it->first == a || it->first < a + n)) {
+        *start = it->first;
+        return &it->second;
+    }
+    if (it != ctx->ranges.begin()) {
+        auto pv = std::prev(it);
+        if (a < pv->second.end || (n == 0 && pv->second.end > a)) {
+            *start = pv->first;
+            return &pv->second;
+        }
+    }
+    return nullptr;
+}
+
+}  // namespace
+
+void ckpt::vmm_release_all(ckpt_ctx *ctx)
+{
+    if (ctx->vmm.empty())
+        return;
+    (void)hipDeviceSynchronize();
+    while (!ctx->vmm.empty())
+        unmap_range(ctx, ctx->vmm.begin());
+    ctx->vmm_of.clear();
+}
+
+extern "C" int ckpt_vmm_granularity(ckpt_ctx *ctx, size_t *out)
+{
+    if (!ctx || !out)
+        return set_error(CKPT_E_INVAL, "ctx or out is NULL");
+    DeviceGuard dg(ctx->cfg.device);
+    uint64_t g = 0;
+    CKPT_TRY(granularity(ctx->cfg.device, &g));
+    *out = g;
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_vmm_alloc(ckpt_ctx *ctx, size_t bytes, void *addr, void **out, ckpt_id *id)
+{
+    if (!ctx || !out || !id)
+        return set_error(CKPT_E_INVAL, "ctx, out or id is NULL");
+    if (bytes == 0)
+        return set_error(CKPT_E_INVAL, "ckpt_vmm_alloc of 0 bytes");
+    HookGuard hg(ctx);
+    DeviceGuard dg(ctx->cfg.device);
+    uint64_t g = 0;
+    CKPT_TRY(granularity(ctx->cfg.device, &g));
+    const uint64_t want = (uint64_t)(uintptr_t)addr;
+    if (want % g != 0)
+        return set_error(CKPT_E_INVAL, "address %p is not a multiple of the granularity %llu", addr,
+                         (unsigned long long)g);
+    const uint64_t span = (bytes + g - 1) / g * g;
+    if (span < bytes)
+        return set_error(CKPT_E_INVAL, "size %zu overflows", bytes);
+    uint64_t s0 = 0;
+    if (want && overlapping(ctx, want, span, &s0))
+        return set_error(CKPT_E_ADDR, "[%p, +%llu) overlaps a live registration", addr, (unsigned long long)span);
+    uint64_t base = 0;
+    CKPT_TRY(map_range(ctx, want, span, &base));
+    uint64_t rid = 0;
+    const int rc = add_registration(ctx, base, bytes, CKPT_DEVICE, 0, &rid);
+    if (rc != CKPT_OK) {
+        unmap_range(ctx, ctx->vmm.find(base));
+        return rc;
+    }
+    ctx->vmm[base].refs = 1;
+    ctx->vmm_of[base] = base;
+    *out = (void *)(uintptr_t)base;
+    *id = rid;
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_vmm_free(ckpt_ctx *ctx, void *ptr)
+{
+    if (!ctx)
+        return set_error(CKPT_E_INVAL, "ctx is NULL");
+    HookGuard hg(ctx);
+    const uint64_t start = (uint64_t)(uintptr_t)ptr;
+    if (!ctx->vmm_of.count(start))
+        return set_error(CKPT_E_NOTFOUND, "%p is not memory of the context", ptr);
+    DeviceGuard dg(ctx->cfg.device);
+    // the range may still be in use by work the caller queued on the device
+    HIP_TRY(hipDeviceSynchronize());
+    vmm_drop(ctx, start);
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_restore_at(ckpt_ctx *ctx, void *stream, const ckpt_image *img, const ckpt_image *delta,
+                               void **addrs_out, ckpt_verify_report *rep)
+{
+    if (!ctx || !img)
+        return set_error(CKPT_E_INVAL, "ctx or image is NULL");
+    const uint64_t n = img->allocs.size();
+    if (img->addrs.size() != n)
+        return set_error(CKPT_E_INVAL, "image has no address section");
+    HookGuard hg(ctx);
+    DeviceGuard dg(ctx->cfg.device);
+    uint64_t g = 0;
+    CKPT_TRY(granularity(ctx->cfg.device, &g));
+
+    // 1. classify: refill a matching live registration, or re-create
+    std::vector<char> create(n, 0);
+    for (uint64_t k = 0; k < n; k++) {
+        const ckpt_alloc_rec &r = img->allocs[k];
+        const uint64_t a = img->addrs[k];
+        if (a == 0 && r.size != 0)
+            return set_error(CKPT_E_INVAL, "allocation %llu has no recorded address", (unsigned long long)k);
+        if (a % 16 != 0)
+            return set_error(CKPT_E_INVAL, "allocation %llu: address 0x%llx is not 16-byte aligned",
+                             (unsigned long long)k, (unsigned long long)a);
+        uint64_t s0 = 0;
+        const RangeEnd *hit = overlapping(ctx, a, r.size, &s0);
+        if (hit) {
+            const auto row = std::lower_bound(ctx->live.begin(), ctx->live.end(), hit->id,
+                                              [](const Reg &x, uint64_t v) { return x.id < v; });
+            if (s0 == a && hit->end == a + r.size && row != ctx->live.end() && row->kind == r.kind)
+                continue;
+            return set_error(CKPT_E_ADDR, "allocation %llu at [0x%llx, +%llu) overlaps registration [0x%llx, 0x%llx)",
+                             (unsigned long long)k, (unsigned long long)a, (unsigned long long)r.size,
+                             (unsigned long long)s0, (unsigned long long)hit->end);
+        }
+        if (r.kind != CKPT_DEVICE)
+            return set_error(CKPT_E_INVAL, "allocation %llu is managed memory and cannot be re-created at 0x%llx",
+                             (unsigned long long)k, (unsigned long long)a);
+        create[k] = 1;
+    }
+    // two allocations of the image may not overlap each other
+    {
+        std::vector<std::pair<uint64_t, uint64_t>> iv;
+        for (uint64_t k = 0; k < n; k++)
+            if (img->allocs[k].size)
+                iv.emplace_back(img->addrs[k], img->addrs[k] + img->allocs[k].size);
+        std::sort(iv.begin(), iv.end());
+        for (size_t i = 1; i < iv.size(); i++)
+            if (iv[i].first < iv[i - 1].second)
+                return set_error(CKPT_E_INVAL, "allocations of the image overlap at 0x%llx",
+                                 (unsigned long long)iv[i].first);
+    }
+
+    // 2. granule-aligned ranges covering the allocations to re-create; ranges
+    //    that touch share a mapping
+    struct Span {
+        uint64_t lo, hi;
+    };
+    std::vector<Span> spans;
+    {
+        std::vector<Span> raw;
+        for (uint64_t k = 0; k < n; k++)
+            if (create[k] && img->allocs[k].size) {
+                const uint64_t a = img->addrs[k], e = a + img->allocs[k].size;
+                raw.push_back({a / g * g, (e + g - 1) / g * g});
+            }
+        std::sort(raw.begin(), raw.end(), [](const Span &x, const Span &y) { return x.lo < y.lo; });
+        for (const Span &s : raw) {
+            if (!spans.empty() && s.lo <= spans.back().hi)
+                spans.back().hi = std::max(spans.back().hi, s.hi);
+            else
+                spans.push_back(s);
+        }
+        for (const Span &s : spans) {
+            uint64_t s0 = 0;
+            if (overlapping(ctx, s.lo, s.hi - s.lo, &s0))
+                return set_error(CKPT_E_ADDR, "range [0x%llx, 0x%llx) holds a live registration at 0x%llx",
+                                 (unsigned long long)s.lo, (unsigned long long)s.hi, (unsigned long long)s0);
+        }
+    }
+
+    // 3. map and register; undo everything on failure
+    std::vector<uint64_t> made_ranges, made_regs;
+    auto undo = [&]() {
+        for (uint64_t st : made_regs) {
+            ctx->vmm_of.erase(st);
+            (void)drop_registration(ctx, st);
+        }
+        for (uint64_t b : made_ranges) {
+            auto it = ctx->vmm.find(b);
+            if (it != ctx->vmm.end())
+                unmap_range(ctx, it);
+        }
+    };
+    for (const Span &s : spans) {
+        uint64_t base = 0;
+        const int rc = map_range(ctx, s.lo, s.hi - s.lo, &base);
+        if (rc != CKPT_OK) {
+            undo();
+            return rc;
+        }
+        made_ranges.push_back(base);
+    }
+    for (uint64_t k = 0; k < n; k++) {
+        if (!create[k])
+            continue;
+        const ckpt_alloc_rec &r = img->allocs[k];
+        const uint64_t a = img->addrs[k];
+        uint64_t rid = 0;
+        int rc = add_registration(ctx, a, r.size, CKPT_DEVICE, r.id, &rid);
+        if (rc != CKPT_OK) {
+            undo();
+            return rc;
+        }
+        made_regs.push_back(a);
+        if (r.size) {
+            // the span that holds it: the last with lo <= a
+            auto sp = std::upper_bound(spans.begin(), spans.end(), a,
+                                       [](uint64_t v, const Span &x) { return v < x.lo; });
+            const uint64_t base = std::prev(sp)->lo;
+            ctx->vmm_of[a] = base;
+            ctx->vmm[base].refs++;
+        }
+    }
+
+    // 4. refill and verify at those addresses
+    std::vector<void *> dst(n);
+    for (uint64_t k = 0; k < n; k++)
+        dst[k] = (void *)(uintptr_t)img->addrs[k];
+    const int rc = ckpt_restore(ctx, stream, img, delta, n ? dst.data() : nullptr, nullptr, n, rep);
+    if (rc != CKPT_OK && rc != CKPT_E_CORRUPT) {
+        (void)hipDeviceSynchronize();
+        undo();
+        return rc;
+    }
+    if (addrs_out)
+        for (uint64_t k = 0; k < n; k++)
+            addrs_out[k] = dst[k];
+    return rc;
+}

@@ -142,3 +142,19 @@ def prefetch_to_host(ptr, nbytes):
     rc = hip.hipMemPrefetchAsync(ptr, nbytes, -1, None)
     hip.hipDeviceSynchronize()
     return rc == 0
+
+
+def hip_malloc(nbytes):
+    """Plain hipMalloc; returns the address."""
+    import ctypes
+    hip = _hipapi()
+    hip.hipMalloc.restype = ctypes.c_int
+    hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    p = ctypes.c_void_p()
+    rc = hip.hipMalloc(ctypes.byref(p), max(nbytes, 1))
+    assert rc == 0, "hipMalloc failed: %d" % rc
+    return p.value
+
+
+def hip_free(ptr):
+    managed_free(ptr)

@@ -1,0 +1,110 @@
+"""Child process of the allocation-hook tests (run as `python -m tests.hook_child`).
+
+torch takes a new allocator only before its first device allocation, so each
+mode runs in a fresh process and prints one JSON line:
+
+  log           install the hook, allocate and free tensors, and check that
+                the context's live set is exactly the live tensors, in
+                allocation order, and that the checkpoint equals the oracle's;
+  save PATH     the same with address-stable memory, then write the image to
+                PATH and print each tensor's address and SHA-256;
+  restore PATH  without the hook, restore the image at its addresses and print
+                the SHA-256 of the bytes found there.
+"""
+import hashlib
+import json
+import sys
+
+import numpy as np
+import torch
+
+from paper_2008_10596_amd import ckpt as K
+
+C = 4096
+
+
+def tensors():
+    """Seeded tensors, some freed again, made with elementwise ops only (no
+    library workspaces).  Returns the live ones in allocation order."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(12701)
+    a = torch.randn(1000, generator=g, device="cuda")
+    b = torch.zeros(5000, dtype=torch.uint8, device="cuda")
+    tmp = a * 3.0
+    c = torch.arange(70000, dtype=torch.int32, device="cuda")
+    d = (tmp + 1.0).sin()
+    del tmp
+    e = torch.randint(0, 256, (3 * 4096 + 17,), dtype=torch.uint8, generator=g, device="cuda")
+    f = torch.empty(64, dtype=torch.float64, device="cuda").fill_(2.5)
+    del c
+    w = torch.nn.Parameter(torch.randn(64, 32, generator=g, device="cuda"))
+    torch.cuda.synchronize()
+    return [a, b, d, e, f, w]
+
+
+def host_bytes(t):
+    return t.detach().contiguous().view(torch.uint8).reshape(-1).cpu().numpy()
+
+
+def check(ctx, live, img):
+    from oracle import oracle as O
+    from paper_2008_10596_amd import hook
+    st = hook.stats()
+    ref = O.checkpoint([host_bytes(t) for t in live], C)
+    return {
+        "live_count": ctx.live_count(), "n_live": len(live),
+        "stats_live": st["allocs"] - st["frees"], "failures": st["failures"],
+        "order": [int(x) for x in img.addrs] == [t.data_ptr() for t in live],
+        "crc": bool(np.array_equal(img.crc, ref["crc"])),
+        "flags": bool(np.array_equal(img.flags, ref["flags"])),
+        "data": bool(np.array_equal(img.data, ref["serialized"])),
+    }
+
+
+def run_log():
+    from paper_2008_10596_amd import hook
+    ctx = K.Context(chunk_bytes=C)
+    hook.install(ctx)
+    live = tensors()
+    img = ctx.checkpoint()
+    out = check(ctx, live, img)
+    del live
+    torch.cuda.synchronize()
+    out["after_free"] = ctx.live_count()
+    print(json.dumps(out), flush=True)
+
+
+def run_save(path):
+    from paper_2008_10596_amd import hook
+    ctx = K.Context(chunk_bytes=C)
+    hook.install(ctx, address_stable=True)
+    live = tensors()
+    img = ctx.checkpoint()
+    out = check(ctx, live, img)
+    with open(path, "wb") as f:
+        f.write(img.serialize())
+    out["addrs"] = [t.data_ptr() for t in live]
+    out["sha"] = [hashlib.sha256(host_bytes(t).tobytes()).hexdigest() for t in live]
+    print(json.dumps(out), flush=True)
+
+
+def run_restore(path):
+    from tests.gpu_common import d2h
+    with open(path, "rb") as f:
+        blob = f.read()
+    ctx = K.Context(chunk_bytes=C)
+    img = K.Image.load(blob, ctx)
+    rc, rep, addrs = ctx.restore_at(img)
+    sizes = [int(s) for s in img.allocs["size"]]
+    sha = [hashlib.sha256(d2h(p, s).tobytes()).hexdigest() for p, s in zip(addrs, sizes)]
+    print(json.dumps({"rc": rc, "n_bad": rep["n_bad"], "addrs": addrs, "sha": sha}), flush=True)
+
+
+if __name__ == "__main__":
+    mode = sys.argv[1]
+    if mode == "log":
+        run_log()
+    elif mode == "save":
+        run_save(sys.argv[2])
+    else:
+        run_restore(sys.argv[2])

@@ -54,11 +54,11 @@ def test_binding_declares_every_symbol(ck):
 def test_strerror_covers_every_status(ck):
     lib = ck.lib()
     seen = set()
-    for st in range(0, -9, -1):
+    for st in range(0, -10, -1):
         s = lib.ckpt_strerror(st).decode()
         assert s and s != "unknown status"
         seen.add(s)
-    assert len(seen) == 9
+    assert len(seen) == 10
     assert lib.ckpt_strerror(-100).decode() == "unknown status"
 
 
@@ -97,5 +97,9 @@ def test_null_arguments_are_rejected(ck):
     assert lib.ckpt_checkpoint(None, None, 0, None, None) == ck.CKPT_E_INVAL
     assert lib.ckpt_restore(None, None, None, None, None, None, 0, None) == ck.CKPT_E_INVAL
     assert lib.ckpt_image_info(None, None) == ck.CKPT_E_INVAL
+    assert lib.ckpt_vmm_granularity(None, None) == ck.CKPT_E_INVAL
+    assert lib.ckpt_vmm_alloc(None, 4096, None, None, None) == ck.CKPT_E_INVAL
+    assert lib.ckpt_vmm_free(None, None) == ck.CKPT_E_INVAL
+    assert lib.ckpt_restore_at(None, None, None, None, None, None) == ck.CKPT_E_INVAL
     lib.ckpt_destroy(None)
     lib.ckpt_image_free(None)

@@ -315,8 +315,18 @@ def test_serialize_load_roundtrip_and_restore():
     blob = img.serialize()
     img2 = K.Image.load(blob, ctx)
     assert img2.serialize() == blob
-    for name in ("crc", "flags", "data", "allocs"):
+    for name in ("crc", "flags", "data", "allocs", "addrs"):
         assert np.array_equal(getattr(img2, name), getattr(img, name)), name
+    assert list(img.addrs) == [t.data_ptr() for t in tensors]
+    # version-1 data (no address section) still loads, with addresses 0
+    n = len(tensors)
+    v1 = bytearray(blob[:88 + n * 40] + blob[88 + n * 48:])
+    v1[8:12] = (1).to_bytes(4, "little")
+    img1 = K.Image.load(bytes(v1), ctx)
+    assert list(img1.addrs) == [0] * n
+    for name in ("crc", "flags", "data", "allocs"):
+        assert np.array_equal(getattr(img1, name), getattr(img, name)), name
+    img1.close()
     dsts = [torch.empty_like(t) for t in tensors]
     rc, _ = ctx.restore(img2, dsts)
     assert rc == K.CKPT_OK
@@ -326,7 +336,7 @@ def test_serialize_load_roundtrip_and_restore():
         K.Image.load(blob[:-1], ctx)
     assert e.value.status == K.CKPT_E_INVAL
     bad = bytearray(blob)
-    bad[88 + 3 * 40 + 2] ^= 1                   # inside the CRC section
+    bad[88 + 3 * 48 + 2] ^= 1                   # inside the CRC section
     with pytest.raises(K.CkptError) as e:
         K.Image.load(bytes(bad), ctx)
     assert e.value.status == K.CKPT_E_INVAL
