@@ -214,3 +214,40 @@ def restore_delta(bufs, sizes, C, crc, flags, dirty_ids, delta_data):
     if rc < 0:
         raise ValueError("delta ids or data inconsistent with the flags")
     return int(cnt[0]), ids[:int(nids[0])]
+
+
+def delta_by_id(allocs, ids, kinds, C, base_ids, base_kinds, base_sizes, base_crc):
+    """Incremental checkpoint of `allocs` (registration ids `ids`, kinds
+    `kinds`) against a base whose allocation table may differ.
+
+    The paper fixes no incremental scheme; the reading here: a chunk is
+    compared with the same chunk of the base allocation that has the same
+    registration id, size and kind, and every chunk of an allocation without
+    such a base allocation is DIRTY.  Allocations of the base that are gone
+    play no part.  CRC and ZERO come from the full checkpoint; DIRTY, the
+    dirty ids and the delta data follow chunk by chunk (plain loops: small
+    inputs only)."""
+    allocs = [_bytes(a) for a in allocs]
+    sizes = [int(a.size) for a in allocs]
+    full = checkpoint(allocs, C, dense=False, serialized=False)
+    _, cb, _, N = layout(sizes, C)
+    _, bcb, _, _ = layout([int(s) for s in base_sizes], C)
+    base_crc = np.ascontiguousarray(base_crc, dtype=np.uint32)
+    base_row = {int(i): j for j, i in enumerate(base_ids)}
+    flags = (full["flags"] & FLAG_ZERO).astype(np.uint8)
+    out = []
+    for k, a in enumerate(allocs):
+        j = base_row.get(int(ids[k]))
+        match = (j is not None and int(base_sizes[j]) == sizes[k] and int(base_kinds[j]) == int(kinds[k]))
+        for c in range((sizes[k] + C - 1) // C):
+            g = int(cb[k]) + c
+            if match and full["crc"][g] == base_crc[int(bcb[j]) + c]:
+                continue
+            flags[g] |= FLAG_DIRTY
+            if not flags[g] & FLAG_ZERO:
+                piece = a[c * C:min(sizes[k], (c + 1) * C)]
+                out.append(piece)
+                out.append(np.zeros((-piece.size) % 16, np.uint8))
+    data = np.concatenate(out) if out else np.zeros(0, np.uint8)
+    return {"crc": full["crc"], "flags": flags, "dirty_ids": np.nonzero(flags & FLAG_DIRTY)[0].astype(np.uint64),
+            "delta": data}
