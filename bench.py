@@ -660,6 +660,20 @@ def main():
             "first_64_allocations_equal": ok,
         }
         log("restore: %s" % result["restore"])
+        # the drained image to a file (durable storage), when the file system has room
+        sink_dir = os.environ.get("TMPDIR", "/tmp")
+        need = img.info()["serialized_bytes"] * 2
+        st = os.statvfs(sink_dir)
+        if st.f_bavail * st.f_frsize > need:
+            path = os.path.join(sink_dir, "ckpt_bench_%d.img" % os.getpid())
+            t0 = time.perf_counter()
+            nbytes = img.write_file(path)
+            w_s = time.perf_counter() - t0
+            os.unlink(path)
+            result["sink"] = {"file_bytes": nbytes, "write_s": round(w_s, 3),
+                              "gbps": round(nbytes / w_s / 1e9, 2), "dir": sink_dir,
+                              "mode": "O_DIRECT (buffered where refused), fsync"}
+            log("sink: %s" % result["sink"])
         img.close()
         del dsts
         dctx.close()

@@ -82,7 +82,8 @@ enum ckpt_status {
     CKPT_E_CORRUPT = -6,   /* restore: some chunk's CRC did not verify           */
     CKPT_E_AGAIN = -7,     /* server: request not finished yet                   */
     CKPT_E_BUDGET = -8,    /* request larger than the staging budget              */
-    CKPT_E_ADDR = -9       /* the address range asked for is not free               */
+    CKPT_E_ADDR = -9,      /* the address range asked for is not free               */
+    CKPT_E_IO = -10        /* a file could not be created, written or read          */
 };
 
 /* ckpt_config.flags */
@@ -241,11 +242,16 @@ int ckpt_live_count(const ckpt_ctx *ctx, size_t *out);
  * when the image is complete.
  *
  * mode CKPT_FULL: base may be NULL (every chunk DIRTY) or an image of the same
- *   allocation table and chunk size (DIRTY against it).  DATA = non-ZERO chunks.
- * mode CKPT_INCREMENTAL: base is required and must have the same allocation
- *   table (ids, kinds, sizes) and chunk size, else CKPT_E_MISMATCH.  DATA =
- *   DIRTY non-ZERO chunks; DIRTY_IDS = every DIRTY chunk; CRC and FLAGS are
- *   complete, so the result can be the base of the next increment.
+ *   chunk size (DIRTY against it).  DATA = non-ZERO chunks.
+ * mode CKPT_INCREMENTAL: base is required and must have the same chunk size,
+ *   else CKPT_E_MISMATCH.  DATA = DIRTY non-ZERO chunks; DIRTY_IDS = every
+ *   DIRTY chunk; CRC and FLAGS are complete, so the result can be the base of
+ *   the next increment.
+ * The allocation table may differ from the base's (allocations made and
+ * freed in between): a chunk is compared with the same chunk of the base
+ * allocation with the same id, size and kind; every chunk of an allocation
+ * without such a match is DIRTY.  ckpt_image_merge folds such an increment
+ * into its base, and ckpt_restore does so by itself.
  * CKPT_E_BUDGET if the dense image exceeds the staging budget.
  */
 int ckpt_checkpoint(ckpt_ctx *ctx, void *stream, int mode, const ckpt_image *base,
@@ -262,9 +268,12 @@ int ckpt_checkpoint(ckpt_ctx *ctx, void *stream, int mode, const ckpt_image *bas
  * each verified against the delta's CRC.  Runs on `stream` and returns when
  * the destination memory is written.
  *
+ * When the delta's allocation table differs from img's, the two are merged
+ * first (ckpt_image_merge) and dst follows the delta's table.
+ *
  * CKPT_E_MISMATCH: n_dst differs from the image's allocation count, a
- *   dst_bytes entry is smaller than its allocation, or the delta's allocation
- *   table / chunk size / base serial does not match img.
+ *   dst_bytes entry is smaller than its allocation, or the delta's chunk size
+ *   or base serial does not match img.
  * CKPT_E_INVAL: image without host DATA, misaligned dst.
  * CKPT_E_CORRUPT: some chunk failed; rep (if given) holds the number of
  *   distinct failing chunk ids and the smallest 64, ascending.
@@ -335,6 +344,23 @@ int ckpt_vmm_free(ckpt_ctx *ctx, void *ptr);
 int ckpt_restore_at(ckpt_ctx *ctx, void *stream, const ckpt_image *img, const ckpt_image *delta,
                     void **addrs_out, ckpt_verify_report *rep);
 
+/*
+ * The restart path: restore the full image in file `path` (written by
+ * ckpt_image_write_file or ckpt_image_serialize) at its recorded addresses.
+ * The paper's restart re-creates every allocation before copying the data
+ * back (Sec. 3.2), and so does this call: it reads the file into ordinary host
+ * memory, checks its tables, reserves and maps every address range -- before
+ * it allocates any device or pinned memory of its own, so that a fresh
+ * process's runtime has placed nothing there yet -- and only then loads the
+ * image and refills the allocations in place, verifying every chunk.  Call
+ * it before other device allocations of the process.
+ * img_out (optional) receives the loaded image (the base for incremental
+ * checkpoints that follow); else it is freed.  Errors as ckpt_restore_at,
+ * plus CKPT_E_NOTFOUND / CKPT_E_IO for the file.
+ */
+int ckpt_restore_file_at(ckpt_ctx *ctx, void *stream, const char *path, void **addrs_out,
+                         ckpt_verify_report *rep, ckpt_image **img_out);
+
 /* ------------------------------------------------- automatic registration
  *
  * The paper interposes on the cudaMalloc family, so every allocation and
@@ -379,6 +405,43 @@ void ckpt_hook_free(void *ptr, size_t bytes, int device, void *stream);
 int ckpt_hook_stats(uint64_t *allocs, uint64_t *frees, uint64_t *failures);
 
 /* ----------------------------------------------------------------- image */
+
+/*
+ * Fold an incremental image into the full image it was taken against: the
+ * result is the full image (every chunk DIRTY, no base) that a checkpoint at
+ * the increment's time would have given -- the increment's allocation table,
+ * CRC, flags and addresses, each non-ZERO chunk's bytes from the increment
+ * when DIRTY there, else from the same chunk of the base allocation with the
+ * same id, size and kind.  The result carries the increment's serial (it
+ * stands for the same state), so a chain base <- d1 <- d2 folds as
+ * merge(merge(base, d1), d2).  Runs on the host; both images need host DATA.
+ * CKPT_E_INVAL: base not full, delta not incremental, or no host DATA.
+ * CKPT_E_MISMATCH: delta was not taken against base (serial, chunk size).
+ * CKPT_E_CORRUPT: the delta marks a chunk clean that has no equal base chunk,
+ *   or its DATA size disagrees with its flags.
+ */
+int ckpt_image_merge(const ckpt_image *base, const ckpt_image *delta, ckpt_image **out);
+
+/*
+ * Write the image's serialized form (the bytes ckpt_image_serialize gives) to
+ * the file `path`, so that it reaches durable storage as the paper's
+ * checkpoints do (DMTCP writes each process's image to a file).  The bytes go
+ * out in 64 MiB blocks, staged through aligned buffers while the previous
+ * block is written, with O_DIRECT unless CKPT_FILE_BUFFERED is given or the
+ * file system refuses it; then fsync.  The file is written as path.partial
+ * and renamed to path once complete, so path never holds a partial image.
+ * *bytes (optional) receives the file size.  CKPT_E_IO on a failing file
+ * operation (the partial file is removed); CKPT_E_INVAL for an image without
+ * host DATA.
+ */
+#define CKPT_FILE_BUFFERED 0x1u   /* write through the page cache */
+int ckpt_image_write_file(const ckpt_image *img, const char *path, uint32_t flags, uint64_t *bytes);
+
+/* Read an image file written by ckpt_image_write_file (or any serialized
+ * image) and load it as ckpt_image_load does.  CKPT_E_NOTFOUND if the file
+ * cannot be opened, CKPT_E_IO if it cannot be read, and ckpt_image_load's
+ * errors for its contents. */
+int ckpt_image_read_file(ckpt_ctx *ctx, const char *path, ckpt_image **out);
 
 int ckpt_image_info(const ckpt_image *img, ckpt_image_meta *out);
 

@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libckpt.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "crc_tables.cpp", "runtime.cpp", "server.cpp", "vmm.cpp", "hook.cpp"]
+SOURCES = ["kernels.hip", "crc_tables.cpp", "runtime.cpp", "server.cpp", "vmm.cpp", "hook.cpp", "sink.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

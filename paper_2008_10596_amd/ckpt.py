@@ -24,7 +24,8 @@ CKPT_FULL, CKPT_INCREMENTAL = 0, 1
 CKPT_OK = 0
 CKPT_E_INVAL, CKPT_E_NOTFOUND, CKPT_E_NOMEM, CKPT_E_HIP = -1, -2, -3, -4
 CKPT_E_MISMATCH, CKPT_E_CORRUPT, CKPT_E_AGAIN, CKPT_E_BUDGET = -5, -6, -7, -8
-CKPT_E_ADDR = -9
+CKPT_E_ADDR, CKPT_E_IO = -9, -10
+CKPT_FILE_BUFFERED = 0x1
 CKPT_STREAM_ORDERED = 0x1
 CKPT_KEEP_DENSE = 0x2
 CKPT_NO_DRAIN = 0x4
@@ -40,7 +41,7 @@ CKPT_REQ_CHECKPOINT, CKPT_REQ_RESTORE = 0, 1
 
 STATUS_NAMES = {0: "CKPT_OK", -1: "CKPT_E_INVAL", -2: "CKPT_E_NOTFOUND", -3: "CKPT_E_NOMEM",
                 -4: "CKPT_E_HIP", -5: "CKPT_E_MISMATCH", -6: "CKPT_E_CORRUPT", -7: "CKPT_E_AGAIN",
-                -8: "CKPT_E_BUDGET", -9: "CKPT_E_ADDR"}
+                -8: "CKPT_E_BUDGET", -9: "CKPT_E_ADDR", -10: "CKPT_E_IO"}
 
 
 class ckpt_config(ctypes.Structure):
@@ -130,6 +131,9 @@ SIGNATURES = [
     ("ckpt_image_serialize", ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     ("ckpt_image_load", ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]),
     ("ckpt_image_free", None, [_vp]),
+    ("ckpt_image_merge", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp)]),
+    ("ckpt_image_write_file", ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]),
+    ("ckpt_image_read_file", ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.POINTER(_vp)]),
     ("ckpt_checkpoint_batch", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
     ("ckpt_vmm_granularity", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     ("ckpt_vmm_alloc", ctypes.c_int, [_vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_uint64)]),
@@ -139,6 +143,8 @@ SIGNATURES = [
     ("ckpt_hook_malloc", _vp, [ctypes.c_size_t, ctypes.c_int, _vp]),
     ("ckpt_hook_free", None, [_vp, ctypes.c_size_t, ctypes.c_int, _vp]),
     ("ckpt_hook_stats", ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64)] * 3),
+    ("ckpt_restore_file_at", ctypes.c_int, [_vp, _vp, ctypes.c_char_p, ctypes.POINTER(_vp),
+                                             ctypes.POINTER(ckpt_verify_report), ctypes.POINTER(_vp)]),
     ("ckpt_last_timing", ctypes.c_int, [_vp, ctypes.POINTER(ckpt_timing)]),
     ("ckpt_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("ckpt_last_hip_error", ctypes.c_int, []),
@@ -285,6 +291,21 @@ class Image:
                "ckpt_image_serialize")
         return bytes(buf)
 
+    def write_file(self, path, buffered=False):
+        """Write the serialized image to path (O_DIRECT unless buffered);
+        returns the file size."""
+        n = ctypes.c_uint64()
+        _check(lib().ckpt_image_write_file(self.handle, os.fsencode(path), CKPT_FILE_BUFFERED if buffered else 0,
+                                           ctypes.byref(n)), "ckpt_image_write_file")
+        return n.value
+
+    @staticmethod
+    def read_file(path, ctx=None):
+        out = _vp()
+        _check(lib().ckpt_image_read_file(ctx.handle if ctx else None, os.fsencode(path), ctypes.byref(out)),
+               "ckpt_image_read_file")
+        return Image(out.value)
+
     @staticmethod
     def load(buf, ctx=None):
         b = (ctypes.c_uint8 * len(buf)).from_buffer_copy(buf)
@@ -387,10 +408,41 @@ class Context:
         return rc, {"n_bad": rep.n_bad, "ids": [rep.ids[i] for i in range(rep.n_ids)]}, \
             [out[k] or 0 for k in range(n)]
 
+    def restore_file_at(self, path, n_allocs=None, stream=None, raise_on_corrupt=False):
+        """The restart path: restore the image file at its recorded addresses,
+        reserving them before any other device memory of this call.  Returns
+        (status, report dict, addresses, Image)."""
+        if n_allocs is None:
+            with open(path, "rb") as f:
+                head = f.read(32)
+            n_allocs = int.from_bytes(head[24:32], "little")
+        out = (_vp * max(n_allocs, 1))()
+        rep = ckpt_verify_report()
+        img = _vp()
+        rc = lib().ckpt_restore_file_at(self.handle, _stream_handle(stream), os.fsencode(path), out,
+                                        ctypes.byref(rep), ctypes.byref(img))
+        if rc not in (CKPT_OK, CKPT_E_CORRUPT) or (rc == CKPT_E_CORRUPT and raise_on_corrupt):
+            raise CkptError(rc, "ckpt_restore_file_at")
+        return rc, {"n_bad": rep.n_bad, "ids": [rep.ids[i] for i in range(rep.n_ids)]}, \
+            [out[k] or 0 for k in range(n_allocs)], Image(img.value)
+
     def timing(self):
         t = ckpt_timing()
         _check(lib().ckpt_last_timing(self.handle, ctypes.byref(t)), "ckpt_last_timing")
         return {f: getattr(t, f) for f, _ in ckpt_timing._fields_ if f != "pad"}
+
+
+def merge(base, *deltas):
+    """Fold a chain of incremental images (each taken against the previous
+    one, the first against base) into one full image."""
+    img = base
+    for d in deltas:
+        out = _vp()
+        _check(lib().ckpt_image_merge(img.handle, d.handle, ctypes.byref(out)), "ckpt_image_merge")
+        if img is not base:
+            img.close()
+        img = Image(out.value)
+    return img
 
 
 def checkpoint_batch(ctxs, stream=None):

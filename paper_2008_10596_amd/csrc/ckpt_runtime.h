@@ -114,6 +114,16 @@ struct VmmRange {
     uint64_t bytes = 0;                    // multiple of the allocation granularity
     hipMemGenericAllocationHandle_t h{};   // the physical memory mapped there
     uint32_t refs = 0;                     // live registrations inside the range
+    bool in_window = false;                // its addresses belong to a VmmWindow
+};
+
+// A large region of virtual addresses the context picked once; address-stable
+// allocations without a requested address are placed in it from the bottom
+// up (each with its own reservation), far below the addresses the runtime
+// hands out for its own use.
+struct VmmWindow {
+    uint64_t base = 0, usable = 0;        // [base, base + usable)
+    std::map<uint64_t, uint64_t> free;    // spots not booked: start -> bytes
 };
 
 // Registration with a given id when it is still unissued in the context (at or
@@ -122,6 +132,24 @@ int add_registration(ckpt_ctx *ctx, uint64_t start, uint64_t bytes, uint32_t kin
                      uint64_t *id);
 int drop_registration(ckpt_ctx *ctx, uint64_t start);
 void vmm_release_all(ckpt_ctx *ctx);
+// When delta's allocation table differs from img's, *merged = the two folded
+// into one full image (ckpt_image_merge); else *merged stays empty.
+int fold_delta(const ckpt_image *img, const ckpt_image *delta, std::unique_ptr<ckpt_image> *merged);
+// A serialized image's header and tables, checked, without the CRC, flag,
+// id and DATA sections (which start at `rest`).  Host memory only.
+struct ImageHead {
+    uint32_t version = 0, mode = 0, C = 0;
+    uint64_t N = 0, data_bytes = 0, ser_bytes = 0, n_dirty = 0, serial = 0, base_serial = 0, digest = 0;
+    std::vector<ckpt_alloc_rec> allocs;
+    std::vector<uint64_t> addrs;
+    const uint8_t *rest = nullptr;
+};
+int parse_head(const void *buf, size_t bytes, ImageHead *h);
+int read_whole_file(const char *path, std::vector<uint8_t> *buf);
+
+// The serialized form up to (not including) DATA, which follows it.
+size_t serialized_head_bytes(const ckpt_image *img);
+void serialize_head(const ckpt_image *img, uint8_t *out);
 
 // The allocation hook (ckpt_hook_*) and the calls on the context it logs into
 // are serialized by one process-wide lock, held only for a hooked context.
@@ -158,13 +186,14 @@ struct ckpt_ctx {
     // base of each registration made inside one
     std::map<uint64_t, ckpt::VmmRange> vmm;
     std::map<uint64_t, uint64_t> vmm_of;
+    std::vector<ckpt::VmmWindow> windows;
     std::atomic<bool> hooked{false};   // the allocation hook logs into this context
 
     // device buffers
     ckpt::DevBuf d_tables, d_plan, d_addr, d_size, d_off, d_cb, d_map;
     ckpt::DevBuf d_crc, d_flags, d_base_crc, d_prev_crc, d_soff, d_ids, d_tile_b, d_tile_c;
-    ckpt::DevBuf d_dense, d_compact, d_bad, d_pick, d_crc2, d_flags2, d_soff2;
-    ckpt::PinnedBuf h_up, h_plan;
+    ckpt::DevBuf d_dense, d_compact, d_bad, d_pick, d_crc2, d_flags2, d_soff2, d_base_cb;
+    ckpt::PinnedBuf h_up, h_plan, h_base_cb;
     uint64_t prev_serial = 0;   // image whose CRC array is in d_prev_crc
 
     ckpt_timing timing{};
@@ -173,7 +202,7 @@ struct ckpt_ctx {
     {
         return {&d_tables, &d_plan, &d_addr, &d_size, &d_off, &d_cb, &d_map, &d_crc, &d_flags, &d_base_crc,
                 &d_prev_crc, &d_soff, &d_ids, &d_tile_b, &d_tile_c, &d_dense, &d_compact, &d_bad, &d_pick,
-                &d_crc2, &d_flags2, &d_soff2};
+                &d_crc2, &d_flags2, &d_soff2, &d_base_cb};
     }
 };
 

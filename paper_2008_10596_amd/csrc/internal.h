@@ -62,6 +62,8 @@ struct DevPlan {
 
 enum ChunkMode { kModePack = 0, kModeHash = 1, kModeRestore = 2 };
 
+constexpr uint64_t kNoBase = ~0ull;
+
 struct ChunkArgs {
     const DevPlan *plan;
     const uint32_t *tables;   // kTabTotalWords words
@@ -83,6 +85,9 @@ struct ChunkArgs {
     uint32_t *crc;
     uint8_t *flags;
     const uint32_t *base_crc; // nullable
+    const uint64_t *base_cb;  // nullable: the base's first chunk id for each
+                              // allocation (kNoBase: no matching allocation in
+                              // the base); null = the base has this table
     // restore inputs
     const uint8_t *staging;   // serialized chunks
     const uint64_t *soff;     // item -> offset in staging

@@ -242,6 +242,9 @@ struct Desc {
     uint64_t g;     // chunk id
     uint32_t len;   // bytes in the chunk
     uint32_t zero;  // restore: the chunk is ZERO
+    uint32_t want;  // the CRC to compare with (base for DIRTY, stored for restore),
+                    // loaded with the descriptor so no wave waits on it at the end
+    uint32_t has_base;  // pack/hash: a base chunk exists and want is its CRC
 };
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -361,24 +364,61 @@ __device__ __forceinline__ void finish_chunk(const ChunkArgs &a, const Desc &d, 
 {
     const uint32_t crc = finish_crc(raw, d.len);
     if (MODE == kModeRestore) {
-        if (crc != a.want_crc[d.g]) {
+        if (crc != d.want) {
             a.bad[d.g] = 1;
             atomicAdd(&a.plan_rw->bad_count, 1ull);
         }
     } else {
         uint8_t f = nonzero ? 0 : kFlagZero;
-        if (a.base_crc == nullptr || a.base_crc[d.g] != crc)
+        if (!d.has_base || d.want != crc)
             f |= kFlagDirty;
         a.crc[d.g] = crc;
         a.flags[d.g] = f;
     }
 }
 
+// The descriptor of item i (chunk g = i, or ids[i] in a delta restore).
+template <int MODE>
+__device__ __forceinline__ Desc make_desc(const ChunkArgs &a, uint64_t i, uint32_t C)
+{
+    const uint64_t g = (MODE == kModeRestore && a.ids) ? a.ids[i] : i;
+    const uint32_t k = a.map[g];
+    const uint64_t start = (g - a.cb[k]) * C;
+    const uint64_t rest = a.size[k] - start;
+    Desc d;
+    d.g = g;
+    d.len = (uint32_t)(rest < C ? rest : C);
+    d.has_base = 0;
+    if (MODE == kModeRestore) {
+        d.zero = a.want_flags[g] & kFlagZero;
+        d.want = a.want_crc[g];
+        d.src = d.zero ? 0 : (uint64_t)(a.staging + a.soff[i]);
+        d.dst = a.dst[k] + start;
+    } else {
+        d.zero = 0;
+        // the base chunk: the same id when the base has this table, else the
+        // same chunk of the base allocation with this allocation's id
+        uint64_t bg = g;
+        d.has_base = a.base_crc != nullptr;
+        if (a.base_cb) {
+            const uint64_t b0 = a.base_cb[k];
+            d.has_base = b0 != kNoBase;
+            bg = b0 + (g - a.cb[k]);
+        }
+        d.want = d.has_base ? a.base_crc[bg] : 0;
+        d.src = a.src[k] + start;
+        d.dst = (MODE == kModePack) ? (uint64_t)(a.dense + a.off[k] + start) : 0;
+    }
+    return d;
+}
+
 template <int MODE, int G, bool NT, bool REP>
 __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
 {
     __shared__ uint32_t tabs[REP ? kRepWords : kTabTotalWords];
-    __shared__ Desc desc[kTile];
+    // two descriptor tiles: the first wave loads the next tile's descriptors
+    // while the workgroup works on the current one
+    __shared__ Desc desc[2][kTile];
     __shared__ uint32_t s_part[16];
     __shared__ uint32_t s_nz[16];
 
@@ -398,38 +438,38 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
     const uint32_t r_win = rw * W;
     const uint64_t M = (MODE == kModeRestore) ? a.plan->n_items : a.plan->n_chunks;
 
-    for (uint64_t g0 = (uint64_t)blockIdx.x * kTile; g0 < M; g0 += (uint64_t)gridDim.x * kTile) {
-        __syncthreads();   // tables loaded / previous tile's descriptors consumed
-        for (int t = threadIdx.x; t < kTile; t += blockDim.x) {
-            const uint64_t i = g0 + t;
-            if (i < M) {
-                const uint64_t g = (MODE == kModeRestore && a.ids) ? a.ids[i] : i;
-                const uint32_t k = a.map[g];
-                const uint64_t start = (g - a.cb[k]) * C;
-                const uint64_t rest = a.size[k] - start;
-                Desc d;
-                d.g = g;
-                d.len = (uint32_t)(rest < C ? rest : C);
-                if (MODE == kModeRestore) {
-                    d.zero = a.want_flags[g] & kFlagZero;
-                    d.src = d.zero ? 0 : (uint64_t)(a.staging + a.soff[i]);
-                    d.dst = a.dst[k] + start;
-                } else {
-                    d.zero = 0;
-                    d.src = a.src[k] + start;
-                    d.dst = (MODE == kModePack) ? (uint64_t)(a.dense + a.off[k] + start) : 0;
-                }
-                desc[t] = d;
-            }
-        }
-        __syncthreads();
-        for (int slot = 0; slot < kTile; slot += groups) {
+    // The items go in R rounds of at most gridDim.x * kTile; each round is
+    // split evenly over the workgroups, so the whole grid sweeps one window of
+    // memory at a time and no workgroup gets more than one item above another.
+    const uint64_t per_round = (uint64_t)gridDim.x * kTile;
+    const uint64_t R = (M + per_round - 1) / per_round;
+    auto tile_lo = [&](uint64_t r) {
+        const uint64_t base = M * r / R, span = M * (r + 1) / R - base;
+        return base + span * blockIdx.x / gridDim.x;
+    };
+    auto tile_hi = [&](uint64_t r) {
+        const uint64_t base = M * r / R, span = M * (r + 1) / R - base;
+        return base + span * (blockIdx.x + 1) / gridDim.x;
+    };
+    const bool stager = threadIdx.x < kTile;
+    uint64_t g0 = R ? tile_lo(0) : 0, hi = R ? tile_hi(0) : 0;
+    if (stager && g0 + threadIdx.x < hi)
+        desc[0][threadIdx.x] = make_desc<MODE>(a, g0 + threadIdx.x, C);
+    int buf = 0;
+    for (uint64_t r = 0; r < R; r++, buf ^= 1) {
+        __syncthreads();   // tables and this tile's descriptors are in LDS
+        const uint64_t n0 = r + 1 < R ? tile_lo(r + 1) : 0, n1 = r + 1 < R ? tile_hi(r + 1) : 0;
+        Desc nd;
+        if (stager && n0 + threadIdx.x < n1)
+            nd = make_desc<MODE>(a, n0 + threadIdx.x, C);   // loads in flight during the tile
+        const int cnt = (int)(hi - g0);   // uniform over the workgroup, at most kTile
+        for (int slot = 0; slot < cnt; slot += groups) {
             const int t = slot + group;
-            const bool valid = t < kTile && g0 + t < M;
+            const bool valid = t < cnt;
             uint32_t raw = 0, orv = 0;
             Desc d;
             if (valid) {
-                d = desc[t];
+                d = desc[buf][t];
                 raw = wave_rounds<MODE, G, NT, REP>(T, d, lane, wig * rw, (wig + 1) * rw, r_win, &orv);
             }
             const bool nonzero = __ballot(orv != 0) != 0;
@@ -454,6 +494,10 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
                 __syncthreads();
             }
         }
+        if (stager && n0 + threadIdx.x < n1)
+            desc[buf ^ 1][threadIdx.x] = nd;   // the other tile was consumed before the last barrier
+        g0 = n0;
+        hi = n1;
     }
 }
 
@@ -466,14 +510,43 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
 struct RowDesc {
     Desc d;
     uint64_t crc, flags, bad, bad_count;
-    uint32_t mode, c;
+    uint32_t mode, pad;
 };
+
+__device__ __forceinline__ RowDesc make_row_desc(const RowArgs &a, uint64_t i, uint32_t C)
+{
+    const StepRow &row = a.rows[a.map[i]];
+    const uint64_t c = i - row.item0;
+    const uint64_t start = c * C;
+    const uint64_t rest = row.rem - start;
+    RowDesc r;
+    r.d.g = i;
+    r.d.len = (uint32_t)(rest < C ? rest : C);
+    r.d.has_base = 0;
+    r.mode = row.mode;
+    r.pad = 0;
+    r.crc = row.crc + 4 * c;
+    r.flags = row.flags + c;
+    r.bad = row.bad + c;
+    r.bad_count = row.bad_count;
+    if (row.mode == kModeRestore) {
+        r.d.zero = *(const uint8_t *)r.flags & kFlagZero;
+        r.d.want = *(const uint32_t *)r.crc;
+        r.d.src = r.d.zero ? 0 : row.src + ((const uint64_t *)row.soff)[c];
+    } else {
+        r.d.zero = 0;
+        r.d.want = 0;
+        r.d.src = row.src + start;
+    }
+    r.d.dst = row.dst + start;
+    return r;
+}
 
 template <int G, bool NT, bool REP>
 __global__ __launch_bounds__(1024) void k_rows(RowArgs a)
 {
     __shared__ uint32_t tabs[REP ? kRepWords : kTabTotalWords];
-    __shared__ RowDesc desc[kTile];
+    __shared__ RowDesc desc[2][kTile];
 
     constexpr int kWords = REP ? kRepWords : kTabTotalWords;
     for (int i = threadIdx.x; i < kWords; i += blockDim.x)
@@ -486,57 +559,54 @@ __global__ __launch_bounds__(1024) void k_rows(RowArgs a)
     const uint32_t r_win = (C + round_bytes - 1) / round_bytes;
     const uint64_t M = a.n_items;
 
-    for (uint64_t g0 = (uint64_t)blockIdx.x * kTile; g0 < M; g0 += (uint64_t)gridDim.x * kTile) {
+    // Balanced interleaved rounds and double-buffered descriptors, as in k_chunks.
+    const uint64_t per_round = (uint64_t)gridDim.x * kTile;
+    const uint64_t R = (M + per_round - 1) / per_round;
+    auto tile_lo = [&](uint64_t r) {
+        const uint64_t base = M * r / R, span = M * (r + 1) / R - base;
+        return base + span * blockIdx.x / gridDim.x;
+    };
+    auto tile_hi = [&](uint64_t r) {
+        const uint64_t base = M * r / R, span = M * (r + 1) / R - base;
+        return base + span * (blockIdx.x + 1) / gridDim.x;
+    };
+    const bool stager = threadIdx.x < kTile;
+    uint64_t g0 = R ? tile_lo(0) : 0, hi = R ? tile_hi(0) : 0;
+    if (stager && g0 + threadIdx.x < hi)
+        desc[0][threadIdx.x] = make_row_desc(a, g0 + threadIdx.x, C);
+    int buf = 0;
+    for (uint64_t r = 0; r < R; r++, buf ^= 1) {
         __syncthreads();
-        for (int t = threadIdx.x; t < kTile; t += blockDim.x) {
-            const uint64_t i = g0 + t;
-            if (i < M) {
-                const StepRow &row = a.rows[a.map[i]];
-                const uint64_t c = i - row.item0;
-                const uint64_t start = c * C;
-                const uint64_t rest = row.rem - start;
-                RowDesc r;
-                r.d.g = i;
-                r.d.len = (uint32_t)(rest < C ? rest : C);
-                r.mode = row.mode;
-                r.c = (uint32_t)c;
-                r.crc = row.crc + 4 * c;
-                r.flags = row.flags + c;
-                r.bad = row.bad + c;
-                r.bad_count = row.bad_count;
-                if (row.mode == kModeRestore) {
-                    r.d.zero = *(const uint8_t *)r.flags & kFlagZero;
-                    r.d.src = r.d.zero ? 0 : row.src + ((const uint64_t *)row.soff)[c];
-                } else {
-                    r.d.zero = 0;
-                    r.d.src = row.src + start;
-                }
-                r.d.dst = row.dst + start;
-                desc[t] = r;
-            }
-        }
-        __syncthreads();
-        for (int t = wave; t < kTile && g0 + t < M; t += nwaves) {
-            const RowDesc r = desc[t];
+        const uint64_t n0 = r + 1 < R ? tile_lo(r + 1) : 0, n1 = r + 1 < R ? tile_hi(r + 1) : 0;
+        RowDesc nd;
+        if (stager && n0 + threadIdx.x < n1)
+            nd = make_row_desc(a, n0 + threadIdx.x, C);
+        const int cnt = (int)(hi - g0);
+        for (int t = wave; t < cnt; t += nwaves) {
+            const RowDesc rd = desc[buf][t];
             uint32_t raw, orv;
-            if (r.mode == kModeRestore)
-                raw = wave_rounds<kModeRestore, G, NT, REP>(T, r.d, lane, 0, r_win, r_win, &orv);
+            if (rd.mode == kModeRestore)
+                raw = wave_rounds<kModeRestore, G, NT, REP>(T, rd.d, lane, 0, r_win, r_win, &orv);
             else
-                raw = wave_rounds<kModePack, G, NT, REP>(T, r.d, lane, 0, r_win, r_win, &orv);
+                raw = wave_rounds<kModePack, G, NT, REP>(T, rd.d, lane, 0, r_win, r_win, &orv);
             const bool nonzero = __ballot(orv != 0) != 0;
             if (lane == 0) {
-                const uint32_t crc = finish_crc(raw, r.d.len);
-                if (r.mode == kModeRestore) {
-                    if (crc != *(const uint32_t *)r.crc) {
-                        *(uint8_t *)r.bad = 1;
-                        atomicAdd((unsigned long long *)r.bad_count, 1ull);
+                const uint32_t crc = finish_crc(raw, rd.d.len);
+                if (rd.mode == kModeRestore) {
+                    if (crc != rd.d.want) {
+                        *(uint8_t *)rd.bad = 1;
+                        atomicAdd((unsigned long long *)rd.bad_count, 1ull);
                     }
                 } else {
-                    *(uint32_t *)r.crc = crc;
-                    *(uint8_t *)r.flags = (nonzero ? 0 : kFlagZero) | kFlagDirty;
+                    *(uint32_t *)rd.crc = crc;
+                    *(uint8_t *)rd.flags = (nonzero ? 0 : kFlagZero) | kFlagDirty;
                 }
             }
         }
+        if (stager && n0 + threadIdx.x < n1)
+            desc[buf ^ 1][threadIdx.x] = nd;
+        g0 = n0;
+        hi = n1;
     }
 }
 

@@ -13,6 +13,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ckpt.h"
@@ -57,6 +58,7 @@ extern "C" const char *ckpt_strerror(int status)
     case CKPT_E_AGAIN: return "not finished";
     case CKPT_E_BUDGET: return "staging budget exceeded";
     case CKPT_E_ADDR: return "address range not free";
+    case CKPT_E_IO: return "file I/O error";
     default: return "unknown status";
     }
 }
@@ -386,6 +388,7 @@ extern "C" void ckpt_destroy(ckpt_ctx *ctx)
             b->release();
         ctx->h_up.release();
         ctx->h_plan.release();
+        ctx->h_base_cb.release();
         vmm_release_all(ctx);
     }
     delete ctx;
@@ -749,8 +752,24 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     const auto t_call = std::chrono::steady_clock::now();
 
     image_wait(base);
-    if (base && !same_table(base, rows, C))
-        return set_error(CKPT_E_MISMATCH, "base image has another allocation table or chunk size");
+    if (base && base->C != C)
+        return set_error(CKPT_E_MISMATCH, "base image has chunk size %u, context %u", base->C, C);
+    // A base with another allocation table is matched by registration id:
+    // base_cb[k] is the base's first chunk of allocation k when the base has
+    // an allocation with its id, size and kind, else kNoBase (every chunk DIRTY).
+    const bool remap = base && !same_table(base, rows, C);
+    std::vector<uint64_t> base_cb;
+    if (remap) {
+        base_cb.assign(n, kNoBase);
+        size_t j = 0;
+        for (uint64_t k = 0; k < n; k++) {
+            while (j < base->allocs.size() && base->allocs[j].id < rows[k].id)
+                j++;
+            if (j < base->allocs.size() && base->allocs[j].id == rows[k].id &&
+                base->allocs[j].size == rows[k].size && base->allocs[j].kind == rows[k].kind)
+                base_cb[k] = base->allocs[j].cb;
+        }
+    }
     if (!incremental && cfg.staging_budget && L.data_bytes > cfg.staging_budget)
         return set_error(CKPT_E_BUDGET, "dense image %llu B exceeds the staging budget %llu B",
                          (unsigned long long)L.data_bytes, (unsigned long long)cfg.staging_budget);
@@ -793,14 +812,25 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     // DIRTY is judged against the base's CRC array; the context keeps the last
     // image's array on the device, so a chain of increments uploads nothing.
     const uint32_t *d_base = nullptr;
+    const uint64_t *d_base_cb = nullptr;
     if (base) {
-        if (base->serial == ctx->prev_serial && ctx->d_prev_crc.cap >= N * 4) {
+        const uint64_t bN = base->N;
+        if (base->serial == ctx->prev_serial && ctx->d_prev_crc.cap >= bN * 4) {
             d_base = (const uint32_t *)ctx->d_prev_crc.p;
         } else {
-            CKPT_TRY(ctx->d_base_crc.ensure(std::max<uint64_t>(N, 1) * 4));
-            if (N)
-                HIP_TRY(hipMemcpyAsync(ctx->d_base_crc.p, base->crc, N * 4, hipMemcpyHostToDevice, s));
+            CKPT_TRY(ctx->d_base_crc.ensure(std::max<uint64_t>(bN, 1) * 4));
+            if (bN)
+                HIP_TRY(hipMemcpyAsync(ctx->d_base_crc.p, base->crc, bN * 4, hipMemcpyHostToDevice, s));
             d_base = (const uint32_t *)ctx->d_base_crc.p;
+        }
+        if (remap) {
+            CKPT_TRY(ctx->h_base_cb.ensure(std::max<uint64_t>(n, 1) * 8));
+            CKPT_TRY(ctx->d_base_cb.ensure(std::max<uint64_t>(n, 1) * 8));
+            if (n) {
+                memcpy(ctx->h_base_cb.p, base_cb.data(), n * 8);
+                HIP_TRY(hipMemcpyAsync(ctx->d_base_cb.p, ctx->h_base_cb.p, n * 8, hipMemcpyHostToDevice, s));
+            }
+            d_base_cb = (const uint64_t *)ctx->d_base_cb.p;
         }
     }
 
@@ -827,6 +857,7 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     a.crc = (uint32_t *)ctx->d_crc.p;
     a.flags = (uint8_t *)ctx->d_flags.p;
     a.base_crc = d_base;
+    a.base_cb = d_base_cb;
     if (N)
         HIP_TRY(launch_chunks(s, incremental ? kModeHash : kModePack, a, ctx->grid_chunks, cfg.block_threads));
     if (timing)
@@ -1124,6 +1155,13 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
         return set_error(CKPT_E_INVAL, "restore needs a drained full image");
     if (img->C != ctx->cfg.chunk_bytes)
         return set_error(CKPT_E_MISMATCH, "image chunk size %u, context %u", img->C, ctx->cfg.chunk_bytes);
+    if (delta && delta->mode == CKPT_INCREMENTAL && delta->drained && delta->base_serial == img->serial &&
+        !same_table(img, delta)) {
+        // the allocation table changed between the two: restore the merged image
+        std::unique_ptr<ckpt_image> merged;
+        CKPT_TRY(fold_delta(img, delta, &merged));
+        return ckpt_restore(ctx, stream, merged.get(), nullptr, dst, dst_bytes, n_dst, rep);
+    }
     const uint64_t n = img->allocs.size();
     if (n_dst != n)
         return set_error(CKPT_E_MISMATCH, "%zu destinations for %llu allocations", n_dst, (unsigned long long)n);
@@ -1275,6 +1313,147 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
 
 // -------------------------------------------------------------------- image
 
+// --------------------------------------------------------------- merging
+//
+// A full image and an incremental image taken against it fold into the full
+// image a checkpoint would have produced at the increment's time: the
+// increment's allocation table, CRC and flags (every chunk DIRTY, as in a
+// full image without a base), and each non-ZERO chunk's bytes from the
+// increment when it is DIRTY there, else from the same chunk of the base
+// allocation with the same id.  All on the host, from the images' DATA.
+extern "C" int ckpt_image_merge(const ckpt_image *base, const ckpt_image *delta, ckpt_image **out)
+{
+    if (!base || !delta || !out)
+        return set_error(CKPT_E_INVAL, "NULL argument");
+    image_wait(base);
+    image_wait(delta);
+    if (!base->drained || !delta->drained)
+        return set_error(CKPT_E_INVAL, "merging needs images with host DATA");
+    if (base->mode != CKPT_FULL || delta->mode != CKPT_INCREMENTAL)
+        return set_error(CKPT_E_INVAL, "merge takes a full image and an incremental image");
+    if (delta->base_serial != base->serial || delta->C != base->C)
+        return set_error(CKPT_E_MISMATCH, "the incremental image was not taken against this base");
+    const uint32_t C = delta->C;
+    const uint64_t n = delta->allocs.size(), N = delta->N, bn = base->allocs.size();
+
+    // base: the serialized offset of each chunk (ZERO chunks have none)
+    std::vector<uint64_t> boff(base->N + 1, 0);
+    for (uint64_t j = 0, g = 0, o = 0; j < bn; j++) {
+        const uint64_t sz = base->allocs[j].size;
+        for (uint64_t c = 0; c * C < sz; c++, g++) {
+            boff[g] = o;
+            if (!(base->flags[g] & kFlagZero))
+                o += ru16(std::min<uint64_t>(C, sz - c * C));
+        }
+    }
+    // the source of every chunk of the result: 0 none (ZERO), 1 delta, 2 base
+    struct Src {
+        uint64_t off, len;   // offset in the source DATA, bytes (a multiple of 16)
+        uint8_t from;
+    };
+    std::vector<Src> src(N);
+    uint64_t total = 0, doff = 0;
+    size_t j = 0;
+    for (uint64_t k = 0, g = 0; k < n; k++) {
+        const ckpt_alloc_rec &r = delta->allocs[k];
+        while (j < bn && base->allocs[j].id < r.id)
+            j++;
+        const bool matched =
+            j < bn && base->allocs[j].id == r.id && base->allocs[j].size == r.size && base->allocs[j].kind == r.kind;
+        for (uint64_t c = 0; c * C < r.size; c++, g++) {
+            const uint64_t len = ru16(std::min<uint64_t>(C, r.size - c * C));
+            const uint8_t f = delta->flags[g];
+            Src &x = src[g];
+            x.len = len;
+            if (f & kFlagZero) {
+                x.from = 0;
+                x.len = 0;
+            } else if (f & kFlagDirty) {
+                x.from = 1;
+                x.off = doff;
+                doff += len;
+            } else {
+                const uint64_t bg = matched ? base->allocs[j].cb + c : kNoBase;
+                if (bg == kNoBase || (base->flags[bg] & kFlagZero) || base->crc[bg] != delta->crc[g])
+                    return set_error(CKPT_E_CORRUPT, "chunk %llu is clean in the increment but has no equal base chunk",
+                                     (unsigned long long)g);
+                x.from = 2;
+                x.off = boff[bg];
+            }
+            total += x.len;
+        }
+    }
+    if (doff != delta->ser_bytes)
+        return set_error(CKPT_E_CORRUPT, "increment DATA holds %llu bytes, its flags describe %llu",
+                         (unsigned long long)delta->ser_bytes, (unsigned long long)doff);
+
+    auto *img = new ckpt_image();
+    std::unique_ptr<ckpt_image> guard(img);
+    img->device = delta->device;
+    img->mode = CKPT_FULL;
+    img->C = C;
+    img->N = N;
+    img->data_bytes = delta->data_bytes;
+    img->ser_bytes = total;
+    // the merged image stands for the increment's state (same CRC array), so
+    // it takes the increment's serial: an increment taken against the
+    // increment can be merged into it next
+    img->serial = delta->serial;
+    img->base_serial = 0;
+    img->drained = true;
+    img->allocs = delta->allocs;
+    img->addrs = delta->addrs;
+    CKPT_TRY(alloc_meta(img, N));
+    if (N) {
+        memcpy(img->crc, delta->crc, N * 4);
+        for (uint64_t g = 0; g < N; g++)
+            img->flags[g] = (uint8_t)((delta->flags[g] & kFlagZero) | kFlagDirty);
+    }
+    CKPT_TRY(img->ids_buf.ensure(8));
+    CKPT_TRY(img->data.ensure(std::max<uint64_t>(total, 1)));
+    // copy in parallel over contiguous chunk ranges
+    const unsigned T = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(8, total >> 26));
+    std::vector<uint64_t> start(T + 1, 0), out_off(T + 1, 0);
+    for (unsigned t = 0; t <= T; t++)
+        start[t] = N * t / T;
+    for (unsigned t = 0; t < T; t++) {
+        uint64_t o = 0;
+        for (uint64_t g = start[t]; g < start[t + 1]; g++)
+            o += src[g].len;
+        out_off[t + 1] = out_off[t] + o;
+    }
+    auto copy_range = [&](unsigned t) {
+        uint8_t *dst = (uint8_t *)img->data.p + out_off[t];
+        for (uint64_t g = start[t]; g < start[t + 1]; g++) {
+            const Src &x = src[g];
+            if (x.from == 0)
+                continue;
+            const uint8_t *from = (const uint8_t *)(x.from == 1 ? delta->data.p : base->data.p) + x.off;
+            memcpy(dst, from, x.len);
+            dst += x.len;
+        }
+    };
+    std::vector<std::thread> pool;
+    for (unsigned t = 1; t < T; t++)
+        pool.emplace_back(copy_range, t);
+    copy_range(0);
+    for (auto &th : pool)
+        th.join();
+    *out = guard.release();
+    return CKPT_OK;
+}
+
+int ckpt::fold_delta(const ckpt_image *img, const ckpt_image *delta, std::unique_ptr<ckpt_image> *merged)
+{
+    merged->reset();
+    if (!img || !delta || same_table(img, delta))
+        return CKPT_OK;
+    ckpt_image *m = nullptr;
+    CKPT_TRY(ckpt_image_merge(img, delta, &m));
+    merged->reset(m);
+    return CKPT_OK;
+}
+
 extern "C" int ckpt_image_info(const ckpt_image *img, ckpt_image_meta *out)
 {
     if (!img || !out)
@@ -1355,21 +1534,14 @@ size_t serialized_size(uint32_t version, uint64_t n, uint64_t N, uint64_t n_dirt
 }
 }  // namespace
 
-extern "C" int ckpt_image_serialize(const ckpt_image *img, void *buf, size_t cap, size_t *need)
+size_t ckpt::serialized_head_bytes(const ckpt_image *img)
 {
-    if (!img || !need)
-        return set_error(CKPT_E_INVAL, "NULL argument");
-    image_wait(img);
-    if (!img->drained)
-        return set_error(CKPT_E_INVAL, "image holds no host data");
+    return serialized_size(kVersion, img->allocs.size(), img->N, img->n_dirty, 0);
+}
+
+void ckpt::serialize_head(const ckpt_image *img, uint8_t *p)
+{
     const uint64_t n = img->allocs.size();
-    const size_t total = serialized_size(kVersion, n, img->N, img->n_dirty, img->ser_bytes);
-    *need = total;
-    if (!buf)
-        return CKPT_OK;
-    if (cap < total)
-        return set_error(CKPT_E_INVAL, "buffer holds %zu of %zu bytes", cap, total);
-    uint8_t *p = (uint8_t *)buf;
     memcpy(p, kMagic, 8);
     uint32_t h32[4] = {kVersion, img->mode, img->C, 16};
     memcpy(p + 8, h32, 16);
@@ -1393,16 +1565,30 @@ extern "C" int ckpt_image_serialize(const ckpt_image *img, void *buf, size_t cap
     p += img->N * 4 + pad8(img->N);
     if (img->n_dirty)
         memcpy(p, img->ids_buf.p, img->n_dirty * 8);
-    p += img->n_dirty * 8;
+}
+
+extern "C" int ckpt_image_serialize(const ckpt_image *img, void *buf, size_t cap, size_t *need)
+{
+    if (!img || !need)
+        return set_error(CKPT_E_INVAL, "NULL argument");
+    image_wait(img);
+    if (!img->drained)
+        return set_error(CKPT_E_INVAL, "image holds no host data");
+    const size_t head = serialized_head_bytes(img);
+    const size_t total = head + img->ser_bytes;
+    *need = total;
+    if (!buf)
+        return CKPT_OK;
+    if (cap < total)
+        return set_error(CKPT_E_INVAL, "buffer holds %zu of %zu bytes", cap, total);
+    serialize_head(img, (uint8_t *)buf);
     if (img->ser_bytes)
-        memcpy(p, img->data.p, img->ser_bytes);
+        memcpy((uint8_t *)buf + head, img->data.p, img->ser_bytes);
     return CKPT_OK;
 }
 
-extern "C" int ckpt_image_load(ckpt_ctx *ctx, const void *buf, size_t bytes, ckpt_image **out)
+int ckpt::parse_head(const void *buf, size_t bytes, ImageHead *h)
 {
-    if (!buf || !out)
-        return set_error(CKPT_E_INVAL, "NULL argument");
     if (bytes < kHeaderBytes)
         return set_error(CKPT_E_INVAL, "truncated image header (%zu bytes)", bytes);
     const uint8_t *p = (const uint8_t *)buf;
@@ -1423,40 +1609,64 @@ extern "C" int ckpt_image_load(ckpt_ctx *ctx, const void *buf, size_t bytes, ckp
     const size_t total = serialized_size(version, n, N, nd, ser);
     if (bytes < total)
         return set_error(CKPT_E_INVAL, "truncated image: %zu of %zu bytes", bytes, total);
-    auto *img = new ckpt_image();
-    std::unique_ptr<ckpt_image> guard(img);
-    img->device = ctx ? ctx->cfg.device : 0;
-    img->mode = h32[1];
-    img->C = h32[2];
-    img->N = N;
-    img->data_bytes = h64[2];
-    img->ser_bytes = ser;
-    img->n_dirty = nd;
-    img->serial = h64[5];
-    img->base_serial = h64[6];
-    img->drained = true;
+    h->version = version;
+    h->mode = h32[1];
+    h->C = h32[2];
+    h->N = N;
+    h->data_bytes = h64[2];
+    h->ser_bytes = ser;
+    h->n_dirty = nd;
+    h->serial = h64[5];
+    h->base_serial = h64[6];
+    h->digest = h64[7];
     p += kHeaderBytes;
-    img->allocs.resize(n);
+    h->allocs.resize(n);
     if (n)
-        memcpy(img->allocs.data(), p, n * sizeof(ckpt_alloc_rec));
+        memcpy(h->allocs.data(), p, n * sizeof(ckpt_alloc_rec));
     p += n * sizeof(ckpt_alloc_rec);
     // the table must be self-consistent: offsets and chunk bases are prefix sums
     uint64_t o = 0, g = 0;
     for (uint64_t k = 0; k < n; k++) {
-        const ckpt_alloc_rec &r = img->allocs[k];
+        const ckpt_alloc_rec &r = h->allocs[k];
         if (r.off != o || r.cb != g || (r.kind != CKPT_DEVICE && r.kind != CKPT_MANAGED))
             return set_error(CKPT_E_INVAL, "inconsistent allocation table at row %llu", (unsigned long long)k);
         o += ru16(r.size);
-        g += (r.size + img->C - 1) / img->C;
+        g += (r.size + h->C - 1) / h->C;
     }
-    if (o != img->data_bytes || g != N)
+    if (o != h->data_bytes || g != N)
         return set_error(CKPT_E_INVAL, "allocation table does not match the header totals");
-    img->addrs.assign(n, 0);
+    h->addrs.assign(n, 0);
     if (version >= 2) {
         if (n)
-            memcpy(img->addrs.data(), p, n * 8);
+            memcpy(h->addrs.data(), p, n * 8);
         p += n * 8;
     }
+    h->rest = p;
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_image_load(ckpt_ctx *ctx, const void *buf, size_t bytes, ckpt_image **out)
+{
+    if (!buf || !out)
+        return set_error(CKPT_E_INVAL, "NULL argument");
+    ImageHead h;
+    CKPT_TRY(parse_head(buf, bytes, &h));
+    auto *img = new ckpt_image();
+    std::unique_ptr<ckpt_image> guard(img);
+    img->device = ctx ? ctx->cfg.device : 0;
+    img->mode = h.mode;
+    img->C = h.C;
+    img->N = h.N;
+    img->data_bytes = h.data_bytes;
+    img->ser_bytes = h.ser_bytes;
+    img->n_dirty = h.n_dirty;
+    img->serial = h.serial;
+    img->base_serial = h.base_serial;
+    img->drained = true;
+    img->allocs = std::move(h.allocs);
+    img->addrs = std::move(h.addrs);
+    const uint8_t *p = h.rest;
+    const uint64_t N = h.N, nd = h.n_dirty, ser = h.ser_bytes;
     CKPT_TRY(alloc_meta(img, N));
     if (N) {
         memcpy(img->crc, p, N * 4);
@@ -1470,7 +1680,7 @@ extern "C" int ckpt_image_load(ckpt_ctx *ctx, const void *buf, size_t bytes, ckp
     CKPT_TRY(img->data.ensure(std::max<uint64_t>(ser, 1)));
     if (ser)
         memcpy(img->data.p, p, ser);
-    if (crc_digest(img->crc, N * 4) != h64[7])
+    if (crc_digest(img->crc, N * 4) != h.digest)
         return set_error(CKPT_E_INVAL, "CRC section digest mismatch");
     *out = guard.release();
     return CKPT_OK;

@@ -34,30 +34,157 @@ int granularity(int device, uint64_t *out)
     return CKPT_OK;
 }
 
-// Reserve [want, want + bytes) (anywhere when want is 0), map fresh device
-// memory there and allow reads and writes from the device.  Nothing is left
-// behind on failure.
-int map_range(ckpt_ctx *ctx, uint64_t want, uint64_t bytes, uint64_t *base)
+// Windows: the first address-stable allocation without a requested address
+// picks a region of kWindowUsable + kWindowGuard bytes (by reserving it and
+// releasing it again at once), and allocations are then placed from its
+// bottom up, each with its own reservation at the chosen address.  The runtime
+// hands out its own addresses top-down, and in another process its first
+// allocations may land somewhat lower or higher than in this one; the bottom
+// of the region sits far below all of them, so the same addresses are free
+// again in a fresh process.  The runtime may still place memory of its own in
+// the region later: such a spot is marked taken and the next one is tried.
+constexpr uint64_t kWindowUsable = uint64_t(1) << 40;   // 1 TiB
+constexpr uint64_t kWindowGuard = uint64_t(1) << 38;    // 256 GiB
+constexpr int kPlaceTries = 8;
+
+// Take [a, a + n) out of a window's free list when it lies in one free range.
+bool window_take(VmmWindow &w, uint64_t a, uint64_t n)
 {
-    const int dev = ctx->cfg.device;
+    auto it = w.free.upper_bound(a);
+    if (it == w.free.begin())
+        return false;
+    --it;
+    const uint64_t s = it->first, e = s + it->second;
+    if (a < s || a + n > e)
+        return false;
+    w.free.erase(it);
+    if (s < a)
+        w.free.emplace(s, a - s);
+    if (a + n < e)
+        w.free.emplace(a + n, e - (a + n));
+    return true;
+}
+
+void window_give(VmmWindow &w, uint64_t a, uint64_t n)
+{
+    auto it = w.free.emplace(a, n).first;
+    auto nx = std::next(it);
+    if (nx != w.free.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        w.free.erase(nx);
+    }
+    if (it != w.free.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            w.free.erase(it);
+        }
+    }
+}
+
+VmmWindow *window_of(ckpt_ctx *ctx, uint64_t a, uint64_t n)
+{
+    for (VmmWindow &w : ctx->windows)
+        if (a < w.base + w.usable && w.base < a + n)
+            return &w;
+    return nullptr;
+}
+
+// hipMemAddressReserve exactly at `want`: CKPT_E_ADDR when the runtime would
+// put the range elsewhere.
+int reserve_exact(uint64_t want, uint64_t bytes)
+{
     void *p = nullptr;
     hipError_t e = hipMemAddressReserve(&p, bytes, 0, (void *)(uintptr_t)want, 0);
-    if (e != hipSuccess) {
-        if (want)
-            return set_error(CKPT_E_ADDR, "cannot reserve [0x%llx, +%llu): %s", (unsigned long long)want,
-                             (unsigned long long)bytes, hipGetErrorString(e));
-        return hip_fail(e, "hipMemAddressReserve", __LINE__);
-    }
-    if (want && (uint64_t)(uintptr_t)p != want) {
+    if (e != hipSuccess)
+        return set_error(CKPT_E_ADDR, "cannot reserve [0x%llx, +%llu): %s", (unsigned long long)want,
+                         (unsigned long long)bytes, hipGetErrorString(e));
+    if ((uint64_t)(uintptr_t)p != want) {
         (void)hipMemAddressFree(p, bytes);
         return set_error(CKPT_E_ADDR, "[0x%llx, +%llu) is not free (the runtime offered %p)",
                          (unsigned long long)want, (unsigned long long)bytes, p);
     }
+    return CKPT_OK;
+}
+
+// A reservation of `bytes`: at `want`, or (want 0) at the lowest free spot of
+// a window.  *in_window: the addresses are also booked in a window.
+int reserve_va(ckpt_ctx *ctx, uint64_t want, uint64_t bytes, uint64_t *base, bool *in_window)
+{
+    if (want) {
+        VmmWindow *w = window_of(ctx, want, bytes);
+        if (w && !window_take(*w, want, bytes))
+            return set_error(CKPT_E_ADDR, "[0x%llx, +%llu) is taken", (unsigned long long)want,
+                             (unsigned long long)bytes);
+        const int rc = reserve_exact(want, bytes);
+        if (rc != CKPT_OK) {
+            if (w)
+                window_give(*w, want, bytes);
+            return rc;
+        }
+        *base = want;
+        *in_window = w != nullptr;
+        return CKPT_OK;
+    }
+    if (ctx->windows.empty()) {
+        VmmWindow w;
+        w.usable = kWindowUsable;
+        void *p = nullptr;
+        HIP_TRY(hipMemAddressReserve(&p, kWindowUsable + kWindowGuard, 0, nullptr, 0));
+        (void)hipMemAddressFree(p, kWindowUsable + kWindowGuard);
+        w.base = (uint64_t)(uintptr_t)p;
+        w.free.emplace(w.base, w.usable);
+        ctx->windows.push_back(w);
+    }
+    VmmWindow &w = ctx->windows.front();
+    for (int t = 0; t < kPlaceTries; t++) {
+        uint64_t a = 0;
+        for (const auto &f : w.free)
+            if (f.second >= bytes) {
+                a = f.first;
+                break;
+            }
+        if (!a)
+            break;
+        window_take(w, a, bytes);
+        if (reserve_exact(a, bytes) == CKPT_OK) {
+            *base = a;
+            *in_window = true;
+            return CKPT_OK;
+        }
+        // the runtime holds memory there now: leave the spot booked as taken
+    }
+    // the window is full or crowded: anywhere the runtime chooses
+    void *p = nullptr;
+    HIP_TRY(hipMemAddressReserve(&p, bytes, 0, nullptr, 0));
+    *base = (uint64_t)(uintptr_t)p;
+    *in_window = false;
+    return CKPT_OK;
+}
+
+void release_va(ckpt_ctx *ctx, uint64_t base, uint64_t bytes, bool in_window)
+{
+    (void)hipMemAddressFree((void *)(uintptr_t)base, bytes);
+    if (in_window)
+        if (VmmWindow *w = window_of(ctx, base, bytes))
+            window_give(*w, base, bytes);
+}
+
+// Virtual addresses for [want, want + bytes) (anywhere when want is 0), fresh
+// device memory mapped there, readable and writable from the device.  Nothing
+// is left behind on failure.
+int map_range(ckpt_ctx *ctx, uint64_t want, uint64_t bytes, uint64_t *base)
+{
+    const int dev = ctx->cfg.device;
+    uint64_t va = 0;
+    bool in_window = false;
+    CKPT_TRY(reserve_va(ctx, want, bytes, &va, &in_window));
+    void *p = (void *)(uintptr_t)va;
     hipMemAllocationProp prop = device_prop(dev);
     hipMemGenericAllocationHandle_t h{};
-    e = hipMemCreate(&h, bytes, &prop, 0);
+    hipError_t e = hipMemCreate(&h, bytes, &prop, 0);
     if (e != hipSuccess) {
-        (void)hipMemAddressFree(p, bytes);
+        release_va(ctx, va, bytes, in_window);
         return set_error(CKPT_E_NOMEM, "hipMemCreate of %llu bytes: %s", (unsigned long long)bytes,
                          hipGetErrorString(e));
     }
@@ -74,14 +201,15 @@ int map_range(ckpt_ctx *ctx, uint64_t want, uint64_t bytes, uint64_t *base)
     }
     if (e != hipSuccess) {
         (void)hipMemRelease(h);
-        (void)hipMemAddressFree(p, bytes);
+        release_va(ctx, va, bytes, in_window);
         return hip_fail(e, "hipMemMap / hipMemSetAccess", __LINE__);
     }
     VmmRange r;
     r.bytes = bytes;
     r.h = h;
-    ctx->vmm.emplace((uint64_t)(uintptr_t)p, r);
-    *base = (uint64_t)(uintptr_t)p;
+    r.in_window = in_window;
+    ctx->vmm.emplace(va, r);
+    *base = va;
     return CKPT_OK;
 }
 
@@ -90,7 +218,7 @@ void unmap_range(ckpt_ctx *ctx, std::map<uint64_t, VmmRange>::iterator it)
     void *p = (void *)(uintptr_t)it->first;
     (void)hipMemUnmap(p, it->second.bytes);
     (void)hipMemRelease(it->second.h);
-    (void)hipMemAddressFree(p, it->second.bytes);
+    release_va(ctx, it->first, it->second.bytes, it->second.in_window);
     ctx->vmm.erase(it);
 }
 
@@ -130,12 +258,13 @@ const RangeEnd *overlapping(const ckpt_ctx *ctx, uint64_t a, uint64_t n, uint64_
 
 void ckpt::vmm_release_all(ckpt_ctx *ctx)
 {
-    if (ctx->vmm.empty())
+    if (ctx->vmm.empty() && ctx->windows.empty())
         return;
     (void)hipDeviceSynchronize();
     while (!ctx->vmm.empty())
         unmap_range(ctx, ctx->vmm.begin());
     ctx->vmm_of.clear();
+    ctx->windows.clear();
 }
 
 extern "C" int ckpt_vmm_granularity(ckpt_ctx *ctx, size_t *out)
@@ -199,24 +328,44 @@ extern "C" int ckpt_vmm_free(ckpt_ctx *ctx, void *ptr)
     return CKPT_OK;
 }
 
-extern "C" int ckpt_restore_at(ckpt_ctx *ctx, void *stream, const ckpt_image *img, const ckpt_image *delta,
-                               void **addrs_out, ckpt_verify_report *rep)
+namespace {
+
+// What one call created, so that a failure can take it back.
+struct Made {
+    std::vector<uint64_t> regs;     // registration starts
+    std::vector<uint64_t> ranges;   // mapped range bases
+};
+
+void undo_made(ckpt_ctx *ctx, const Made &made)
 {
-    if (!ctx || !img)
-        return set_error(CKPT_E_INVAL, "ctx or image is NULL");
-    const uint64_t n = img->allocs.size();
-    if (img->addrs.size() != n)
+    for (uint64_t st : made.regs) {
+        ctx->vmm_of.erase(st);
+        (void)drop_registration(ctx, st);
+    }
+    for (uint64_t b : made.ranges) {
+        auto it = ctx->vmm.find(b);
+        if (it != ctx->vmm.end())
+            unmap_range(ctx, it);
+    }
+}
+
+// Steps 1-3 of a restore at the recorded addresses: every allocation of the
+// table either matches a live registration exactly, or is re-created at its
+// address (granule-aligned ranges mapped once) and registered there.
+int recreate(ckpt_ctx *ctx, const std::vector<ckpt_alloc_rec> &allocs, const std::vector<uint64_t> &addrs,
+             Made *made)
+{
+    const uint64_t n = allocs.size();
+    if (addrs.size() != n)
         return set_error(CKPT_E_INVAL, "image has no address section");
-    HookGuard hg(ctx);
-    DeviceGuard dg(ctx->cfg.device);
     uint64_t g = 0;
     CKPT_TRY(granularity(ctx->cfg.device, &g));
 
     // 1. classify: refill a matching live registration, or re-create
     std::vector<char> create(n, 0);
     for (uint64_t k = 0; k < n; k++) {
-        const ckpt_alloc_rec &r = img->allocs[k];
-        const uint64_t a = img->addrs[k];
+        const ckpt_alloc_rec &r = allocs[k];
+        const uint64_t a = addrs[k];
         if (a == 0 && r.size != 0)
             return set_error(CKPT_E_INVAL, "allocation %llu has no recorded address", (unsigned long long)k);
         if (a % 16 != 0)
@@ -242,8 +391,8 @@ extern "C" int ckpt_restore_at(ckpt_ctx *ctx, void *stream, const ckpt_image *im
     {
         std::vector<std::pair<uint64_t, uint64_t>> iv;
         for (uint64_t k = 0; k < n; k++)
-            if (img->allocs[k].size)
-                iv.emplace_back(img->addrs[k], img->addrs[k] + img->allocs[k].size);
+            if (allocs[k].size)
+                iv.emplace_back(addrs[k], addrs[k] + allocs[k].size);
         std::sort(iv.begin(), iv.end());
         for (size_t i = 1; i < iv.size(); i++)
             if (iv[i].first < iv[i - 1].second)
@@ -260,8 +409,8 @@ extern "C" int ckpt_restore_at(ckpt_ctx *ctx, void *stream, const ckpt_image *im
     {
         std::vector<Span> raw;
         for (uint64_t k = 0; k < n; k++)
-            if (create[k] && img->allocs[k].size) {
-                const uint64_t a = img->addrs[k], e = a + img->allocs[k].size;
+            if (create[k] && allocs[k].size) {
+                const uint64_t a = addrs[k], e = a + allocs[k].size;
                 raw.push_back({a / g * g, (e + g - 1) / g * g});
             }
         std::sort(raw.begin(), raw.end(), [](const Span &x, const Span &y) { return x.lo < y.lo; });
@@ -280,39 +429,27 @@ extern "C" int ckpt_restore_at(ckpt_ctx *ctx, void *stream, const ckpt_image *im
     }
 
     // 3. map and register; undo everything on failure
-    std::vector<uint64_t> made_ranges, made_regs;
-    auto undo = [&]() {
-        for (uint64_t st : made_regs) {
-            ctx->vmm_of.erase(st);
-            (void)drop_registration(ctx, st);
-        }
-        for (uint64_t b : made_ranges) {
-            auto it = ctx->vmm.find(b);
-            if (it != ctx->vmm.end())
-                unmap_range(ctx, it);
-        }
+    auto fail = [&](int rc) {
+        undo_made(ctx, *made);
+        return rc;
     };
     for (const Span &s : spans) {
         uint64_t base = 0;
         const int rc = map_range(ctx, s.lo, s.hi - s.lo, &base);
-        if (rc != CKPT_OK) {
-            undo();
-            return rc;
-        }
-        made_ranges.push_back(base);
+        if (rc != CKPT_OK)
+            return fail(rc);
+        made->ranges.push_back(base);
     }
     for (uint64_t k = 0; k < n; k++) {
         if (!create[k])
             continue;
-        const ckpt_alloc_rec &r = img->allocs[k];
-        const uint64_t a = img->addrs[k];
+        const ckpt_alloc_rec &r = allocs[k];
+        const uint64_t a = addrs[k];
         uint64_t rid = 0;
         int rc = add_registration(ctx, a, r.size, CKPT_DEVICE, r.id, &rid);
-        if (rc != CKPT_OK) {
-            undo();
-            return rc;
-        }
-        made_regs.push_back(a);
+        if (rc != CKPT_OK)
+            return fail(rc);
+        made->regs.push_back(a);
         if (r.size) {
             // the span that holds it: the last with lo <= a
             auto sp = std::upper_bound(spans.begin(), spans.end(), a,
@@ -323,18 +460,77 @@ extern "C" int ckpt_restore_at(ckpt_ctx *ctx, void *stream, const ckpt_image *im
         }
     }
 
+    return CKPT_OK;
+}
+
+}  // namespace
+
+extern "C" int ckpt_restore_at(ckpt_ctx *ctx, void *stream, const ckpt_image *img, const ckpt_image *delta,
+                               void **addrs_out, ckpt_verify_report *rep)
+{
+    if (!ctx || !img)
+        return set_error(CKPT_E_INVAL, "ctx or image is NULL");
+    if (delta && delta->mode == CKPT_INCREMENTAL && delta->base_serial == img->serial) {
+        // the allocation table changed between the two: restore the merged image
+        std::unique_ptr<ckpt_image> merged;
+        CKPT_TRY(fold_delta(img, delta, &merged));
+        if (merged)
+            return ckpt_restore_at(ctx, stream, merged.get(), nullptr, addrs_out, rep);
+    }
+    HookGuard hg(ctx);
+    DeviceGuard dg(ctx->cfg.device);
+    Made made;
+    CKPT_TRY(recreate(ctx, img->allocs, img->addrs, &made));
+
     // 4. refill and verify at those addresses
+    const uint64_t n = img->allocs.size();
     std::vector<void *> dst(n);
     for (uint64_t k = 0; k < n; k++)
         dst[k] = (void *)(uintptr_t)img->addrs[k];
     const int rc = ckpt_restore(ctx, stream, img, delta, n ? dst.data() : nullptr, nullptr, n, rep);
     if (rc != CKPT_OK && rc != CKPT_E_CORRUPT) {
         (void)hipDeviceSynchronize();
-        undo();
+        undo_made(ctx, made);
         return rc;
     }
     if (addrs_out)
         for (uint64_t k = 0; k < n; k++)
             addrs_out[k] = dst[k];
+    return rc;
+}
+
+extern "C" int ckpt_restore_file_at(ckpt_ctx *ctx, void *stream, const char *path, void **addrs_out,
+                                    ckpt_verify_report *rep, ckpt_image **img_out)
+{
+    if (!ctx || !path)
+        return set_error(CKPT_E_INVAL, "ctx or path is NULL");
+    // the file into ordinary host memory, and its tables, before any device work
+    std::vector<uint8_t> buf;
+    CKPT_TRY(read_whole_file(path, &buf));
+    ImageHead h;
+    CKPT_TRY(parse_head(buf.data(), buf.size(), &h));
+    if (h.mode != CKPT_FULL)
+        return set_error(CKPT_E_INVAL, "restore needs a full image");
+    HookGuard hg(ctx);
+    DeviceGuard dg(ctx->cfg.device);
+    // the address ranges first: nothing of this call has used device memory yet
+    Made made;
+    CKPT_TRY(recreate(ctx, h.allocs, h.addrs, &made));
+    ckpt_image *img = nullptr;
+    int rc = ckpt_image_load(ctx, buf.data(), buf.size(), &img);
+    if (rc == CKPT_OK) {
+        // every allocation is now a live registration at its address: refilled in place
+        rc = ckpt_restore_at(ctx, stream, img, nullptr, addrs_out, rep);
+    }
+    if (rc != CKPT_OK && rc != CKPT_E_CORRUPT) {
+        (void)hipDeviceSynchronize();
+        undo_made(ctx, made);
+        ckpt_image_free(img);
+        return rc;
+    }
+    if (img_out)
+        *img_out = img;
+    else
+        ckpt_image_free(img);
     return rc;
 }

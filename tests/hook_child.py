@@ -81,8 +81,7 @@ def run_save(path):
     live = tensors()
     img = ctx.checkpoint()
     out = check(ctx, live, img)
-    with open(path, "wb") as f:
-        f.write(img.serialize())
+    img.write_file(path)
     out["addrs"] = [t.data_ptr() for t in live]
     out["sha"] = [hashlib.sha256(host_bytes(t).tobytes()).hexdigest() for t in live]
     print(json.dumps(out), flush=True)
@@ -90,11 +89,8 @@ def run_save(path):
 
 def run_restore(path):
     from tests.gpu_common import d2h
-    with open(path, "rb") as f:
-        blob = f.read()
     ctx = K.Context(chunk_bytes=C)
-    img = K.Image.load(blob, ctx)
-    rc, rep, addrs = ctx.restore_at(img)
+    rc, rep, addrs, img = ctx.restore_file_at(path)
     sizes = [int(s) for s in img.allocs["size"]]
     sha = [hashlib.sha256(d2h(p, s).tobytes()).hexdigest() for p, s in zip(addrs, sizes)]
     print(json.dumps({"rc": rc, "n_bad": rep["n_bad"], "addrs": addrs, "sha": sha}), flush=True)

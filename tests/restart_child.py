@@ -3,10 +3,10 @@
   save PATH     make address-stable allocations with seeded contents in a
                 fresh process, checkpoint them, write the serialized image to
                 PATH and print the addresses and ids as JSON;
-  restore PATH  in another fresh process, load the image, restore it at the
-                addresses it was taken from, check the bytes there, take an
-                incremental checkpoint against the loaded image, and print
-                the results as JSON.
+  restore PATH  in another fresh process, restore the image file at the
+                addresses it was taken from (ranges reserved first), check the
+                bytes there, take an incremental checkpoint against the loaded
+                image, and print the results as JSON.
 
 Each side regenerates the contents from the same seed, so no data passes
 between the processes except the image file.
@@ -46,18 +46,16 @@ def save(path):
         addrs.append(p)
         ids.append(i)
     img = ctx.checkpoint()
-    with open(path, "wb") as f:
-        f.write(img.serialize())
+    img.write_file(path)
     print(json.dumps({"addrs": addrs, "ids": ids}), flush=True)
 
 
 def restore(path):
     data = contents()
-    with open(path, "rb") as f:
-        blob = f.read()
     ctx = K.Context(chunk_bytes=C)
-    img = K.Image.load(blob, ctx)
-    rc, rep, addrs = ctx.restore_at(img)
+    # the restart path: the address ranges come first, before any other
+    # device or pinned memory of this process
+    rc, rep, addrs, img = ctx.restore_file_at(path)
     same = [bool(np.array_equal(d2h(p, a.size), a)) for p, a in zip(addrs, data)]
     ids = [int(x) for x in img.allocs["id"]]
     # the restored context keeps the image's ids, so it can continue incrementally

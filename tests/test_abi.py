@@ -54,11 +54,11 @@ def test_binding_declares_every_symbol(ck):
 def test_strerror_covers_every_status(ck):
     lib = ck.lib()
     seen = set()
-    for st in range(0, -10, -1):
+    for st in range(0, -11, -1):
         s = lib.ckpt_strerror(st).decode()
         assert s and s != "unknown status"
         seen.add(s)
-    assert len(seen) == 10
+    assert len(seen) == 11
     assert lib.ckpt_strerror(-100).decode() == "unknown status"
 
 

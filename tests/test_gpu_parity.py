@@ -219,11 +219,18 @@ def test_incremental_base_mismatch():
     tensors = random_allocs([10000, 5000], seed=4)
     register_all(ctx, tensors)
     base = ctx.checkpoint()
-    ctx.register(random_allocs([64], seed=5)[0])
-    with pytest.raises(K.CkptError) as e:
-        ctx.checkpoint(mode=K.CKPT_INCREMENTAL, base=base)
-    assert e.value.status == K.CKPT_E_MISMATCH
+    # a new allocation since the base: an id-keyed increment, the new
+    # allocation's chunk DIRTY and nothing else
+    extra = random_allocs([64], seed=5)[0]
+    ctx.register(extra)
+    d = ctx.checkpoint(mode=K.CKPT_INCREMENTAL, base=base)
+    assert list(d.dirty_ids) == [base.info()["n_chunks"]]
+    # another chunk size is a mismatch
     other = K.Context(chunk_bytes=8192)
+    register_all(other, tensors)
+    with pytest.raises(K.CkptError) as e:
+        other.checkpoint(mode=K.CKPT_INCREMENTAL, base=base)
+    assert e.value.status == K.CKPT_E_MISMATCH
     with pytest.raises(K.CkptError) as e:
         other.restore(base, tensors)
     assert e.value.status == K.CKPT_E_MISMATCH

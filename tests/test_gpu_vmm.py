@@ -266,6 +266,40 @@ def test_restore_at_with_delta_and_corruption():
     ctx.close()
 
 
+def test_restore_file_at(tmp_path):
+    sizes = [3 * 4096 + 5, 70000, 16]
+    data = seeded(sizes, 7, zero=(2,))
+    ctx = K.Context(chunk_bytes=C)
+    ptrs = []
+    for a in data:
+        p, _ = ctx.vmm_alloc(a.size)
+        h2d(p, a)
+        ptrs.append(p)
+    img = ctx.checkpoint()
+    path = str(tmp_path / "a.ckpt")
+    img.write_file(path)
+    for p in ptrs:
+        ctx.vmm_free(p)
+    rc, rep, addrs, back = ctx.restore_file_at(path)
+    assert rc == K.CKPT_OK and rep["n_bad"] == 0 and addrs == ptrs
+    for p, a in zip(addrs, data):
+        assert np.array_equal(d2h(p, a.size), a)
+    assert np.array_equal(back.crc, img.crc) and np.array_equal(back.data, img.data)
+    # while the allocations live, the same call refills them in place
+    h2d(ptrs[1], np.zeros(70000, np.uint8))
+    rc, _, addrs2, back2 = ctx.restore_file_at(path)
+    assert rc == K.CKPT_OK and addrs2 == ptrs and ctx.live_count() == 3
+    assert np.array_equal(d2h(ptrs[1], 70000), data[1])
+    with pytest.raises(K.CkptError) as e:
+        ctx.restore_file_at(str(tmp_path / "missing.ckpt"), n_allocs=3)
+    assert e.value.status == K.CKPT_E_NOTFOUND
+    for p in ptrs:
+        ctx.vmm_free(p)
+    for im in (img, back, back2):
+        im.close()
+    ctx.close()
+
+
 def test_restart_in_a_fresh_process_at_the_same_addresses(tmp_path):
     """Save in one fresh process, restore in another: every allocation comes
     back at its address, with its id, and an incremental checkpoint against
