@@ -359,6 +359,70 @@ __device__ __forceinline__ uint32_t wave_rounds(const Tabs<REP> &T, const Desc &
     return acc;
 }
 
+// Chunks of at most one batch of rounds (r_win <= kLoadsInFlight / G, one
+// wave per chunk): the same steps as wave_rounds, split into the loads and the
+// rest, so that a wave can have the next chunk's loads in flight while it
+// hashes, combines and finishes the current one.
+template <int MODE, int G, bool NT>
+__device__ __forceinline__ void small_loads(const Desc &d, int lane, uint32_t r_win, uint4 (&v)[kLoadsInFlight / G][G])
+{
+    constexpr int B = kLoadsInFlight / G;
+    constexpr uint32_t per_round = 64 * G;
+    const uint32_t np = (d.len + 15) >> 4;
+    const uint32_t z = r_win * per_round - np;
+    const uint32_t r0 = z / per_round;
+#pragma unroll
+    for (int b = 0; b < B; b++)
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            const int p = (int)((r0 + b) * per_round + lane * G + j) - (int)z;
+            v[b][j] = make_uint4(0u, 0u, 0u, 0u);
+            if (r0 + b < r_win && p >= 0)
+                v[b][j] = load_piece<MODE, NT>(d, (uint32_t)p * 16);
+        }
+}
+
+template <int MODE, int G, bool NT, bool REP>
+__device__ __forceinline__ uint32_t small_rest(const Tabs<REP> &T, const Desc &d, int lane, uint32_t r_win,
+                                               uint4 (&v)[kLoadsInFlight / G][G], uint32_t *orv)
+{
+    constexpr int B = kLoadsInFlight / G;
+    constexpr uint32_t per_round = 64 * G;
+    const uint32_t np = (d.len + 15) >> 4;
+    const uint32_t z = r_win * per_round - np;
+    const uint32_t r0 = z / per_round;
+    uint32_t acc = 0, o = 0;
+#pragma unroll
+    for (int b = 0; b < B; b++) {
+        const uint32_t r = r0 + b;
+        if (r >= r_win)
+            break;
+        if (b > 0)
+            acc = T.gap(acc);
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            const int p = (int)(r * per_round + lane * G + j) - (int)z;
+            if (p >= 0)
+                store_piece<MODE, NT>(d, (uint32_t)p * 16, v[b][j]);
+            o |= v[b][j].x | v[b][j].y | v[b][j].z | v[b][j].w;
+            if (p == 0)
+                v[b][j].x ^= init_mask(d.len);
+            acc = T.chain(acc, v[b][j].x);
+            acc = T.chain(acc, v[b][j].y);
+            acc = T.chain(acc, v[b][j].z);
+            acc = T.chain(acc, v[b][j].w);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kTreeLevels; k++) {
+        const uint32_t right = __shfl_down(acc, 1 << k, 64);
+        if ((lane & ((2 << k) - 1)) == 0)
+            acc = T.tree(k, acc) ^ right;
+    }
+    *orv = o;
+    return acc;
+}
+
 template <int MODE>
 __device__ __forceinline__ void finish_chunk(const ChunkArgs &a, const Desc &d, uint32_t raw, bool nonzero)
 {
@@ -376,6 +440,38 @@ __device__ __forceinline__ void finish_chunk(const ChunkArgs &a, const Desc &d, 
         a.flags[d.g] = f;
     }
 }
+
+// Balanced interleaved rounds: the M items go in R rounds of at most
+// gridDim.x * tile; round r covers [floor(M r / R), floor(M (r+1) / R)) and is
+// split evenly over the workgroups.  Every quotient is formed once: with
+// q = M / R and rem = M % R, a round's span is q or q + 1 (a carry from the
+// running remainder), and this workgroup's offsets within a span of either
+// size are fixed.  next() yields the workgroup's range in the next round.
+struct Rounds {
+    uint64_t R, q, rem, lo_a, hi_a, lo_b, hi_b, base, acc;
+
+    __device__ void init(uint64_t M, uint32_t tile)
+    {
+        const uint64_t per_round = (uint64_t)gridDim.x * tile;
+        R = (M + per_round - 1) / per_round;
+        q = R ? M / R : 0;
+        rem = R ? M % R : 0;
+        lo_a = q * blockIdx.x / gridDim.x;
+        hi_a = q * (blockIdx.x + 1) / gridDim.x;
+        lo_b = (q + 1) * blockIdx.x / gridDim.x;
+        hi_b = (q + 1) * (blockIdx.x + 1) / gridDim.x;
+        base = 0;
+        acc = 0;
+    }
+    __device__ void next(uint64_t *lo, uint64_t *hi)
+    {
+        const bool carry = acc + rem >= R;   // acc, rem < R: no overflow
+        *lo = base + (carry ? lo_b : lo_a);
+        *hi = base + (carry ? hi_b : hi_a);
+        base += q + (carry ? 1 : 0);
+        acc = carry ? acc + rem - R : acc + rem;
+    }
+};
 
 // The descriptor of item i (chunk g = i, or ids[i] in a delta restore).
 template <int MODE>
@@ -412,7 +508,10 @@ __device__ __forceinline__ Desc make_desc(const ChunkArgs &a, uint64_t i, uint32
     return d;
 }
 
-template <int MODE, int G, bool NT, bool REP>
+// SMALL: every chunk is one batch of rounds and one wave hashes it (the host
+// picks this instantiation only then); the wave keeps the next chunk's loads in
+// flight while it finishes the current one.
+template <int MODE, int G, bool NT, bool REP, bool SMALL = false>
 __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
 {
     __shared__ uint32_t tabs[REP ? kRepWords : kTabTotalWords];
@@ -438,31 +537,55 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
     const uint32_t r_win = rw * W;
     const uint64_t M = (MODE == kModeRestore) ? a.plan->n_items : a.plan->n_chunks;
 
-    // The items go in R rounds of at most gridDim.x * kTile; each round is
-    // split evenly over the workgroups, so the whole grid sweeps one window of
-    // memory at a time and no workgroup gets more than one item above another.
-    const uint64_t per_round = (uint64_t)gridDim.x * kTile;
-    const uint64_t R = (M + per_round - 1) / per_round;
-    auto tile_lo = [&](uint64_t r) {
-        const uint64_t base = M * r / R, span = M * (r + 1) / R - base;
-        return base + span * blockIdx.x / gridDim.x;
-    };
-    auto tile_hi = [&](uint64_t r) {
-        const uint64_t base = M * r / R, span = M * (r + 1) / R - base;
-        return base + span * (blockIdx.x + 1) / gridDim.x;
-    };
+    // The items go in rounds of at most gridDim.x * kTile, each split evenly
+    // over the workgroups, so the whole grid sweeps one window of memory at a
+    // time and no workgroup gets more than one item above another.
+    Rounds rs;
+    rs.init(M, kTile);
+    const uint64_t R = rs.R;
     const bool stager = threadIdx.x < kTile;
-    uint64_t g0 = R ? tile_lo(0) : 0, hi = R ? tile_hi(0) : 0;
+    uint64_t g0 = 0, hi = 0;
+    if (R)
+        rs.next(&g0, &hi);
     if (stager && g0 + threadIdx.x < hi)
         desc[0][threadIdx.x] = make_desc<MODE>(a, g0 + threadIdx.x, C);
     int buf = 0;
     for (uint64_t r = 0; r < R; r++, buf ^= 1) {
         __syncthreads();   // tables and this tile's descriptors are in LDS
-        const uint64_t n0 = r + 1 < R ? tile_lo(r + 1) : 0, n1 = r + 1 < R ? tile_hi(r + 1) : 0;
+        uint64_t n0 = 0, n1 = 0;
+        if (r + 1 < R)
+            rs.next(&n0, &n1);
         Desc nd;
         if (stager && n0 + threadIdx.x < n1)
             nd = make_desc<MODE>(a, n0 + threadIdx.x, C);   // loads in flight during the tile
         const int cnt = (int)(hi - g0);   // uniform over the workgroup, at most kTile
+        if constexpr (SMALL) {
+            // one batch per chunk: the next chunk's loads go out before this
+            // chunk is hashed, combined and finished
+            uint4 cur[kLoadsInFlight / G][G], nxt[kLoadsInFlight / G][G];
+            Desc dn;
+            if (group < cnt) {
+                dn = desc[buf][group];
+                small_loads<MODE, G, NT>(dn, lane, r_win, nxt);
+            }
+            for (int t = group; t < cnt; t += groups) {
+                const Desc d = dn;
+#pragma unroll
+                for (int b = 0; b < kLoadsInFlight / G; b++)
+#pragma unroll
+                    for (int j = 0; j < G; j++)
+                        cur[b][j] = nxt[b][j];
+                if (t + groups < cnt) {
+                    dn = desc[buf][t + groups];
+                    small_loads<MODE, G, NT>(dn, lane, r_win, nxt);
+                }
+                uint32_t orv = 0;
+                const uint32_t raw = small_rest<MODE, G, NT, REP>(T, d, lane, r_win, cur, &orv);
+                const bool nonzero = __ballot(orv != 0) != 0;
+                if (lane == 0)
+                    finish_chunk<MODE>(a, d, raw, nonzero);
+            }
+        } else {
         for (int slot = 0; slot < cnt; slot += groups) {
             const int t = slot + group;
             const bool valid = t < cnt;
@@ -493,6 +616,7 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
                 }
                 __syncthreads();
             }
+        }
         }
         if (stager && n0 + threadIdx.x < n1)
             desc[buf ^ 1][threadIdx.x] = nd;   // the other tile was consumed before the last barrier
@@ -560,24 +684,21 @@ __global__ __launch_bounds__(1024) void k_rows(RowArgs a)
     const uint64_t M = a.n_items;
 
     // Balanced interleaved rounds and double-buffered descriptors, as in k_chunks.
-    const uint64_t per_round = (uint64_t)gridDim.x * kTile;
-    const uint64_t R = (M + per_round - 1) / per_round;
-    auto tile_lo = [&](uint64_t r) {
-        const uint64_t base = M * r / R, span = M * (r + 1) / R - base;
-        return base + span * blockIdx.x / gridDim.x;
-    };
-    auto tile_hi = [&](uint64_t r) {
-        const uint64_t base = M * r / R, span = M * (r + 1) / R - base;
-        return base + span * (blockIdx.x + 1) / gridDim.x;
-    };
+    Rounds rs;
+    rs.init(M, kTile);
+    const uint64_t R = rs.R;
     const bool stager = threadIdx.x < kTile;
-    uint64_t g0 = R ? tile_lo(0) : 0, hi = R ? tile_hi(0) : 0;
+    uint64_t g0 = 0, hi = 0;
+    if (R)
+        rs.next(&g0, &hi);
     if (stager && g0 + threadIdx.x < hi)
         desc[0][threadIdx.x] = make_row_desc(a, g0 + threadIdx.x, C);
     int buf = 0;
     for (uint64_t r = 0; r < R; r++, buf ^= 1) {
         __syncthreads();
-        const uint64_t n0 = r + 1 < R ? tile_lo(r + 1) : 0, n1 = r + 1 < R ? tile_hi(r + 1) : 0;
+        uint64_t n0 = 0, n1 = 0;
+        if (r + 1 < R)
+            rs.next(&n0, &n1);
         RowDesc nd;
         if (stager && n0 + threadIdx.x < n1)
             nd = make_row_desc(a, n0 + threadIdx.x, C);
@@ -843,10 +964,18 @@ template <int MODE>
 static void launch_chunks_m(hipStream_t s, const ChunkArgs &a, int grid, int block)
 {
     if (a.table_mode == kTableReplicated) {     // G = 1 only
-        if (a.nontemporal)
+        // one wave per chunk and one batch of rounds per chunk: the pipelined form
+        const bool small = a.waves_per_chunk == 1 && (a.C + kRoundBytes - 1) / kRoundBytes <= kLoadsInFlight;
+        if (small) {
+            if (a.nontemporal)
+                hipLaunchKernelGGL((k_chunks<MODE, 1, true, true, true>), dim3(grid), dim3(block), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_chunks<MODE, 1, false, true, true>), dim3(grid), dim3(block), 0, s, a);
+        } else if (a.nontemporal) {
             hipLaunchKernelGGL((k_chunks<MODE, 1, true, true>), dim3(grid), dim3(block), 0, s, a);
-        else
+        } else {
             hipLaunchKernelGGL((k_chunks<MODE, 1, false, true>), dim3(grid), dim3(block), 0, s, a);
+        }
         return;
     }
     switch (a.lane_pieces) {
