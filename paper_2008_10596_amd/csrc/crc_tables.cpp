@@ -41,7 +41,7 @@ void build_tables(uint32_t *out, uint32_t G, uint32_t rounds_per_wave)
 {
     const uint64_t round = (uint64_t)kRoundBytes * G;
     build_operator(out + kTabChain, 4);
-    build_operator(out + kTabGap, round - 16ull * G);
+    build_operator(out + kTabGap, round);   // one round: the lane's next piece is a round later
     for (int k = 0; k < kTreeLevels; k++)
         build_operator(out + kTabTree + k * kTabWords, (16ull * G) << k);
     build_operator(out + kTabSeg, (uint64_t)rounds_per_wave * round);
@@ -50,8 +50,8 @@ void build_tables(uint32_t *out, uint32_t G, uint32_t rounds_per_wave)
 void build_tables_replicated(uint32_t *out, uint32_t rounds_per_wave)
 {
     std::vector<uint32_t> op(kTabWords);
-    // gap (1008 bytes), 8 copies per entry
-    build_operator(op.data(), kRoundBytes - 16);
+    // one round (1024 bytes), 8 copies per entry
+    build_operator(op.data(), kRoundBytes);
     for (int j = 0; j < 4; j++)
         for (int b = 0; b < 256; b++)
             for (int r = 0; r < 8; r++)

@@ -71,6 +71,7 @@ struct Tabs {
         }
         return y;
     }
+    // the register moved one round (kRoundBytes * G bytes) forward
     __device__ __forceinline__ uint32_t gap(uint32_t v) const
     {
         if (!REP)
@@ -327,26 +328,33 @@ __device__ __forceinline__ uint32_t wave_rounds(const Tabs<REP> &T, const Desc &
                 if (rb + b < r_end && p >= 0)
                     v[b][j] = load_piece<MODE, NT>(d, (uint32_t)p * 16);
             }
+        // Each round's contribution is chained from a zero register, so the
+        // rounds' lookups are independent; they are combined by Horner's rule
+        // with the one-round shift.  Pieces past r_end are zero and add nothing.
+        uint32_t c[B];
 #pragma unroll
         for (int b = 0; b < B; b++) {
             const uint32_t r = rb + b;
-            if (r >= r_end)
-                break;
-            if (r > r0)
-                acc = T.gap(acc);
+            c[b] = 0;
 #pragma unroll
             for (int j = 0; j < G; j++) {
                 const int p = (int)(r * per_round + lane * G + j) - (int)z;
-                if (p >= 0)
+                if (r < r_end && p >= 0)
                     store_piece<MODE, NT>(d, (uint32_t)p * 16, v[b][j]);
                 o |= v[b][j].x | v[b][j].y | v[b][j].z | v[b][j].w;
                 if (p == 0)
                     v[b][j].x ^= init_mask(d.len);
-                acc = T.chain(acc, v[b][j].x);
-                acc = T.chain(acc, v[b][j].y);
-                acc = T.chain(acc, v[b][j].z);
-                acc = T.chain(acc, v[b][j].w);
+                c[b] = T.chain(c[b], v[b][j].x);
+                c[b] = T.chain(c[b], v[b][j].y);
+                c[b] = T.chain(c[b], v[b][j].z);
+                c[b] = T.chain(c[b], v[b][j].w);
             }
+        }
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            const uint32_t r = rb + b;
+            if (r < r_end)
+                acc = (r > r0 ? T.gap(acc) : 0u) ^ c[b];
         }
     }
 #pragma unroll
@@ -391,28 +399,30 @@ __device__ __forceinline__ uint32_t small_rest(const Tabs<REP> &T, const Desc &d
     const uint32_t np = (d.len + 15) >> 4;
     const uint32_t z = r_win * per_round - np;
     const uint32_t r0 = z / per_round;
-    uint32_t acc = 0, o = 0;
+    uint32_t acc = 0, o = 0, c[B];
+    // independent per-round chains, then Horner's rule (as in wave_rounds)
 #pragma unroll
     for (int b = 0; b < B; b++) {
         const uint32_t r = r0 + b;
-        if (r >= r_win)
-            break;
-        if (b > 0)
-            acc = T.gap(acc);
+        c[b] = 0;
 #pragma unroll
         for (int j = 0; j < G; j++) {
             const int p = (int)(r * per_round + lane * G + j) - (int)z;
-            if (p >= 0)
+            if (r < r_win && p >= 0)
                 store_piece<MODE, NT>(d, (uint32_t)p * 16, v[b][j]);
             o |= v[b][j].x | v[b][j].y | v[b][j].z | v[b][j].w;
             if (p == 0)
                 v[b][j].x ^= init_mask(d.len);
-            acc = T.chain(acc, v[b][j].x);
-            acc = T.chain(acc, v[b][j].y);
-            acc = T.chain(acc, v[b][j].z);
-            acc = T.chain(acc, v[b][j].w);
+            c[b] = T.chain(c[b], v[b][j].x);
+            c[b] = T.chain(c[b], v[b][j].y);
+            c[b] = T.chain(c[b], v[b][j].z);
+            c[b] = T.chain(c[b], v[b][j].w);
         }
     }
+#pragma unroll
+    for (int b = 0; b < B; b++)
+        if (r0 + b < r_win)
+            acc = (b > 0 ? T.gap(acc) : 0u) ^ c[b];
 #pragma unroll
     for (int k = 0; k < kTreeLevels; k++) {
         const uint32_t right = __shfl_down(acc, 1 << k, 64);
