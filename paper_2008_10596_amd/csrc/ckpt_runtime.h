@@ -192,7 +192,7 @@ struct ckpt_ctx {
     // device buffers
     ckpt::DevBuf d_tables, d_plan, d_addr, d_size, d_off, d_cb, d_map;
     ckpt::DevBuf d_crc, d_flags, d_base_crc, d_prev_crc, d_soff, d_ids, d_tile_b, d_tile_c;
-    ckpt::DevBuf d_dense, d_compact, d_bad, d_pick, d_crc2, d_flags2, d_soff2, d_base_cb;
+    ckpt::DevBuf d_dense, d_compact, d_bad, d_pick, d_crc2, d_flags2, d_soff2, d_base_cb, d_snap_flags;
     ckpt::PinnedBuf h_up, h_plan, h_base_cb;
     uint64_t prev_serial = 0;   // image whose CRC array is in d_prev_crc
 
@@ -202,7 +202,7 @@ struct ckpt_ctx {
     {
         return {&d_tables, &d_plan, &d_addr, &d_size, &d_off, &d_cb, &d_map, &d_crc, &d_flags, &d_base_crc,
                 &d_prev_crc, &d_soff, &d_ids, &d_tile_b, &d_tile_c, &d_dense, &d_compact, &d_bad, &d_pick,
-                &d_crc2, &d_flags2, &d_soff2, &d_base_cb};
+                &d_crc2, &d_flags2, &d_soff2, &d_base_cb, &d_snap_flags};
     }
 };
 

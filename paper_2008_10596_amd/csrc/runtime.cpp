@@ -781,7 +781,10 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
         HIP_TRY(hipDeviceSynchronize());
         T.order_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
-    CKPT_TRY(order_after_meta(ctx, s));
+    // The previous call's host copies may still be running on the side stream;
+    // they read only the snapshot buffers (d_prev_crc, d_snap_flags), which
+    // this call writes only after waiting for them (order_after_meta below), so
+    // this call's table upload and pack overlap them.
     if (ctx->managed_prefetch)
         for (const Row &r : rows)
             if (r.kind == CKPT_MANAGED && r.size)
@@ -880,6 +883,7 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     PinnedBuf all_data;              // one pinned buffer when there is a single output
 
     hipStream_t ds = ctx->side;      // drain stream
+    bool snap = false;               // the host copies read the snapshot buffers
     if (incremental) {
         // The delta is gathered from the allocations themselves, so it must be
         // taken before `s` may run new work: hash, select and gather all on s.
@@ -887,6 +891,18 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
         CKPT_TRY(read_plan(ctx, s, &P));
         ds = s;
     } else {
+        if (no_drain && N) {
+            // Snapshot the CRC and flag arrays for the host copies, which then
+            // run on the side stream after this call returns: the next pack may
+            // overwrite d_crc / d_flags at once.  The CRC snapshot is also the
+            // base of the next increment.
+            CKPT_TRY(order_after_meta(ctx, s));
+            CKPT_TRY(ctx->d_prev_crc.ensure(N * 4));
+            CKPT_TRY(ctx->d_snap_flags.ensure(N));
+            HIP_TRY(hipMemcpyAsync(ctx->d_prev_crc.p, ctx->d_crc.p, N * 4, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(ctx->d_snap_flags.p, ctx->d_flags.p, N, hipMemcpyDeviceToDevice, s));
+            snap = true;
+        }
         HIP_TRY(hipEventRecord(ctx->ev[3], s));   // packed: the caller's stream is free
         HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->ev[3], 0));
         if (no_drain) {
@@ -991,8 +1007,10 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     auto meta = std::make_shared<PinnedBuf>();
     CKPT_TRY(meta->ensure(std::max<uint64_t>(5 * N, 8)));
     if (N) {
-        HIP_TRY(hipMemcpyAsync(meta->p, ctx->d_crc.p, N * 4, hipMemcpyDeviceToHost, ds));
-        HIP_TRY(hipMemcpyAsync((uint8_t *)meta->p + 4 * N, ctx->d_flags.p, N, hipMemcpyDeviceToHost, ds));
+        const void *crc_src = snap ? ctx->d_prev_crc.p : ctx->d_crc.p;
+        const void *flags_src = snap ? ctx->d_snap_flags.p : ctx->d_flags.p;
+        HIP_TRY(hipMemcpyAsync(meta->p, crc_src, N * 4, hipMemcpyDeviceToHost, ds));
+        HIP_TRY(hipMemcpyAsync((uint8_t *)meta->p + 4 * N, flags_src, N, hipMemcpyDeviceToHost, ds));
     }
     for (size_t i = 0; i < nout; i++) {
         auto *img = new ckpt_image();
@@ -1031,7 +1049,10 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
             HIP_TRY(hipMemcpyAsync(imgs[0]->ids_buf.p, ctx->d_ids.p, P.sel_count * 8, hipMemcpyDeviceToHost, ds));
     }
     // keep this CRC array on the device as the base of the next increment
-    if (nout == 1 && N) {
+    // (the snapshot already is)
+    if (nout == 1 && N && !snap) {
+        if (ds == s)
+            CKPT_TRY(order_after_meta(ctx, s));   // earlier host copies may read d_prev_crc
         CKPT_TRY(ctx->d_prev_crc.ensure(N * 4));
         HIP_TRY(hipMemcpyAsync(ctx->d_prev_crc.p, ctx->d_crc.p, N * 4, hipMemcpyDeviceToDevice, ds));
     }
