@@ -195,6 +195,8 @@ struct ckpt_ctx {
     ckpt::DevBuf d_dense, d_compact, d_bad, d_pick, d_crc2, d_flags2, d_soff2, d_base_cb, d_snap_flags;
     ckpt::PinnedBuf h_up, h_plan, h_base_cb;
     uint64_t prev_serial = 0;   // image whose CRC array is in d_prev_crc
+    uint32_t zero_crc = 0;      // CRC-32C of chunk_bytes zero bytes, once computed
+    bool zero_crc_ready = false;
 
     ckpt_timing timing{};
 

@@ -433,6 +433,21 @@ __device__ __forceinline__ uint32_t small_rest(const Tabs<REP> &T, const Desc &d
     return acc;
 }
 
+// Restore of a full-length ZERO chunk: its bytes are zeros, so its CRC is the
+// CRC of C zero bytes, known beforehand; the wave stores the zeros and the
+// stored CRC is compared with that value, with no table lookups.
+template <bool NT>
+__device__ __forceinline__ void restore_zero_chunk(const ChunkArgs &a, const Desc &d, int lane)
+{
+    const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+    for (uint32_t p = (uint32_t)lane * 16; p < d.len; p += 64 * 16)
+        st16<NT>((uint8_t *)d.dst + p, zero);
+    if (lane == 0 && a.zero_crc != d.want) {
+        a.bad[d.g] = 1;
+        atomicAdd(&a.plan_rw->bad_count, 1ull);
+    }
+}
+
 template <int MODE>
 __device__ __forceinline__ void finish_chunk(const ChunkArgs &a, const Desc &d, uint32_t raw, bool nonzero)
 {
@@ -589,6 +604,10 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
                     dn = desc[buf][t + groups];
                     small_loads<MODE, G, NT>(dn, lane, r_win, nxt);
                 }
+                if (MODE == kModeRestore && d.zero && d.len == C) {   // uniform over the wave
+                    restore_zero_chunk<NT>(a, d, lane);
+                    continue;
+                }
                 uint32_t orv = 0;
                 const uint32_t raw = small_rest<MODE, G, NT, REP>(T, d, lane, r_win, cur, &orv);
                 const bool nonzero = __ballot(orv != 0) != 0;
@@ -603,6 +622,10 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
             Desc d;
             if (valid) {
                 d = desc[buf][t];
+                if (MODE == kModeRestore && W == 1 && d.zero && d.len == C) {   // uniform over the wave
+                    restore_zero_chunk<NT>(a, d, lane);
+                    continue;
+                }
                 raw = wave_rounds<MODE, G, NT, REP>(T, d, lane, wig * rw, (wig + 1) * rw, r_win, &orv);
             }
             const bool nonzero = __ballot(orv != 0) != 0;

@@ -1255,6 +1255,11 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
     a.soff = (const uint64_t *)ctx->d_soff.p;
     a.want_crc = (const uint32_t *)ctx->d_crc.p;
     a.want_flags = (const uint8_t *)ctx->d_flags.p;
+    if (!ctx->zero_crc_ready) {   // CRC-32C of C zero bytes: init through C zero bytes, xorout
+        ctx->zero_crc = host_shift(0xFFFFFFFFu, ctx->cfg.chunk_bytes) ^ 0xFFFFFFFFu;
+        ctx->zero_crc_ready = true;
+    }
+    a.zero_crc = ctx->zero_crc;
     a.bad = (uint8_t *)ctx->d_bad.p;
     DevPlan P;
     if (N) {

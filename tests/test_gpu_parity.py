@@ -296,6 +296,35 @@ def test_corruption_is_reported_exactly():
     assert rep["ids"] == list(range(min(64, img.info()["n_chunks"])))
 
 
+@pytest.mark.parametrize("C", [1024, 4096, 65536])
+def test_zero_chunks_verified_on_every_path(C):
+    """Full-length ZERO chunks are restored without hashing (their CRC is the
+    CRC of C zero bytes); ZERO tails are hashed.  Both must verify, and a
+    changed stored CRC on either must be reported exactly."""
+    sizes = [3 * C, 2 * C + 48, C]
+    tensors = random_allocs(sizes, seed=11)
+    tensors[0][C:2 * C] = 0                      # chunk 1: full ZERO
+    tensors[1][2 * C:] = 0                       # chunk 5: ZERO tail of 48 bytes
+    tensors[2].zero_()                           # chunk 6: full ZERO
+    ctx = K.Context(chunk_bytes=C)
+    register_all(ctx, tensors)
+    img = ctx.checkpoint()
+    ref = O.checkpoint([host(t) for t in tensors], C)
+    assert np.array_equal(img.flags, ref["flags"]) and np.array_equal(img.crc, ref["crc"])
+    assert [g for g in range(len(ref["flags"])) if ref["flags"][g] & FLAG_ZERO] == [1, 5, 6]
+    dsts = [torch.full((s,), 0x5A, dtype=torch.uint8, device="cuda") for s in sizes]
+    rc, rep = ctx.restore(img, dsts)
+    assert rc == K.CKPT_OK, rep
+    check_restored(dsts, tensors)
+    for g in (1, 5, 6):
+        img.crc[g] ^= 0x80
+        rc, rep = ctx.restore(img, dsts)
+        assert rc == K.CKPT_E_CORRUPT and rep["ids"] == [g], (g, rep)
+        img.crc[g] ^= 0x80
+    img.close()
+    ctx.close()
+
+
 def test_many_bad_report_first_64_of_many():
     C = 256
     tensors = random_allocs([C * 500 + 7], seed=9)
