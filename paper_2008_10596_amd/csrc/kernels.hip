@@ -302,6 +302,48 @@ __device__ __forceinline__ void store_piece(const Desc &d, uint32_t start, uint4
 // 16-byte loads each lane keeps in flight before hashing them.
 constexpr int kLoadsInFlight = 4;
 
+// The register of the lane K places down (lane + K), for K < 16: a DPP row
+// shift, with no LDS round trip.  Lanes whose source is outside their row of
+// 16 get 0; the combine below reads only lanes whose source is inside.
+template <int K>
+__device__ __forceinline__ uint32_t dpp_down(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + K, 0xF, 0xF, true);
+}
+
+// Combine the 64 lanes' registers into lane 0: at level k, lane i (a multiple
+// of 2^(k+1)) moves its register past the 16 * 2^k bytes of lane i + 2^k's
+// share and adds that lane's register.  Levels 0-3 stay inside rows of 16
+// lanes (DPP); levels 4 and 5 cross rows (__shfl_down).  The whole wave must
+// be active.
+static_assert(kTreeLevels == 6, "the combine is written out for 64 lanes");
+
+template <bool REP>
+__device__ __forceinline__ uint32_t wave_combine(const Tabs<REP> &T, uint32_t acc, int lane)
+{
+    uint32_t right = dpp_down<1>(acc);
+    if ((lane & 1) == 0)
+        acc = T.tree(0, acc) ^ right;
+    right = dpp_down<2>(acc);
+    if ((lane & 3) == 0)
+        acc = T.tree(1, acc) ^ right;
+    right = dpp_down<4>(acc);
+    if ((lane & 7) == 0)
+        acc = T.tree(2, acc) ^ right;
+    right = dpp_down<8>(acc);
+    if ((lane & 15) == 0)
+        acc = T.tree(3, acc) ^ right;
+    right = __shfl_down(acc, 16, 64);
+    if ((lane & 31) == 0)
+        acc = T.tree(4, acc) ^ right;
+    right = __shfl_down(acc, 32, 64);
+    if (lane == 0)
+        acc = T.tree(5, acc) ^ right;
+    return acc;
+}
+
+
+
 // One wave's share of a chunk: rounds [r_begin, r_end) of a window of r_win
 // rounds of 1024 G bytes.  Returns the raw register of those rounds in lane 0
 // (as a message ending with the wave's last round) and ORs the data words
@@ -357,12 +399,7 @@ __device__ __forceinline__ uint32_t wave_rounds(const Tabs<REP> &T, const Desc &
                 acc = (r > r0 ? T.gap(acc) : 0u) ^ c[b];
         }
     }
-#pragma unroll
-    for (int k = 0; k < kTreeLevels; k++) {
-        const uint32_t right = __shfl_down(acc, 1 << k, 64);
-        if ((lane & ((2 << k) - 1)) == 0)
-            acc = T.tree(k, acc) ^ right;
-    }
+    acc = wave_combine<REP>(T, acc, lane);
     *orv = o;
     return acc;
 }
@@ -423,12 +460,7 @@ __device__ __forceinline__ uint32_t small_rest(const Tabs<REP> &T, const Desc &d
     for (int b = 0; b < B; b++)
         if (r0 + b < r_win)
             acc = (b > 0 ? T.gap(acc) : 0u) ^ c[b];
-#pragma unroll
-    for (int k = 0; k < kTreeLevels; k++) {
-        const uint32_t right = __shfl_down(acc, 1 << k, 64);
-        if ((lane & ((2 << k) - 1)) == 0)
-            acc = T.tree(k, acc) ^ right;
-    }
+    acc = wave_combine<REP>(T, acc, lane);
     *orv = o;
     return acc;
 }
