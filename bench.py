@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=60, help="measured requests per rate")
     ap.add_argument("--serving-rates", default="10,50,150", help="arrival rates (req/s)")
     ap.add_argument("--serving-shapes", type=int, default=24)
+    ap.add_argument("--sections-only", action="store_true",
+                    help="diagnostic runs (e.g. counter passes): skip the headline at-scale steps and "
+                         "print only the --only sections as JSON")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after the timed steps, one plain device copy of this many bytes "
                          "(calibrates hardware byte counters against a known size)")
@@ -515,6 +518,16 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.cuda.get_device_properties(0)
     C = args.chunk
+    if args.sections_only:
+        stream = torch.cuda.current_stream()
+        sections = set(args.only.split(",")) if args.only else set()
+        out = {"sections_only": True}
+        if "incremental" in sections:
+            out["incremental"] = bench_incremental(K, synth, torch, stream, args)
+        if "batched" in sections:
+            out["batched"] = bench_batched(K, synth, torch, stream, args)
+        print(json.dumps(out), flush=True)
+        return
     w = synth.at_scale(cap=int(16 * synth.GiB * args.scale))
     sizes = [int(s) for s in w["sizes"]]
     log("workload: %d allocations, %.2f GiB, %d all-zero; device %s, %d CUs"

@@ -120,9 +120,8 @@ def fill_random_(t, seed):
         return t
     g = torch.Generator(device=t.device)
     g.manual_seed(int(seed) & ((1 << 63) - 1))
-    words = (n + 3) // 4
-    r = torch.randint(-(1 << 31), (1 << 31) - 1, (words,), dtype=torch.int32, device=t.device, generator=g)
-    t.copy_(r.view(torch.uint8)[:n])
+    # written in place: no intermediate tensor and no copy kernel
+    torch.randint(0, 256, (n,), dtype=torch.uint8, device=t.device, generator=g, out=t)
     return t
 
 
