@@ -415,6 +415,18 @@ __device__ __forceinline__ void small_loads(const Desc &d, int lane, uint32_t r_
     constexpr uint32_t per_round = 64 * G;
     const uint32_t np = (d.len + 15) >> 4;
     const uint32_t z = r_win * per_round - np;
+    if (d.len == r_win * per_round * 16 && (MODE != kModeRestore || !d.zero)) {
+        // the chunk fills the window exactly (uniform over the wave): every
+        // piece is 16 bytes of data
+#pragma unroll
+        for (int b = 0; b < B; b++)
+#pragma unroll
+            for (int j = 0; j < G; j++)
+                v[b][j] = (uint32_t)b < r_win
+                              ? ld16<NT>((const uint8_t *)d.src + ((uint32_t)b * per_round + lane * G + j) * 16)
+                              : make_uint4(0u, 0u, 0u, 0u);
+        return;
+    }
     const uint32_t r0 = z / per_round;
 #pragma unroll
     for (int b = 0; b < B; b++)
@@ -435,6 +447,40 @@ __device__ __forceinline__ uint32_t small_rest(const Tabs<REP> &T, const Desc &d
     constexpr uint32_t per_round = 64 * G;
     const uint32_t np = (d.len + 15) >> 4;
     const uint32_t z = r_win * per_round - np;
+    if (d.len == r_win * per_round * 16) {
+        // The chunk fills the window exactly (uniform over the wave): every
+        // piece is 16 bytes of data, and only lane 0's first piece carries the
+        // complemented init (the chunk is at least 16 bytes long).
+        uint32_t acc = 0, o = 0, c[B];
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            c[b] = 0;
+#pragma unroll
+            for (int j = 0; j < G; j++) {
+                const uint32_t off = ((uint32_t)b * per_round + lane * G + j) * 16;
+                if ((uint32_t)b < r_win) {
+                    if (MODE == kModePack)
+                        st16<NT>((uint8_t *)d.dst + off, v[b][j]);
+                    else if (MODE == kModeRestore)
+                        st16<NT>((uint8_t *)d.dst + off, v[b][j]);
+                }
+                o |= v[b][j].x | v[b][j].y | v[b][j].z | v[b][j].w;
+                if (b == 0 && j == 0 && lane == 0)
+                    v[b][j].x = ~v[b][j].x;
+                c[b] = T.chain(c[b], v[b][j].x);
+                c[b] = T.chain(c[b], v[b][j].y);
+                c[b] = T.chain(c[b], v[b][j].z);
+                c[b] = T.chain(c[b], v[b][j].w);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; b++)
+            if ((uint32_t)b < r_win)
+                acc = (b > 0 ? T.gap(acc) : 0u) ^ c[b];
+        acc = wave_combine<REP>(T, acc, lane);
+        *orv = o;
+        return acc;
+    }
     const uint32_t r0 = z / per_round;
     uint32_t acc = 0, o = 0, c[B];
     // independent per-round chains, then Horner's rule (as in wave_rounds)

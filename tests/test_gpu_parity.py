@@ -60,6 +60,47 @@ def test_edge_sizes_and_chunk_sizes(C):
     full_roundtrip(tensors, C)
 
 
+@pytest.mark.parametrize("C", [1024, 4096, 65536])
+def test_restore_writes_nothing_past_each_destination(C):
+    """Restore destinations are views of one buffer filled with a guard byte;
+    every byte outside [dst_k, dst_k + size_k) must keep it, including the
+    bytes between a size and the next multiple of 16 (tail pieces)."""
+    sizes = [1, 15, 17, C - 4, C + 12, 3 * C - 1, 2 * C, 70001]
+    tensors = random_allocs(sizes, seed=C + 1, zero=(6,))
+    ctx = K.Context(chunk_bytes=C)
+    register_all(ctx, tensors)
+    img = ctx.checkpoint()
+    gap = 64
+    offs, o = [], gap
+    for sz in sizes:
+        offs.append(o)
+        o += (sz + 15) // 16 * 16 + gap
+    buf = torch.full((o,), 0xEE, dtype=torch.uint8, device="cuda")
+    dsts = [buf[a:a + sz] for a, sz in zip(offs, sizes)]
+    rc, rep = ctx.restore(img, dsts)
+    assert rc == K.CKPT_OK, rep
+    check_restored(dsts, tensors)
+    h = host(buf)
+    mask = np.ones(o, bool)
+    for a, sz in zip(offs, sizes):
+        mask[a:a + sz] = False
+    assert (h[mask] == 0xEE).all(), np.flatnonzero(h[mask] != 0xEE)[:10]
+    # the same through a delta overlay
+    for t in tensors:
+        t[-1] ^= 0x5A
+    torch.cuda.synchronize()
+    delta = ctx.checkpoint(mode=K.CKPT_INCREMENTAL, base=img)
+    buf.fill_(0xEE)
+    rc, rep = ctx.restore(img, dsts, delta=delta)
+    assert rc == K.CKPT_OK, rep
+    check_restored(dsts, tensors)
+    h = host(buf)
+    assert (h[mask] == 0xEE).all()
+    img.close()
+    delta.close()
+    ctx.close()
+
+
 @pytest.mark.parametrize("block,wpc", [(64, 1), (256, 1), (256, 2), (256, 4), (512, 8), (1024, 1), (1024, 16)])
 @pytest.mark.parametrize("C", [4096, 65536])
 def test_launch_shapes(block, wpc, C):
