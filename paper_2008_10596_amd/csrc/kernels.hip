@@ -357,6 +357,49 @@ __device__ __forceinline__ uint32_t wave_rounds(const Tabs<REP> &T, const Desc &
     constexpr uint32_t per_round = 64 * G;                                // pieces per round
     const uint32_t np = (d.len + 15) >> 4;                                // data pieces
     const uint32_t z = r_win * per_round - np;                            // leading zero pieces
+    if (d.len == r_win * per_round * 16 && (MODE != kModeRestore || !d.zero)) {
+        // The chunk fills the window exactly (uniform over the wave): every
+        // piece is 16 bytes of data at offset (r * per_round + lane * G + j) * 16
+        // and only piece 0 carries the complemented init.
+        uint32_t acc = 0, o = 0;
+        for (uint32_t rb = r_begin; rb < r_end; rb += B) {
+            uint4 v[B][G];
+#pragma unroll
+            for (int b = 0; b < B; b++)
+#pragma unroll
+                for (int j = 0; j < G; j++)
+                    v[b][j] = rb + b < r_end
+                                  ? ld16<NT>((const uint8_t *)d.src + ((rb + b) * per_round + lane * G + j) * 16)
+                                  : make_uint4(0u, 0u, 0u, 0u);
+            uint32_t c[B];
+#pragma unroll
+            for (int b = 0; b < B; b++) {
+                const uint32_t r = rb + b;
+                c[b] = 0;
+#pragma unroll
+                for (int j = 0; j < G; j++) {
+                    if (MODE != kModeHash && r < r_end)
+                        st16<NT>((uint8_t *)d.dst + (r * per_round + lane * G + j) * 16, v[b][j]);
+                    o |= v[b][j].x | v[b][j].y | v[b][j].z | v[b][j].w;
+                    if (r == 0 && j == 0 && lane == 0)
+                        v[b][j].x = ~v[b][j].x;
+                    c[b] = T.chain(c[b], v[b][j].x);
+                    c[b] = T.chain(c[b], v[b][j].y);
+                    c[b] = T.chain(c[b], v[b][j].z);
+                    c[b] = T.chain(c[b], v[b][j].w);
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < B; b++) {
+                const uint32_t r = rb + b;
+                if (r < r_end)
+                    acc = (r > r_begin ? T.gap(acc) : 0u) ^ c[b];
+            }
+        }
+        acc = wave_combine<REP>(T, acc, lane);
+        *orv = o;
+        return acc;
+    }
     const uint32_t r0 = max(r_begin, z / per_round);                      // earlier rounds: all zero
     uint32_t acc = 0, o = 0;
     for (uint32_t rb = r0; rb < r_end; rb += B) {
