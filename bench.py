@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--table-mode", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed pack steps")
-    ap.add_argument("--drain-steps", type=int, default=3)
+    ap.add_argument("--drain-steps", type=int, default=5)
     ap.add_argument("--only", default="", help="comma list of extra sections to run "
                     "(drain,restore_at,incremental,batched,serving); default: all")
     ap.add_argument("--serving-requests", type=int, default=60, help="measured requests per rate")
@@ -127,11 +127,37 @@ def cpu_baseline(tensors, sizes, C, budget_bytes=2 << 30, reps=3):
         times.append(time.perf_counter() - t0)
         assert rc == 0
     t = statistics.median(times)
+    # one thread, on the allocations that fit the first 512 MiB of the sample
+    k1, tot1 = 0, 0
+    while k1 < len(ss) and (tot1 + ss[k1] <= (512 << 20) or k1 == 0):
+        tot1 += ss[k1]
+        k1 += 1
+    _, dense1, N1, alg1 = algorithmic_bytes(ss[:k1], C)
+    ptrs1 = O._ptr_array(hosts[:k1])
+    szs1 = np.array(ss[:k1], np.uint64)
+    t1s = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        rc = lib.oracle_checkpoint(k1, ptrs1, O._p(szs1, O._u64p), C, None, 1, O._p(dense[:dense1], O._u8p),
+                                   O._p(crc, O._u32p), O._p(flags, O._u8p), None, None)
+        t1s.append(time.perf_counter() - t0)
+        assert rc == 0
+    t1 = statistics.median(t1s)
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(alg / t / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": "first %d of %d allocations (%.2f GiB live, %d chunks) of the same workload; "
                       "median of %d runs of oracle_checkpoint (dense image + CRC + flags), host copies "
                       "made before timing" % (len(take), len(sizes), S / 2**30, N, reps),
-            "seconds": round(t, 3)}
+            "seconds": round(t, 3),
+            "value_1_thread": round(alg1 / t1 / 1e9, 3),
+            "sample_1_thread": "first %d allocations (%.2f GiB live) of the sample, one thread, median of %d"
+                               % (k1, tot1 / 2**30, reps),
+            "cpu_model": cpu}
 
 
 def bench_incremental(K, synth, torch, stream, args, reps=3):

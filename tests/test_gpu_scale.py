@@ -173,3 +173,47 @@ def test_batched_at_scale_sampled():
     leader.close()
     del sets
     free()
+
+
+def test_allocation_larger_than_4GiB():
+    """One allocation past 2^32 bytes: chunks around the 4 GiB boundary and the
+    tail checked against the oracle, dense and serialized bytes included, and
+    a restore compared on the device (64-bit offsets everywhere)."""
+    C = 4096
+    size = (4 << 30) + C + 100
+    t = torch.empty(size, dtype=torch.uint8, device="cuda")
+    synth.fill_random_(t, synth.alloc_seed(9, 0))
+    zc = (3 << 30) // C                       # one ZERO chunk below the boundary
+    t[zc * C:(zc + 1) * C] = 0
+    torch.cuda.synchronize()
+    log("large allocation: %d bytes" % size)
+    ctx = K.Context(chunk_bytes=C, flags=K.CKPT_KEEP_DENSE)
+    ctx.register(t)
+    img = ctx.checkpoint()
+    N = -(-size // C)
+    assert img.info()["n_chunks"] == N
+    crc, flags, data = img.crc, img.flags, img.data
+    dense_p, dense_n = img.dense_ptr
+    assert dense_n == r16(size)
+    # serialized offset of every chunk from the flags
+    lens = np.minimum(C, size - np.arange(N, dtype=np.int64) * C)
+    ser_len = np.where(flags & 1, 0, (lens + 15) // 16 * 16)
+    soff = np.concatenate([[0], np.cumsum(ser_len)])
+    b = (4 << 30) // C
+    for g0, g1 in ((0, 3), (zc - 1, zc + 2), (b - 2, b + 2), (N - 3, N)):
+        lo, hi = g0 * C, min(size, g1 * C)
+        piece = d2h(t.data_ptr() + lo, hi - lo)
+        ref = O.checkpoint([piece], C)
+        assert np.array_equal(crc[g0:g1], ref["crc"]), g0
+        assert np.array_equal(flags[g0:g1], ref["flags"]), g0
+        assert np.array_equal(data[soff[g0]:soff[g1]], ref["serialized"]), g0
+        assert np.array_equal(d2h(dense_p + lo, r16(hi) - lo), ref["dense"]), g0
+    assert flags[zc] & 1 and not flags[zc - 1] & 1
+    dst = torch.empty_like(t)
+    rc, rep = ctx.restore(img, [dst])
+    assert rc == K.CKPT_OK, rep
+    assert torch.equal(dst, t)
+    img.close()
+    ctx.close()
+    del t, dst
+    free()
