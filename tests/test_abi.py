@@ -103,3 +103,35 @@ def test_null_arguments_are_rejected(ck):
     assert lib.ckpt_restore_at(None, None, None, None, None, None) == ck.CKPT_E_INVAL
     lib.ckpt_destroy(None)
     lib.ckpt_image_free(None)
+
+
+def test_host_only_failures_before_any_device_work(ck, tmp_path):
+    """Calls that must fail on their arguments or files alone (no GPU here)."""
+    lib = ck.lib()
+    out = ctypes.c_void_p()
+    # files: missing, empty, and not an image
+    assert lib.ckpt_image_read_file(None, str(tmp_path / "missing.img").encode(), ctypes.byref(out)) == \
+        ck.CKPT_E_NOTFOUND
+    bad = tmp_path / "bad.img"
+    bad.write_bytes(b"NOTANIMAGE" * 20)
+    assert lib.ckpt_image_read_file(None, str(bad).encode(), ctypes.byref(out)) == ck.CKPT_E_INVAL
+    bad.write_bytes(b"")
+    assert lib.ckpt_image_read_file(None, str(bad).encode(), ctypes.byref(out)) == ck.CKPT_E_INVAL
+    assert lib.ckpt_image_read_file(None, None, ctypes.byref(out)) == ck.CKPT_E_INVAL
+    # a version-2 header that claims more allocation rows than the file holds
+    hdr = bytearray(b"CKPTIMG1")
+    hdr += (2).to_bytes(4, "little") + (0).to_bytes(4, "little") + (4096).to_bytes(4, "little") + \
+        (16).to_bytes(4, "little")
+    hdr += (3).to_bytes(8, "little") + bytes(56)
+    bad.write_bytes(bytes(hdr))
+    assert lib.ckpt_image_read_file(None, str(bad).encode(), ctypes.byref(out)) == ck.CKPT_E_INVAL
+    # hook flags, merge, file restore and sink arguments
+    assert lib.ckpt_hook_install(None, 0x80) == ck.CKPT_E_INVAL
+    assert lib.ckpt_hook_install(None, 0) == ck.CKPT_OK            # uninstall: nothing installed
+    a, f, x = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    assert lib.ckpt_hook_stats(ctypes.byref(a), ctypes.byref(f), ctypes.byref(x)) == ck.CKPT_OK
+    assert (a.value, f.value, x.value) == (0, 0, 0)
+    assert lib.ckpt_hook_malloc(0, 0, None) is None                 # 0 bytes: NULL, nothing logged
+    assert lib.ckpt_image_merge(None, None, ctypes.byref(out)) == ck.CKPT_E_INVAL
+    assert lib.ckpt_restore_file_at(None, None, b"x", None, None, None) == ck.CKPT_E_INVAL
+    assert lib.ckpt_image_write_file(None, b"x", 0, None) == ck.CKPT_E_INVAL
