@@ -211,8 +211,56 @@ def bench_incremental(K, synth, torch, stream, args, reps=3):
     for C in chunks:
         bases[C].close()
         ctxs[C].close()
+    out["churn"] = bench_churn(K, synth, torch, stream, args, tensors, sizes)
     del tensors
     return out
+
+
+def bench_churn(K, synth, torch, stream, args, tensors, sizes, C=65536, reps=3):
+    """Allocation-set changes between checkpoints: from a drained base, 1% of
+    the allocations are freed and as many new ones made (random bytes); the
+    increment is matched to the base by registration id, and the merge folds
+    base + increment into the current full image on the host."""
+    import numpy as np
+    ctx = K.Context(chunk_bytes=C, flags=K.CKPT_TIMING, **tune_kw(args))
+    for t in tensors:
+        ctx.register(t)
+    base = ctx.checkpoint(stream=stream)
+    rng = np.random.default_rng(synth.BASE_SEED)
+    gone = set(rng.choice(len(tensors), len(tensors) // 100, replace=False).tolist())
+    fresh = []
+    for j, k in enumerate(sorted(gone)):
+        ctx.unregister(tensors[k])
+        t = torch.empty(sizes[k], dtype=torch.uint8, device="cuda")
+        synth.fill_random_(t, synth.alloc_seed(3, k, phase=2))
+        fresh.append(t)
+    torch.cuda.synchronize()
+    for t in fresh:
+        ctx.register(t)
+    tm = []
+    for r in range(reps + 1):
+        d = ctx.checkpoint(stream=stream, mode=K.CKPT_INCREMENTAL, base=base)
+        if r:
+            tm.append(ctx.timing())
+        info = d.info()
+        if r < reps:
+            d.close()
+    t0 = time.perf_counter()
+    merged = K.merge(base, d)
+    merge_s = time.perf_counter() - t0
+    mi = merged.info()
+    res = {"chunk_bytes": C, "freed": len(gone), "new": len(fresh), "chunks": info["n_chunks"],
+           "dirty_chunks": info["n_dirty"],
+           "hash_ms": round(statistics.median(x["pack_ms"] for x in tm), 4),
+           "total_ms": round(statistics.median(x["total_ms"] for x in tm), 3),
+           "merge_s": round(merge_s, 3), "merged_bytes": mi["serialized_bytes"],
+           "merge_gbps_host": round(mi["serialized_bytes"] / merge_s / 1e9, 2)}
+    log("churn: %s" % res)
+    for im in (merged, d, base):
+        im.close()
+    ctx.close()
+    del fresh
+    return res
 
 
 def bench_batched(K, synth, torch, stream, args, reps=3):
@@ -735,10 +783,16 @@ def main():
             t0 = time.perf_counter()
             nbytes = img.write_file(path)
             w_s = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            back = K.Image.read_file(path, dctx)
+            r_s = time.perf_counter() - t0
+            same = back.info()["crc_digest"] == img.info()["crc_digest"]
+            back.close()
             os.unlink(path)
             result["sink"] = {"file_bytes": nbytes, "write_s": round(w_s, 3),
-                              "gbps": round(nbytes / w_s / 1e9, 2), "dir": sink_dir,
-                              "mode": "O_DIRECT (buffered where refused), fsync"}
+                              "gbps": round(nbytes / w_s / 1e9, 2), "read_s": round(r_s, 3),
+                              "read_gbps": round(nbytes / r_s / 1e9, 2), "read_back_equal": same,
+                              "dir": sink_dir, "mode": "O_DIRECT (buffered where refused), fsync"}
             log("sink: %s" % result["sink"])
         img.close()
         del dsts
