@@ -51,13 +51,14 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="only the timed pack steps")
     ap.add_argument("--drain-steps", type=int, default=5)
     ap.add_argument("--only", default="", help="comma list of extra sections to run "
-                    "(drain,restore_at,incremental,batched,serving); default: all")
+                    "(drain,restore_at,incremental,batched,serving,hook); default: all")
     ap.add_argument("--serving-requests", type=int, default=60, help="measured requests per rate")
     ap.add_argument("--serving-rates", default="10,50,150", help="arrival rates (req/s)")
     ap.add_argument("--serving-shapes", type=int, default=24)
     ap.add_argument("--sections-only", action="store_true",
                     help="diagnostic runs (e.g. counter passes): skip the headline at-scale steps and "
                          "print only the --only sections as JSON")
+    ap.add_argument("--hook-child", default="", help=argparse.SUPPRESS)   # internal: one hook timing run
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after the timed steps, one plain device copy of this many bytes "
                          "(calibrates hardware byte counters against a known size)")
@@ -418,6 +419,52 @@ def bench_restore_at(K, torch, tensors, sizes, C, stream, reps=3):
     return out
 
 
+def hook_child(mode):
+    """One fresh process: time allocate + free pairs of device tensors with
+    torch's own caching allocator ("torch") or through libckpt's allocation
+    hook ("hook": hipMalloc + registration; "stable": address-stable memory;
+    "_cache": with the hook's block cache)."""
+    import torch
+    from paper_2008_10596_amd import ckpt as K
+    from paper_2008_10596_amd import hook
+    ctx = K.Context()
+    if mode != "torch":
+        hook.install(ctx, address_stable=mode.startswith("stable"), cache=mode.endswith("_cache"))
+    sizes = [4096, 1 << 20, 16 << 20]
+    out = {}
+    for sz in sizes:
+        for _ in range(20):                       # warm
+            t = torch.empty(sz, dtype=torch.uint8, device="cuda")
+            del t
+        torch.cuda.synchronize()
+        n = 500
+        t0 = time.perf_counter()
+        for _ in range(n):
+            t = torch.empty(sz, dtype=torch.uint8, device="cuda")
+            del t
+        torch.cuda.synchronize()
+        out[str(sz)] = round((time.perf_counter() - t0) / n * 1e6, 2)
+    live = ctx.live_count()
+    print(json.dumps({"mode": mode, "us_per_alloc_free": out, "live_after": live}), flush=True)
+
+
+def bench_hook(args):
+    """Cost of logging every allocation (each mode in a fresh process, since
+    torch takes a new allocator only before its first device allocation)."""
+    import subprocess
+    res = {}
+    for mode in ("torch", "hook", "stable", "hook_cache", "stable_cache"):
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--hook-child", mode],
+                           capture_output=True, text=True, timeout=300)
+        if r.returncode != 0:
+            raise RuntimeError("hook child %s failed: %s" % (mode, r.stderr[-1000:]))
+        res[mode] = json.loads(r.stdout.strip().splitlines()[-1])["us_per_alloc_free"]
+    return {"us_per_alloc_free_by_bytes": res,
+            "note": "torch = its caching allocator; hook = every allocation hipMalloc'd and registered; "
+                    "stable = every allocation an address-stable VMM mapping, registered; "
+                    "_cache = the hook's block cache on (freed blocks reused on their stream)"}
+
+
 def bench_serving(K, synth, torch, args):
     """Serving workload (reduced sweep): Poisson arrivals of checkpoint (70%)
     and restore (30%) requests over a pool of request shapes of 1-256
@@ -579,6 +626,9 @@ def bench_serving(K, synth, torch, args):
 
 def main():
     args = parse()
+    if args.hook_child:
+        hook_child(args.hook_child)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(each GPU would drain its own allocations independently).", file=sys.stderr)
@@ -600,6 +650,8 @@ def main():
             out["incremental"] = bench_incremental(K, synth, torch, stream, args)
         if "batched" in sections:
             out["batched"] = bench_batched(K, synth, torch, stream, args)
+        if "hook" in sections:
+            out["hook"] = bench_hook(args)
         print(json.dumps(out), flush=True)
         return
     w = synth.at_scale(cap=int(16 * synth.GiB * args.scale))
@@ -712,7 +764,7 @@ def main():
         result["roofline"]["traffic_source"] = "profiles/" + prof[2]
 
     sections = set(args.only.split(",")) if args.only else {"drain", "restore_at", "incremental", "batched",
-                                                             "serving"}
+                                                             "serving", "hook"}
     if args.no_extras:
         sections = set()
     if "drain" in sections:
@@ -820,6 +872,9 @@ def main():
     if "serving" in sections:
         result["serving"] = bench_serving(K, synth, torch, args)
         torch.cuda.empty_cache()
+    if "hook" in sections:
+        result["hook"] = bench_hook(args)
+        log("hook: %s" % result["hook"])
     print(json.dumps(result), flush=True)
 
 

@@ -384,25 +384,47 @@ int ckpt_restore_file_at(ckpt_ctx *ctx, void *stream, const char *path, void **a
 #define CKPT_HOOK_ADDRESS_STABLE 0x1u   /* allocate with ckpt_vmm_alloc, so that
                                            ckpt_restore_at can bring every
                                            allocation back at its address      */
+#define CKPT_HOOK_CACHE 0x2u            /* keep freed blocks for reuse (below)   */
 
 /* Install ctx (NULL: none) as the context the hook logs into.  Resets the
- * hook counters.  CKPT_E_INVAL: unknown flags. */
+ * hook counters and releases the blocks cached for the previous context.
+ * CKPT_E_INVAL: unknown flags. */
 int ckpt_hook_install(ckpt_ctx *ctx, uint32_t flags);
 
-/* Allocate `bytes` on `device` (hipMalloc, or ckpt_vmm_alloc with
- * CKPT_HOOK_ADDRESS_STABLE) and register it when `device` is the installed
- * context's; other devices get plain unregistered hipMalloc memory.  NULL on
- * failure or for 0 bytes.  `stream` is not used: the memory is usable on any
- * stream. */
+/* Allocate `bytes` on `device` (hipMalloc, or an address-stable mapping of
+ * the context with CKPT_HOOK_ADDRESS_STABLE) and register exactly `bytes`
+ * there when `device` is the installed context's; other devices get plain
+ * unregistered hipMalloc memory.  NULL on failure or for 0 bytes.
+ *
+ * Without CKPT_HOOK_CACHE `stream` is not used and the memory is usable on
+ * any stream.  With it, blocks come in size classes (four per power of two,
+ * at least 512 bytes; address-stable ones are granularity multiples), and a
+ * freed block is kept, unregistered, for the next allocation of its class on
+ * the stream it was first allocated for: that allocation follows, in stream
+ * order, all work queued on that stream before the free.  As with any
+ * stream-ordered caching allocator, a caller that used the memory on other
+ * streams synchronizes them before freeing.  When the device runs out of
+ * memory the cached blocks are released and the allocation tried again. */
 void *ckpt_hook_malloc(size_t bytes, int device, void *stream);
 
-/* Unregister and free memory from ckpt_hook_malloc.  Waits for the device's
- * queued work before the memory is released.  bytes and stream are not used. */
+/* Unregister memory from ckpt_hook_malloc and free it: without
+ * CKPT_HOOK_CACHE after the device's queued work is done; with it into the
+ * cache, at once.  bytes and stream are not used. */
 void ckpt_hook_free(void *ptr, size_t bytes, int device, void *stream);
 
 /* Registered allocations and frees since ckpt_hook_install, and allocations
  * that failed. */
 int ckpt_hook_stats(uint64_t *allocs, uint64_t *frees, uint64_t *failures);
+
+/* Blocks and bytes the cache holds now, and allocations it served since
+ * ckpt_hook_install. */
+int ckpt_hook_cache_stats(uint64_t *blocks, uint64_t *bytes, uint64_t *hits);
+
+/* Release every cached block (after the device's queued work is done);
+ * *released (may be NULL) = their bytes.  ckpt_restore_at and
+ * ckpt_restore_file_at of the installed context do this first, so that the
+ * recorded addresses are free. */
+int ckpt_hook_trim(uint64_t *released);
 
 /* ----------------------------------------------------------------- image */
 

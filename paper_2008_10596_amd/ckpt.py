@@ -34,6 +34,7 @@ CKPT_DRAIN_DIRECT = 0x10
 CKPT_GRAPH = 0x20
 CKPT_NO_GRAPH = 0x40
 CKPT_HOOK_ADDRESS_STABLE = 0x1
+CKPT_HOOK_CACHE = 0x2
 CKPT_SEC_ALLOCS, CKPT_SEC_CRC, CKPT_SEC_FLAGS, CKPT_SEC_DATA, CKPT_SEC_DIRTY_IDS, CKPT_SEC_DENSE = range(6)
 CKPT_SEC_ADDRS = 6
 CKPT_REPORT_MAX = 64
@@ -143,6 +144,8 @@ SIGNATURES = [
     ("ckpt_hook_malloc", _vp, [ctypes.c_size_t, ctypes.c_int, _vp]),
     ("ckpt_hook_free", None, [_vp, ctypes.c_size_t, ctypes.c_int, _vp]),
     ("ckpt_hook_stats", ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64)] * 3),
+    ("ckpt_hook_cache_stats", ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64)] * 3),
+    ("ckpt_hook_trim", ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64)]),
     ("ckpt_restore_file_at", ctypes.c_int, [_vp, _vp, ctypes.c_char_p, ctypes.POINTER(_vp),
                                              ctypes.POINTER(ckpt_verify_report), ctypes.POINTER(_vp)]),
     ("ckpt_last_timing", ctypes.c_int, [_vp, ctypes.POINTER(ckpt_timing)]),

@@ -6,6 +6,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "ckpt.h"
@@ -136,16 +137,41 @@ void vmm_release_all(ckpt_ctx *ctx);
 // into one full image (ckpt_image_merge); else *merged stays empty.
 int fold_delta(const ckpt_image *img, const ckpt_image *delta, std::unique_ptr<ckpt_image> *merged);
 // A serialized image's header and tables, checked, without the CRC, flag,
-// id and DATA sections (which start at `rest`).  Host memory only.
+// id and DATA sections (the first three start at `rest`; DATA follows them,
+// head_bytes from the image's start).  Host memory only.
 struct ImageHead {
     uint32_t version = 0, mode = 0, C = 0;
     uint64_t N = 0, data_bytes = 0, ser_bytes = 0, n_dirty = 0, serial = 0, base_serial = 0, digest = 0;
+    uint64_t head_bytes = 0;
     std::vector<ckpt_alloc_rec> allocs;
     std::vector<uint64_t> addrs;
     const uint8_t *rest = nullptr;
 };
-int parse_head(const void *buf, size_t bytes, ImageHead *h);
-int read_whole_file(const char *path, std::vector<uint8_t> *buf);
+// Checks the fixed header at hdr (hdr_bytes readable) of an image of `avail`
+// bytes and gives the size of everything before DATA and of DATA.
+int head_layout(const void *hdr, size_t hdr_bytes, uint64_t avail, uint64_t *head_bytes, uint64_t *ser_bytes);
+// Parses buf[0, bytes).  data_apart = 0: buf is the whole image; else buf holds
+// at least everything before DATA and the caller holds DATA (data_apart bytes,
+// which must be ser_bytes) elsewhere.
+int parse_head(const void *buf, size_t bytes, ImageHead *h, uint64_t data_apart = 0);
+// A new drained image with h's tables and CRC/flag/id sections (the digest
+// checked; h's tables are moved out) and room for DATA, not yet filled.
+int image_from_head(ckpt_ctx *ctx, ImageHead *h, ckpt_image **out);
+// An image file opened for reading: its head read and checked, DATA not yet.
+struct ImageFile {
+    int fd = -1;
+    std::string path;
+    std::vector<uint8_t> head;
+    ImageHead h;
+    ImageFile() = default;
+    ImageFile(const ImageFile &) = delete;
+    ImageFile &operator=(const ImageFile &) = delete;
+    ~ImageFile();
+};
+int open_image_file(const char *path, ImageFile *f);
+// image_from_head, then DATA read from the file straight into the image's
+// pinned memory by several threads.
+int load_image_file(ckpt_ctx *ctx, ImageFile *f, ckpt_image **out);
 
 // The serialized form up to (not including) DATA, which follows it.
 size_t serialized_head_bytes(const ckpt_image *img);
@@ -155,6 +181,13 @@ void serialize_head(const ckpt_image *img, uint8_t *out);
 // are serialized by one process-wide lock, held only for a hooked context.
 std::recursive_mutex &hook_mutex();
 void hook_forget(ckpt_ctx *ctx);
+// Releases the hook's cached blocks when ctx is the installed context.
+void hook_trim_for(ckpt_ctx *ctx);
+// An address-stable block of `bytes` (a granularity multiple) placed by the
+// context, mapped but not registered; unmapped again by vmm_block_unmap (or
+// with the context's other ranges when it is destroyed).
+int vmm_block_map(ckpt_ctx *ctx, uint64_t bytes, uint64_t *base);
+void vmm_block_unmap(ckpt_ctx *ctx, uint64_t base);
 
 }  // namespace ckpt
 

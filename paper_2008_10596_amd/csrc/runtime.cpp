@@ -1613,11 +1613,12 @@ extern "C" int ckpt_image_serialize(const ckpt_image *img, void *buf, size_t cap
     return CKPT_OK;
 }
 
-int ckpt::parse_head(const void *buf, size_t bytes, ImageHead *h)
+int ckpt::head_layout(const void *hdr, size_t hdr_bytes, uint64_t avail, uint64_t *head_bytes, uint64_t *ser_bytes)
 {
-    if (bytes < kHeaderBytes)
-        return set_error(CKPT_E_INVAL, "truncated image header (%zu bytes)", bytes);
-    const uint8_t *p = (const uint8_t *)buf;
+    if (hdr_bytes < kHeaderBytes || avail < kHeaderBytes)
+        return set_error(CKPT_E_INVAL, "truncated image header (%llu bytes)",
+                         (unsigned long long)std::min<uint64_t>(hdr_bytes, avail));
+    const uint8_t *p = (const uint8_t *)hdr;
     if (memcmp(p, kMagic, 8) != 0)
         return set_error(CKPT_E_INVAL, "bad magic");
     uint32_t h32[4];
@@ -1628,23 +1629,41 @@ int ckpt::parse_head(const void *buf, size_t bytes, ImageHead *h)
         h32[2] % 16 != 0 || h32[3] != 16)
         return set_error(CKPT_E_INVAL, "bad header fields");
     const uint64_t n = h64[0], N = h64[1], nd = h64[4], ser = h64[3];
-    // bound every count by the buffer before multiplying
-    if (n > bytes / sizeof(ckpt_alloc_rec) || N > bytes / 5 || nd > bytes / 8 || ser > bytes)
+    // bound every count by the image's size before multiplying
+    if (n > avail / sizeof(ckpt_alloc_rec) || N > avail / 5 || nd > avail / 8 || ser > avail)
         return set_error(CKPT_E_INVAL, "truncated image");
-    const uint32_t version = h32[0];
-    const size_t total = serialized_size(version, n, N, nd, ser);
-    if (bytes < total)
-        return set_error(CKPT_E_INVAL, "truncated image: %zu of %zu bytes", bytes, total);
-    h->version = version;
+    const uint64_t total = serialized_size(h32[0], n, N, nd, ser);
+    if (avail < total)
+        return set_error(CKPT_E_INVAL, "truncated image: %llu of %llu bytes", (unsigned long long)avail,
+                         (unsigned long long)total);
+    *head_bytes = total - ser;
+    *ser_bytes = ser;
+    return CKPT_OK;
+}
+
+int ckpt::parse_head(const void *buf, size_t bytes, ImageHead *h, uint64_t data_apart)
+{
+    uint64_t head = 0, ser = 0;
+    CKPT_TRY(head_layout(buf, bytes, bytes + data_apart, &head, &ser));
+    if (data_apart && (data_apart != ser || bytes < head))
+        return set_error(CKPT_E_INVAL, "image sections do not match the header");
+    const uint8_t *p = (const uint8_t *)buf;
+    uint32_t h32[4];
+    uint64_t h64[8];
+    memcpy(h32, p + 8, 16);
+    memcpy(h64, p + 24, 64);
+    const uint64_t n = h64[0];
+    h->version = h32[0];
     h->mode = h32[1];
     h->C = h32[2];
-    h->N = N;
+    h->N = h64[1];
     h->data_bytes = h64[2];
     h->ser_bytes = ser;
-    h->n_dirty = nd;
+    h->n_dirty = h64[4];
     h->serial = h64[5];
     h->base_serial = h64[6];
     h->digest = h64[7];
+    h->head_bytes = head;
     p += kHeaderBytes;
     h->allocs.resize(n);
     if (n)
@@ -1659,10 +1678,10 @@ int ckpt::parse_head(const void *buf, size_t bytes, ImageHead *h)
         o += ru16(r.size);
         g += (r.size + h->C - 1) / h->C;
     }
-    if (o != h->data_bytes || g != N)
+    if (o != h->data_bytes || g != h->N)
         return set_error(CKPT_E_INVAL, "allocation table does not match the header totals");
     h->addrs.assign(n, 0);
-    if (version >= 2) {
+    if (h->version >= 2) {
         if (n)
             memcpy(h->addrs.data(), p, n * 8);
         p += n * 8;
@@ -1671,28 +1690,24 @@ int ckpt::parse_head(const void *buf, size_t bytes, ImageHead *h)
     return CKPT_OK;
 }
 
-extern "C" int ckpt_image_load(ckpt_ctx *ctx, const void *buf, size_t bytes, ckpt_image **out)
+int ckpt::image_from_head(ckpt_ctx *ctx, ImageHead *h, ckpt_image **out)
 {
-    if (!buf || !out)
-        return set_error(CKPT_E_INVAL, "NULL argument");
-    ImageHead h;
-    CKPT_TRY(parse_head(buf, bytes, &h));
     auto *img = new ckpt_image();
     std::unique_ptr<ckpt_image> guard(img);
     img->device = ctx ? ctx->cfg.device : 0;
-    img->mode = h.mode;
-    img->C = h.C;
-    img->N = h.N;
-    img->data_bytes = h.data_bytes;
-    img->ser_bytes = h.ser_bytes;
-    img->n_dirty = h.n_dirty;
-    img->serial = h.serial;
-    img->base_serial = h.base_serial;
+    img->mode = h->mode;
+    img->C = h->C;
+    img->N = h->N;
+    img->data_bytes = h->data_bytes;
+    img->ser_bytes = h->ser_bytes;
+    img->n_dirty = h->n_dirty;
+    img->serial = h->serial;
+    img->base_serial = h->base_serial;
     img->drained = true;
-    img->allocs = std::move(h.allocs);
-    img->addrs = std::move(h.addrs);
-    const uint8_t *p = h.rest;
-    const uint64_t N = h.N, nd = h.n_dirty, ser = h.ser_bytes;
+    img->allocs = std::move(h->allocs);
+    img->addrs = std::move(h->addrs);
+    const uint8_t *p = h->rest;
+    const uint64_t N = h->N, nd = h->n_dirty, ser = h->ser_bytes;
     CKPT_TRY(alloc_meta(img, N));
     if (N) {
         memcpy(img->crc, p, N * 4);
@@ -1702,13 +1717,24 @@ extern "C" int ckpt_image_load(ckpt_ctx *ctx, const void *buf, size_t bytes, ckp
     CKPT_TRY(img->ids_buf.ensure(std::max<uint64_t>(nd, 1) * 8));
     if (nd)
         memcpy(img->ids_buf.p, p, nd * 8);
-    p += nd * 8;
-    CKPT_TRY(img->data.ensure(std::max<uint64_t>(ser, 1)));
-    if (ser)
-        memcpy(img->data.p, p, ser);
-    if (crc_digest(img->crc, N * 4) != h.digest)
+    if (crc_digest(img->crc, N * 4) != h->digest)
         return set_error(CKPT_E_INVAL, "CRC section digest mismatch");
+    CKPT_TRY(img->data.ensure(std::max<uint64_t>(ser, 1)));
     *out = guard.release();
+    return CKPT_OK;
+}
+
+extern "C" int ckpt_image_load(ckpt_ctx *ctx, const void *buf, size_t bytes, ckpt_image **out)
+{
+    if (!buf || !out)
+        return set_error(CKPT_E_INVAL, "NULL argument");
+    ImageHead h;
+    CKPT_TRY(parse_head(buf, bytes, &h));
+    ckpt_image *img = nullptr;
+    CKPT_TRY(image_from_head(ctx, &h, &img));
+    if (h.ser_bytes)
+        memcpy(img->data.p, (const uint8_t *)buf + h.head_bytes, h.ser_bytes);
+    *out = img;
     return CKPT_OK;
 }
 

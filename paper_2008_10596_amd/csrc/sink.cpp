@@ -12,6 +12,8 @@
 #include <condition_variable>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
+#include <string>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -177,30 +179,89 @@ extern "C" int ckpt_image_write_file(const ckpt_image *img, const char *path, ui
     return CKPT_OK;
 }
 
-int ckpt::read_whole_file(const char *path, std::vector<uint8_t> *buf)
+ImageFile::~ImageFile()
 {
-    const int fd = open(path, O_RDONLY);
-    if (fd < 0)
-        return set_error(CKPT_E_NOTFOUND, "cannot open %s: %s", path, strerror(errno));
-    struct stat st;
-    if (fstat(fd, &st) != 0) {
+    if (fd >= 0)
         close(fd);
-        return set_error(CKPT_E_IO, "cannot stat %s", path);
-    }
-    const size_t n = (size_t)st.st_size;
-    buf->resize(n);
-    size_t got = 0;
-    while (got < n) {
-        const ssize_t r = pread(fd, buf->data() + got, std::min(n - got, kBlock), (off_t)got);
+}
+
+namespace {
+
+// n bytes at file offset off into p; CKPT_E_IO on an error or a short file
+int read_all(int fd, uint8_t *p, size_t n, uint64_t off, const char *path)
+{
+    while (n) {
+        const ssize_t r = pread(fd, p, std::min(n, kBlock), (off_t)off);
         if (r < 0 && errno == EINTR)
             continue;
-        if (r <= 0) {
-            close(fd);
-            return set_error(CKPT_E_IO, "read of %s failed at %zu", path, got);
-        }
-        got += (size_t)r;
+        if (r < 0)
+            return set_error(CKPT_E_IO, "read of %s failed: %s", path, strerror(errno));
+        if (r == 0)
+            return set_error(CKPT_E_INVAL, "truncated image file %s", path);
+        p += r;
+        n -= (size_t)r;
+        off += (uint64_t)r;
     }
-    close(fd);
+    return CKPT_OK;
+}
+
+}  // namespace
+
+int ckpt::open_image_file(const char *path, ImageFile *f)
+{
+    f->path = path;
+    f->fd = open(path, O_RDONLY);
+    if (f->fd < 0)
+        return set_error(CKPT_E_NOTFOUND, "cannot open %s: %s", path, strerror(errno));
+    struct stat st;
+    if (fstat(f->fd, &st) != 0)
+        return set_error(CKPT_E_IO, "cannot stat %s", path);
+    const uint64_t size = (uint64_t)st.st_size;
+    // the fixed header gives the size of the head; a short file fails here
+    uint8_t hdr[128];
+    const size_t nh = (size_t)std::min<uint64_t>(size, sizeof hdr);
+    CKPT_TRY(read_all(f->fd, hdr, nh, 0, path));
+    uint64_t head = 0, ser = 0;
+    CKPT_TRY(head_layout(hdr, nh, size, &head, &ser));
+    f->head.resize(head);
+    CKPT_TRY(read_all(f->fd, f->head.data(), head, 0, path));
+    return parse_head(f->head.data(), head, &f->h, ser);
+}
+
+int ckpt::load_image_file(ckpt_ctx *ctx, ImageFile *f, ckpt_image **out)
+{
+    const uint64_t off = f->h.head_bytes, ser = f->h.ser_bytes;
+    ckpt_image *img = nullptr;
+    CKPT_TRY(image_from_head(ctx, &f->h, &img));
+    std::unique_ptr<ckpt_image> guard(img);
+    // DATA in kBlock pieces, dealt round-robin to up to 8 readers, each
+    // reading straight into the pinned buffer (no staging copy)
+    const uint64_t nblocks = (ser + kBlock - 1) / kBlock;
+    const unsigned nt = (unsigned)std::min<uint64_t>({nblocks, 8, std::max(1u, std::thread::hardware_concurrency())});
+    std::vector<int> rcs(nt, CKPT_OK);
+    std::vector<std::string> errs(nt);
+    auto reader = [&](unsigned t) {
+        for (uint64_t b = t; b < nblocks; b += nt) {
+            const uint64_t lo = b * kBlock, n = std::min<uint64_t>(kBlock, ser - lo);
+            const int rc = read_all(f->fd, (uint8_t *)img->data.p + lo, n, off + lo, f->path.c_str());
+            if (rc != CKPT_OK) {
+                rcs[t] = rc;
+                errs[t] = ckpt_last_error();
+                return;
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < nt; t++)
+        th.emplace_back(reader, t);
+    if (nt)
+        reader(0);
+    for (auto &x : th)
+        x.join();
+    for (unsigned t = 0; t < nt; t++)
+        if (rcs[t] != CKPT_OK)
+            return set_error(rcs[t], "%s", errs[t].c_str());
+    *out = guard.release();
     return CKPT_OK;
 }
 
@@ -208,7 +269,7 @@ extern "C" int ckpt_image_read_file(ckpt_ctx *ctx, const char *path, ckpt_image 
 {
     if (!path || !out)
         return set_error(CKPT_E_INVAL, "NULL argument");
-    std::vector<uint8_t> buf;
-    CKPT_TRY(read_whole_file(path, &buf));
-    return ckpt_image_load(ctx, buf.data(), buf.size(), out);
+    ImageFile f;
+    CKPT_TRY(open_image_file(path, &f));
+    return load_image_file(ctx, &f, out);
 }

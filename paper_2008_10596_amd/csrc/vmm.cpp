@@ -313,6 +313,29 @@ extern "C" int ckpt_vmm_alloc(ckpt_ctx *ctx, size_t bytes, void *addr, void **ou
     return CKPT_OK;
 }
 
+int ckpt::vmm_block_map(ckpt_ctx *ctx, uint64_t bytes, uint64_t *base)
+{
+    DeviceGuard dg(ctx->cfg.device);
+    uint64_t g = 0;
+    CKPT_TRY(granularity(ctx->cfg.device, &g));
+    if (bytes == 0 || bytes % g != 0)
+        return set_error(CKPT_E_INVAL, "block of %llu bytes is not a granularity multiple",
+                         (unsigned long long)bytes);
+    CKPT_TRY(map_range(ctx, 0, bytes, base));
+    ctx->vmm[*base].refs = 1;   // the block's owner holds it, registered or not
+    return CKPT_OK;
+}
+
+void ckpt::vmm_block_unmap(ckpt_ctx *ctx, uint64_t base)
+{
+    ctx->vmm_of.erase(base);
+    auto it = ctx->vmm.find(base);
+    if (it == ctx->vmm.end())
+        return;
+    DeviceGuard dg(ctx->cfg.device);
+    unmap_range(ctx, it);
+}
+
 extern "C" int ckpt_vmm_free(ckpt_ctx *ctx, void *ptr)
 {
     if (!ctx)
@@ -360,6 +383,9 @@ int recreate(ckpt_ctx *ctx, const std::vector<ckpt_alloc_rec> &allocs, const std
         return set_error(CKPT_E_INVAL, "image has no address section");
     uint64_t g = 0;
     CKPT_TRY(granularity(ctx->cfg.device, &g));
+    // blocks the hook keeps for reuse hold address ranges without being
+    // registered: give them back so that the recorded addresses are free
+    hook_trim_for(ctx);
 
     // 1. classify: refill a matching live registration, or re-create
     std::vector<char> create(n, 0);
@@ -504,11 +530,10 @@ extern "C" int ckpt_restore_file_at(ckpt_ctx *ctx, void *stream, const char *pat
 {
     if (!ctx || !path)
         return set_error(CKPT_E_INVAL, "ctx or path is NULL");
-    // the file into ordinary host memory, and its tables, before any device work
-    std::vector<uint8_t> buf;
-    CKPT_TRY(read_whole_file(path, &buf));
-    ImageHead h;
-    CKPT_TRY(parse_head(buf.data(), buf.size(), &h));
+    // the file's tables into ordinary host memory before any device work
+    ImageFile f;
+    CKPT_TRY(open_image_file(path, &f));
+    const ImageHead &h = f.h;
     if (h.mode != CKPT_FULL)
         return set_error(CKPT_E_INVAL, "restore needs a full image");
     HookGuard hg(ctx);
@@ -517,7 +542,7 @@ extern "C" int ckpt_restore_file_at(ckpt_ctx *ctx, void *stream, const char *pat
     Made made;
     CKPT_TRY(recreate(ctx, h.allocs, h.addrs, &made));
     ckpt_image *img = nullptr;
-    int rc = ckpt_image_load(ctx, buf.data(), buf.size(), &img);
+    int rc = load_image_file(ctx, &f, &img);
     if (rc == CKPT_OK) {
         // every allocation is now a live registration at its address: refilled in place
         rc = ckpt_restore_at(ctx, stream, img, nullptr, addrs_out, rep);

@@ -12,7 +12,10 @@ brings every allocation back at its address.
 torch accepts a new allocator only before the process's first device
 allocation, so install() must run first.  The pluggable allocator does not
 cache: every tensor allocation reaches the hook, which is what makes the log
-exact, at the cost of a hipMalloc per allocation.
+exact.  Without `cache` each one costs a hipMalloc (or a mapping) and each
+free a wait for the device; with `cache=True` freed blocks are kept for
+reuse on their stream, as torch's own caching allocator does, and the log
+stays exact (a cached block is unregistered until it is handed out again).
 """
 import ctypes
 
@@ -21,9 +24,9 @@ import torch
 from . import ckpt as K
 
 
-def install(ctx, address_stable=False):
+def install(ctx, address_stable=False, cache=False):
     """Log torch's device allocations into ctx; returns the allocator object."""
-    flags = K.CKPT_HOOK_ADDRESS_STABLE if address_stable else 0
+    flags = (K.CKPT_HOOK_ADDRESS_STABLE if address_stable else 0) | (K.CKPT_HOOK_CACHE if cache else 0)
     K._check(K.lib().ckpt_hook_install(ctx.handle, flags), "ckpt_hook_install")
     alloc = torch.cuda.memory.CUDAPluggableAllocator(K.LIB_PATH, "ckpt_hook_malloc", "ckpt_hook_free")
     torch.cuda.memory.change_current_allocator(alloc)
@@ -35,3 +38,17 @@ def stats():
     v = [ctypes.c_uint64() for _ in range(3)]
     K._check(K.lib().ckpt_hook_stats(*[ctypes.byref(x) for x in v]), "ckpt_hook_stats")
     return {"allocs": v[0].value, "frees": v[1].value, "failures": v[2].value}
+
+
+def cache_stats():
+    """{"blocks", "bytes", "hits"} of the block cache."""
+    v = [ctypes.c_uint64() for _ in range(3)]
+    K._check(K.lib().ckpt_hook_cache_stats(*[ctypes.byref(x) for x in v]), "ckpt_hook_cache_stats")
+    return {"blocks": v[0].value, "bytes": v[1].value, "hits": v[2].value}
+
+
+def trim():
+    """Release every cached block; returns their bytes."""
+    n = ctypes.c_uint64()
+    K._check(K.lib().ckpt_hook_trim(ctypes.byref(n)), "ckpt_hook_trim")
+    return n.value

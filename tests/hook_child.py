@@ -9,7 +9,13 @@ mode runs in a fresh process and prints one JSON line:
   save PATH     the same with address-stable memory, then write the image to
                 PATH and print each tensor's address and SHA-256;
   restore PATH  without the hook, restore the image at its addresses and print
-                the SHA-256 of the bytes found there.
+                the SHA-256 of the bytes found there;
+  cache MODE    the log check with the block cache on (MODE "plain" or
+                "stable"), then: a freed block is handed out again to the next
+                allocation of its class, registered with its own size; with
+                "stable", an image taken before a free is restored at its
+                addresses while the freed block sits in the cache;
+  save_cache PATH  "save" with the cache on.
 """
 import hashlib
 import json
@@ -74,10 +80,56 @@ def run_log():
     print(json.dumps(out), flush=True)
 
 
-def run_save(path):
+def run_cache(mode):
+    from paper_2008_10596_amd import hook
+    from tests.gpu_common import d2h
+    stable = mode == "stable"
+    ctx = K.Context(chunk_bytes=C)
+    hook.install(ctx, address_stable=stable, cache=True)
+    live = tensors()
+    img = ctx.checkpoint()
+    out = check(ctx, live, img)
+    sha0 = [hashlib.sha256(host_bytes(t).tobytes()).hexdigest() for t in live]
+    cs = hook.cache_stats()
+    out["cached_after_frees"] = cs["blocks"]
+    # the freed block of e comes back for the next allocation of its size
+    e = live.pop(3)
+    pe, ne = e.data_ptr(), e.numel()
+    del e
+    torch.cuda.synchronize()
+    h0 = hook.cache_stats()["hits"]
+    x = torch.full((ne - 5,), 9, dtype=torch.uint8, device="cuda")
+    out["reused"] = x.data_ptr() == pe
+    out["hit"] = hook.cache_stats()["hits"] == h0 + 1
+    torch.cuda.synchronize()
+    out["after_reuse"] = check(ctx, live + [x], ctx.checkpoint())
+    if stable:
+        # x's block goes back to the cache; the image still has e at that address
+        del x
+        torch.cuda.synchronize()
+        rc, rep, addrs = ctx.restore_at(img)
+        sizes = [int(v) for v in img.allocs["size"]]
+        out["restore_rc"] = rc
+        out["restore_bad"] = rep["n_bad"]
+        out["restore_addrs"] = addrs == [int(a) for a in img.addrs]
+        out["restore_sha"] = [hashlib.sha256(d2h(p, n).tobytes()).hexdigest() for p, n in zip(addrs, sizes)] == sha0
+        out["cached_after_restore"] = hook.cache_stats()["blocks"]
+    else:
+        del x
+        torch.cuda.synchronize()
+    out["cached_before_trim"] = hook.cache_stats()["blocks"]
+    out["trimmed"] = hook.trim()
+    out["cached_after_trim"] = hook.cache_stats()["blocks"]
+    del live
+    torch.cuda.synchronize()
+    out["live_at_end"] = ctx.live_count()
+    print(json.dumps(out), flush=True)
+
+
+def run_save(path, cache=False):
     from paper_2008_10596_amd import hook
     ctx = K.Context(chunk_bytes=C)
-    hook.install(ctx, address_stable=True)
+    hook.install(ctx, address_stable=True, cache=cache)
     live = tensors()
     img = ctx.checkpoint()
     out = check(ctx, live, img)
@@ -102,5 +154,9 @@ if __name__ == "__main__":
         run_log()
     elif mode == "save":
         run_save(sys.argv[2])
+    elif mode == "save_cache":
+        run_save(sys.argv[2], cache=True)
+    elif mode == "cache":
+        run_cache(sys.argv[2])
     else:
         run_restore(sys.argv[2])

@@ -132,6 +132,13 @@ def test_host_only_failures_before_any_device_work(ck, tmp_path):
     assert lib.ckpt_hook_stats(ctypes.byref(a), ctypes.byref(f), ctypes.byref(x)) == ck.CKPT_OK
     assert (a.value, f.value, x.value) == (0, 0, 0)
     assert lib.ckpt_hook_malloc(0, 0, None) is None                 # 0 bytes: NULL, nothing logged
+    assert lib.ckpt_hook_install(None, ck.CKPT_HOOK_CACHE | ck.CKPT_HOOK_ADDRESS_STABLE) == ck.CKPT_OK
+    assert lib.ckpt_hook_cache_stats(ctypes.byref(a), ctypes.byref(f), ctypes.byref(x)) == ck.CKPT_OK
+    assert (a.value, f.value, x.value) == (0, 0, 0)
+    assert lib.ckpt_hook_cache_stats(None, ctypes.byref(f), ctypes.byref(x)) == ck.CKPT_E_INVAL
+    assert lib.ckpt_hook_trim(ctypes.byref(a)) == ck.CKPT_OK and a.value == 0
+    assert lib.ckpt_hook_trim(None) == ck.CKPT_OK
+    assert lib.ckpt_hook_install(None, 0) == ck.CKPT_OK
     assert lib.ckpt_image_merge(None, None, ctypes.byref(out)) == ck.CKPT_E_INVAL
     assert lib.ckpt_restore_file_at(None, None, b"x", None, None, None) == ck.CKPT_E_INVAL
     assert lib.ckpt_image_write_file(None, b"x", 0, None) == ck.CKPT_E_INVAL

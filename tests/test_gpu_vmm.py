@@ -364,3 +364,35 @@ def test_hook_address_stable_restart(tmp_path):
     assert b["rc"] == K.CKPT_OK and b["n_bad"] == 0
     assert b["addrs"] == a["addrs"]
     assert b["sha"] == a["sha"]
+
+
+@pytest.mark.parametrize("mode", ["plain", "stable"])
+def test_hook_cache_keeps_the_log_exact(mode):
+    """With the block cache, the live set is still exactly the live tensors
+    (registered with their own sizes, whatever the block's class), a freed
+    block is handed out again, and trim() empties the cache."""
+    out = _child("tests.hook_child", "cache", mode)
+    _check_logged(out)
+    assert out["cached_after_frees"] >= 1
+    assert out["reused"] and out["hit"]
+    _check_logged(out["after_reuse"])
+    if mode == "stable":
+        # the restore at the recorded addresses gives the cached block back first
+        assert out["restore_rc"] == K.CKPT_OK and out["restore_bad"] == 0
+        assert out["restore_addrs"] and out["restore_sha"]
+        assert out["cached_after_restore"] == 0
+    else:
+        assert out["cached_before_trim"] >= 1 and out["trimmed"] > 0
+    assert out["cached_after_trim"] == 0
+    # stable: the allocation re-created by the restore belongs to the context
+    assert out["live_at_end"] == (1 if mode == "stable" else 0)
+
+
+def test_hook_cache_address_stable_restart(tmp_path):
+    path = str(tmp_path / "torch_cache.ckpt")
+    a = _child("tests.hook_child", "save_cache", path)
+    _check_logged(a)
+    b = _child("tests.hook_child", "restore", path)
+    assert b["rc"] == K.CKPT_OK and b["n_bad"] == 0
+    assert b["addrs"] == a["addrs"]
+    assert b["sha"] == a["sha"]
