@@ -47,11 +47,11 @@ void build_tables(uint32_t *out, uint32_t G, uint32_t rounds_per_wave)
     build_operator(out + kTabSeg, (uint64_t)rounds_per_wave * round);
 }
 
-void build_tables_replicated(uint32_t *out, uint32_t rounds_per_wave)
+void build_tables_replicated(uint32_t *out, uint32_t rounds_per_wave, uint32_t gap_bytes)
 {
     std::vector<uint32_t> op(kTabWords);
-    // one round (1024 bytes), 8 copies per entry
-    build_operator(op.data(), kRoundBytes);
+    // the gap operator (one round, or the quad form's skip), 8 copies per entry
+    build_operator(op.data(), gap_bytes);
     for (int j = 0; j < 4; j++)
         for (int b = 0; b < 256; b++)
             for (int r = 0; r < 8; r++)

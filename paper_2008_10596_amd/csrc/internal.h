@@ -44,6 +44,15 @@ constexpr int kRepTreeOff = 98304;                         // bytes
 constexpr int kRepWords = (kRepTreeOff / 4) + (kTreeLevels + 1) * kTabWords;   // 124 KiB
 constexpr int kTableCompact = 1;
 constexpr int kTableReplicated = 2;
+
+// The quad form of the hash-only pass (chunks of at most four rounds): each
+// row of kQuadLanes lanes hashes its own chunk, and lane l of a row reads the
+// pieces at l * 16 of every kQuadLanes * 16-byte stretch.  Its table set is
+// the replicated one with the gap operator replaced by a skip: the last word
+// of a piece moves the register 4 bytes and over the other lanes' pieces of
+// that stretch, kQuadSkipBytes in all.
+constexpr int kQuadLanes = 16;
+constexpr uint32_t kQuadSkipBytes = 4 + (kQuadLanes - 1) * 16;
 constexpr int kFlagZero = 1;
 constexpr int kFlagDirty = 2;
 
@@ -66,7 +75,8 @@ constexpr uint64_t kNoBase = ~0ull;
 
 struct ChunkArgs {
     const DevPlan *plan;
-    const uint32_t *tables;   // kTabTotalWords words
+    const uint32_t *tables;   // table_words words
+    const uint32_t *tables_quad;   // nullable: the quad form's replicated set
     uint32_t C;
     uint32_t waves_per_chunk;
     uint32_t lane_pieces;     // G
@@ -190,8 +200,10 @@ hipError_t launch_pick_u64(hipStream_t s, const uint64_t *src, const uint64_t *i
 // a launch with G pieces per lane per round and `rounds_per_wave` consecutive
 // rounds per wave.
 void build_tables(uint32_t *out, uint32_t G, uint32_t rounds_per_wave);
-// The replicated set (kRepWords words; G = 1 only).
-void build_tables_replicated(uint32_t *out, uint32_t rounds_per_wave);
+// The replicated set (kRepWords words; G = 1 only); its gap operator moves
+// the register gap_bytes forward (kRoundBytes, or kQuadSkipBytes for the
+// quad form).
+void build_tables_replicated(uint32_t *out, uint32_t rounds_per_wave, uint32_t gap_bytes = kRoundBytes);
 // Register after feeding nbytes zero bytes (host, for tests of the tables).
 uint32_t host_shift(uint32_t reg, uint64_t nbytes);
 

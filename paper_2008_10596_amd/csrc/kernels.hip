@@ -654,16 +654,122 @@ __device__ __forceinline__ Desc make_desc(const ChunkArgs &a, uint64_t i, uint32
     return d;
 }
 
-// SMALL: every chunk is one batch of rounds and one wave hashes it (the host
-// picks this instantiation only then); the wave keeps the next chunk's loads in
-// flight while it finishes the current one.
-template <int MODE, int G, bool NT, bool REP, bool SMALL = false>
+// --------------------------------------------- quad form (hash only, C <= 4 KiB)
+//
+// Each row of 16 lanes hashes a chunk of its own, four chunks per wave.  A
+// chunk of len bytes sits at the end of a window of r_win rounds of 1 KiB as
+// in the one-wave form.  The window is cut into stretches of 256 bytes, one
+// 16-byte piece per lane: lane l of the row reads piece l of every stretch,
+// so each load instruction covers 256 contiguous bytes per row.  The lane
+// chains its pieces in order into one register; the last word of a piece
+// (but the last piece's) uses the skip operator, which also moves the
+// register over the other 15 lanes' pieces of the stretch, so no separate
+// round operator is needed.  The row's 16 registers are then combined inside
+// the row with the tree operators for 16, 32, 64 and 128 bytes.  The
+// cross-lane tree, the flag test and the finish are shared by four chunks,
+// which is what this form saves over one wave per chunk.
+constexpr int kQuadRows = 64 / kQuadLanes;        // chunks per wave
+constexpr int kQuadPieces = 4;                    // 16-byte pieces per lane per round
+constexpr int kQuadRoundPieces = kQuadLanes * kQuadPieces;
+constexpr int kQuadMaxRounds = 4;
+static_assert(kQuadRoundPieces * 16 == kRoundBytes, "a row round is one wave round long");
+static_assert(kQuadRows == 4, "the row flags are 16-bit fields of the wave ballot");
+
+// descriptor tile of the quad form: four chunks per wave and four quads per
+// wave of a 1024-thread workgroup between two barriers
+constexpr int kQuadTile = 256;
+
+// Loads of round b of a row's window (b < r_win): piece j of the lane is
+// window piece (4 b + j) * 16 + lr.
+template <bool NT>
+__device__ __forceinline__ void quad_loads(const Desc &d, bool valid, bool exact, int lr, uint32_t r_win, uint32_t b,
+                                           uint4 (&v)[kQuadPieces])
+{
+    const uint32_t first = b * kQuadRoundPieces + lr;   // window piece of v[0]
+    if (exact) {   // every row's chunk fills its window: whole pieces, no offset
+#pragma unroll
+        for (int j = 0; j < kQuadPieces; j++)
+            v[j] = ld16<NT>((const uint8_t *)d.src + (first + j * kQuadLanes) * 16);
+        return;
+    }
+    const int z = valid ? (int)(r_win * kQuadRoundPieces) - (int)((d.len + 15) >> 4) : 0;
+#pragma unroll
+    for (int j = 0; j < kQuadPieces; j++) {
+        const int p = (int)(first + j * kQuadLanes) - z;
+        v[j] = make_uint4(0u, 0u, 0u, 0u);
+        if (valid && p >= 0)
+            v[j] = load_piece<kModeHash, NT>(d, (uint32_t)p * 16);
+    }
+}
+
+// Chains round b's pieces into the lane's register (T is the quad table set:
+// its gap operator is the skip) and ORs their data words into *o.
+__device__ __forceinline__ void quad_hash(const Tabs<true> &T, const Desc &d, bool valid, bool exact, int lr,
+                                          uint32_t r_win, uint32_t b, uint4 (&v)[kQuadPieces], uint32_t *acc,
+                                          uint32_t *o)
+{
+    const uint32_t first = b * kQuadRoundPieces + lr;
+    const int z = (valid && !exact) ? (int)(r_win * kQuadRoundPieces) - (int)((d.len + 15) >> 4) : 0;
+    const bool last_round = b + 1 == r_win;   // uniform over the wave
+    uint32_t r = *acc;
+#pragma unroll
+    for (int j = 0; j < kQuadPieces; j++) {
+        *o |= v[j].x | v[j].y | v[j].z | v[j].w;
+        // the first data byte's piece carries the complemented init (zero
+        // pieces before it leave the register at zero)
+        if (exact) {
+            if (first + j * kQuadLanes == 0)
+                v[j].x = ~v[j].x;
+        } else if (valid && (int)(first + j * kQuadLanes) == z) {
+            v[j].x ^= init_mask(d.len);
+        }
+        r = T.chain(r, v[j].x);
+        r = T.chain(r, v[j].y);
+        r = T.chain(r, v[j].z);
+        if (j == kQuadPieces - 1 && last_round)
+            r = T.chain(r, v[j].w);   // the window ends with this stretch
+        else
+            r = T.gap(r ^ v[j].w);    // 4 bytes, then the other lanes' pieces
+    }
+    *acc = r;
+}
+
+// The row's 16 registers combined into the row's lane 0 (DPP row shifts):
+// at level k, lane i moves its register past the 16 << k bytes of lane
+// i + 2^k's pieces and adds that lane's register.
+__device__ __forceinline__ uint32_t quad_combine(const Tabs<true> &T, uint32_t acc, int lane)
+{
+    uint32_t right = dpp_down<1>(acc);
+    if ((lane & 1) == 0)
+        acc = T.tree(0, acc) ^ right;
+    right = dpp_down<2>(acc);
+    if ((lane & 3) == 0)
+        acc = T.tree(1, acc) ^ right;
+    right = dpp_down<4>(acc);
+    if ((lane & 7) == 0)
+        acc = T.tree(2, acc) ^ right;
+    right = dpp_down<8>(acc);
+    if ((lane & 15) == 0)
+        acc = T.tree(3, acc) ^ right;
+    return acc;
+}
+
+// FORM: kFormWave (one or more waves per chunk), kFormSmall (every chunk is
+// one batch of rounds and one wave hashes it; the wave keeps the next chunk's
+// loads in flight while it finishes the current one) or kFormQuad (above).
+// The host picks kFormSmall and kFormQuad only where they apply.
+constexpr int kFormWave = 0;
+constexpr int kFormSmall = 1;
+constexpr int kFormQuad = 2;
+
+template <int MODE, int G, bool NT, bool REP, int FORM = kFormWave>
 __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
 {
     __shared__ uint32_t tabs[REP ? kRepWords : kTabTotalWords];
     // two descriptor tiles: the first wave loads the next tile's descriptors
     // while the workgroup works on the current one
-    __shared__ Desc desc[2][kTile];
+    constexpr int kDescTile = FORM == kFormQuad ? kQuadTile : kTile;
+    __shared__ Desc desc[2][kDescTile];
     __shared__ uint32_t s_part[16];
     __shared__ uint32_t s_nz[16];
 
@@ -686,10 +792,11 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
     // The items go in rounds of at most gridDim.x * kTile, each split evenly
     // over the workgroups, so the whole grid sweeps one window of memory at a
     // time and no workgroup gets more than one item above another.
+    const int tile = kDescTile < (int)blockDim.x ? kDescTile : (int)blockDim.x;
     Rounds rs;
-    rs.init(M, kTile);
+    rs.init(M, (uint32_t)tile);
     const uint64_t R = rs.R;
-    const bool stager = threadIdx.x < kTile;
+    const bool stager = (int)threadIdx.x < tile;
     uint64_t g0 = 0, hi = 0;
     if (R)
         rs.next(&g0, &hi);
@@ -704,8 +811,51 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
         Desc nd;
         if (stager && n0 + threadIdx.x < n1)
             nd = make_desc<MODE>(a, n0 + threadIdx.x, C);   // loads in flight during the tile
-        const int cnt = (int)(hi - g0);   // uniform over the workgroup, at most kTile
-        if constexpr (SMALL) {
+        const int cnt = (int)(hi - g0);   // uniform over the workgroup, at most tile
+        if constexpr (FORM == kFormQuad) {
+            static_assert(MODE == kModeHash && REP && G == 1, "the quad form hashes with the replicated tables");
+            // This wave's quads of the tile, round by round: the next round's
+            // loads (of this quad, or the first of the next) are in flight
+            // while the current round is hashed.
+            const int q = lane / kQuadLanes, lr = lane & (kQuadLanes - 1);
+            const int stride = kQuadRows * nwaves, first = kQuadRows * wave;
+            const int nq = first < cnt ? (cnt - first + stride - 1) / stride : 0;   // uniform over the wave
+            Desc dn;
+            bool vn = false, en = false;
+            uint4 cur[kQuadPieces], nxt[kQuadPieces];
+            if (nq > 0) {
+                vn = first + q < cnt;
+                if (vn)
+                    dn = desc[buf][first + q];
+                en = __ballot(!vn || dn.len != r_win * kRoundBytes) == 0;
+                quad_loads<NT>(dn, vn, en, lr, r_win, 0, nxt);
+            }
+            for (int k = 0; k < nq; k++) {
+                const Desc dc = dn;
+                const bool vc = vn, ec = en;
+                uint32_t acc = 0, orv = 0;
+                for (uint32_t b = 0; b < r_win; b++) {
+#pragma unroll
+                    for (int j = 0; j < kQuadPieces; j++)
+                        cur[j] = nxt[j];
+                    if (b + 1 < r_win) {
+                        quad_loads<NT>(dc, vc, ec, lr, r_win, b + 1, nxt);
+                    } else if (k + 1 < nq) {
+                        const int t = first + (k + 1) * stride + q;
+                        vn = t < cnt;
+                        if (vn)
+                            dn = desc[buf][t];
+                        en = __ballot(!vn || dn.len != r_win * kRoundBytes) == 0;
+                        quad_loads<NT>(dn, vn, en, lr, r_win, 0, nxt);
+                    }
+                    quad_hash(T, dc, vc, ec, lr, r_win, b, cur, &acc, &orv);
+                }
+                const uint32_t raw = quad_combine(T, acc, lane);
+                const uint64_t nz = __ballot(orv != 0);
+                if (vc && lr == 0)
+                    finish_chunk<MODE>(a, dc, raw, ((nz >> (q * kQuadLanes)) & 0xFFFFull) != 0);
+            }
+        } else if constexpr (FORM == kFormSmall) {
             // one batch per chunk: the next chunk's loads go out before this
             // chunk is hashed, combined and finished
             uint4 cur[kLoadsInFlight / G][G], nxt[kLoadsInFlight / G][G];
@@ -1118,13 +1268,25 @@ template <int MODE>
 static void launch_chunks_m(hipStream_t s, const ChunkArgs &a, int grid, int block)
 {
     if (a.table_mode == kTableReplicated) {     // G = 1 only
+        const uint32_t rounds = (a.C + kRoundBytes - 1) / kRoundBytes;
+        // hash-only chunks of at most 4 KiB: four chunks per wave
+        if (MODE == kModeHash && a.tables_quad && a.waves_per_chunk == 1 && rounds <= kQuadMaxRounds) {
+            ChunkArgs q = a;
+            q.tables = a.tables_quad;
+            if (a.nontemporal)
+                hipLaunchKernelGGL((k_chunks<kModeHash, 1, true, true, kFormQuad>), dim3(grid), dim3(block), 0, s, q);
+            else
+                hipLaunchKernelGGL((k_chunks<kModeHash, 1, false, true, kFormQuad>), dim3(grid), dim3(block), 0, s,
+                                   q);
+            return;
+        }
         // one wave per chunk and one batch of rounds per chunk: the pipelined form
-        const bool small = a.waves_per_chunk == 1 && (a.C + kRoundBytes - 1) / kRoundBytes <= kLoadsInFlight;
+        const bool small = a.waves_per_chunk == 1 && rounds <= kLoadsInFlight;
         if (small) {
             if (a.nontemporal)
-                hipLaunchKernelGGL((k_chunks<MODE, 1, true, true, true>), dim3(grid), dim3(block), 0, s, a);
+                hipLaunchKernelGGL((k_chunks<MODE, 1, true, true, kFormSmall>), dim3(grid), dim3(block), 0, s, a);
             else
-                hipLaunchKernelGGL((k_chunks<MODE, 1, false, true, true>), dim3(grid), dim3(block), 0, s, a);
+                hipLaunchKernelGGL((k_chunks<MODE, 1, false, true, kFormSmall>), dim3(grid), dim3(block), 0, s, a);
         } else if (a.nontemporal) {
             hipLaunchKernelGGL((k_chunks<MODE, 1, true, true>), dim3(grid), dim3(block), 0, s, a);
         } else {

@@ -352,11 +352,14 @@ int ckpt::ctx_ready(ckpt_ctx *ctx)
     const uint32_t round_bytes = kRoundBytes * cfg.lane_pieces;
     const uint32_t r_full = (cfg.chunk_bytes + round_bytes - 1) / round_bytes;
     const uint32_t rw = (r_full + cfg.waves_per_chunk - 1) / cfg.waves_per_chunk;
-    std::vector<uint32_t> tabs(cfg.table_mode == kTableReplicated ? kRepWords : kTabTotalWords);
-    if (cfg.table_mode == kTableReplicated)
+    // replicated: the set of the one-wave forms, then the quad form's
+    std::vector<uint32_t> tabs(cfg.table_mode == kTableReplicated ? 2 * kRepWords : kTabTotalWords);
+    if (cfg.table_mode == kTableReplicated) {
         build_tables_replicated(tabs.data(), rw);
-    else
+        build_tables_replicated(tabs.data() + kRepWords, rw, kQuadSkipBytes);
+    } else {
         build_tables(tabs.data(), cfg.lane_pieces, rw);
+    }
     CKPT_TRY(ctx->d_tables.ensure(tabs.size() * 4));
     HIP_TRY(hipMemcpy(ctx->d_tables.p, tabs.data(), tabs.size() * 4, hipMemcpyHostToDevice));
     CKPT_TRY(ctx->d_plan.ensure(sizeof(DevPlan)));
@@ -573,6 +576,8 @@ ChunkArgs ckpt::chunk_args(ckpt_ctx *ctx)
     a.plan = (const DevPlan *)ctx->d_plan.p;
     a.plan_rw = (DevPlan *)ctx->d_plan.p;
     a.tables = (const uint32_t *)ctx->d_tables.p;
+    if (ctx->cfg.table_mode == kTableReplicated)
+        a.tables_quad = a.tables + kRepWords;
     a.C = ctx->cfg.chunk_bytes;
     a.waves_per_chunk = ctx->cfg.waves_per_chunk;
     a.lane_pieces = ctx->cfg.lane_pieces;

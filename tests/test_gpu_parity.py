@@ -226,6 +226,38 @@ def test_incremental_matches_oracle_and_restores(C, G, table):
     assert np.array_equal(delta2.data, dref2["delta"])
 
 
+@pytest.mark.parametrize("block", [64, 256, 1024])
+@pytest.mark.parametrize("C", [16, 48, 256, 1008, 1024, 1040, 2048, 3088, 4096, 4112])
+def test_incremental_edge_sizes(C, block):
+    """Hash-only pass over the edge sizes: every chunk length from 1 byte to a
+    full chunk, rows of four chunks that end inside a tile, all-zero chunks."""
+    log("incremental edge sizes C=%d block=%d" % (C, block))
+    tensors = random_allocs(EDGE_SIZES, seed=C + block, zero=(9, 20))
+    ctx = K.Context(chunk_bytes=C, block_threads=block)
+    register_all(ctx, tensors)
+    base = ctx.checkpoint()
+    base_ref = O.checkpoint([host(t) for t in tensors], C)
+    check_full(base, base_ref, tensors, C)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(C * 7 + block)
+    for k, t in enumerate(tensors):
+        n = t.numel()
+        if n and k % 3 != 2:
+            pos = torch.randint(0, n, (1 + n // 5000,), generator=g, device="cuda")
+            t[pos] ^= 0x11
+    tensors[20][5:9] = 3                      # a chunk of an all-zero allocation gets data
+    hosts = [host(t) for t in tensors]
+    dref = O.delta(hosts, C, base_ref["crc"])
+    delta = ctx.checkpoint(mode=K.CKPT_INCREMENTAL, base=base)
+    assert np.array_equal(delta.crc, dref["crc"])
+    assert np.array_equal(delta.flags, dref["flags"])
+    assert np.array_equal(delta.dirty_ids, dref["dirty_ids"])
+    assert np.array_equal(delta.data, dref["delta"])
+    for im in (base, delta):
+        im.close()
+    ctx.close()
+
+
 def test_incremental_all_dirty_equals_full():
     C = 4096
     tensors = random_allocs([C * 5 + 9, 300, C * 2], seed=77, zero=(1,))
