@@ -226,14 +226,20 @@ def test_incremental_matches_oracle_and_restores(C, G, table):
     assert np.array_equal(delta2.data, dref2["delta"])
 
 
-@pytest.mark.parametrize("block", [64, 256, 1024])
-@pytest.mark.parametrize("C", [16, 48, 256, 1008, 1024, 1040, 2048, 3088, 4096, 4112])
-def test_incremental_edge_sizes(C, block):
+HASH_SHAPES = ([(C, block, 1) for C in (16, 48, 256, 1008, 1024, 1040, 2048, 3088, 4096, 4112)
+                for block in (64, 256, 1024)] +
+               [(4096, 1024, 2), (4096, 256, 4), (16384, 1024, 1), (65536, 1024, 1), (65536, 1024, 4),
+                (65536, 256, 2), (262144, 1024, 2), (262144, 512, 8)])
+
+
+@pytest.mark.parametrize("C,block,wpc", HASH_SHAPES)
+def test_incremental_edge_sizes(C, block, wpc):
     """Hash-only pass over the edge sizes: every chunk length from 1 byte to a
-    full chunk, rows of four chunks that end inside a tile, all-zero chunks."""
-    log("incremental edge sizes C=%d block=%d" % (C, block))
-    tensors = random_allocs(EDGE_SIZES, seed=C + block, zero=(9, 20))
-    ctx = K.Context(chunk_bytes=C, block_threads=block)
+    full chunk, rows of four chunks that end inside a tile, all-zero chunks,
+    one or several waves per chunk."""
+    log("incremental edge sizes C=%d block=%d waves/chunk=%d" % (C, block, wpc))
+    tensors = random_allocs(EDGE_SIZES, seed=C + block + wpc, zero=(9, 20))
+    ctx = K.Context(chunk_bytes=C, block_threads=block, waves_per_chunk=wpc)
     register_all(ctx, tensors)
     base = ctx.checkpoint()
     base_ref = O.checkpoint([host(t) for t in tensors], C)
