@@ -419,6 +419,54 @@ def bench_restore_at(K, torch, tensors, sizes, C, stream, reps=3):
     return out
 
 
+def sink_deflate(K, img, ctx, path):
+    """Write img as the compressed container and read it back; rates are
+    per byte of the serialized image (what a caller saves), file bytes apart."""
+    ser = img.info()["serialized_bytes"]
+    t0 = time.perf_counter()
+    nbytes = img.write_file(path, deflate=True)
+    w_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    back = K.Image.read_file(path, ctx)
+    r_s = time.perf_counter() - t0
+    same = back.info()["crc_digest"] == img.info()["crc_digest"] and bool((back.data[:1 << 20] ==
+                                                                          img.data[:1 << 20]).all())
+    back.close()
+    os.unlink(path)
+    return {"serialized_bytes": ser, "file_bytes": nbytes, "ratio": round(nbytes / max(ser, 1), 4),
+            "write_s": round(w_s, 3), "write_gbps_serialized": round(ser / w_s / 1e9, 2),
+            "read_s": round(r_s, 3), "read_gbps_serialized": round(ser / r_s / 1e9, 2), "read_back_equal": same}
+
+
+def bench_sink_bf16(K, torch, args, sink_dir):
+    """The compressed container on model-weight-like bytes: 16 allocations,
+    2 GiB in all, of bfloat16 values drawn from N(0, 1) (seeded)."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(12701)
+    total = int((2 << 30) * args.scale)
+    per = total // 16 // 2 * 2
+    ts = [torch.randn(per // 2, generator=g, device="cuda").to(torch.bfloat16).view(torch.uint8) for _ in range(16)]
+    torch.cuda.synchronize()
+    ctx = K.Context(chunk_bytes=args.chunk)
+    for t in ts:
+        ctx.register(t)
+    img = ctx.checkpoint()
+    path = os.path.join(sink_dir, "ckpt_bench_bf16_%d.img" % os.getpid())
+    t0 = time.perf_counter()
+    plain = img.write_file(path)
+    plain_s = time.perf_counter() - t0
+    os.unlink(path)
+    out = sink_deflate(K, img, ctx, path)
+    out["plain_write_s"] = round(plain_s, 3)
+    out["plain_write_gbps"] = round(plain / plain_s / 1e9, 2)
+    out["workload"] = "16 allocations, %.2f GiB of bfloat16 N(0,1) values" % (16 * per / 2**30)
+    img.close()
+    ctx.close()
+    del ts
+    torch.cuda.empty_cache()
+    return out
+
+
 def hook_child(mode):
     """One fresh process: time allocate + free pairs of device tensors with
     torch's own caching allocator ("torch") or through libckpt's allocation
@@ -846,6 +894,8 @@ def main():
                               "read_gbps": round(nbytes / r_s / 1e9, 2), "read_back_equal": same,
                               "dir": sink_dir, "mode": "O_DIRECT (buffered where refused), fsync"}
             log("sink: %s" % result["sink"])
+            result["sink"]["deflate"] = {"at_scale_random": sink_deflate(K, img, dctx, path)}
+            log("sink deflate (random): %s" % result["sink"]["deflate"]["at_scale_random"])
         img.close()
         del dsts
         dctx.close()
@@ -875,6 +925,9 @@ def main():
     if "hook" in sections:
         result["hook"] = bench_hook(args)
         log("hook: %s" % result["hook"])
+    if "sink" in result:
+        result["sink"]["deflate"]["bf16"] = bench_sink_bf16(K, torch, args, result["sink"]["dir"])
+        log("sink deflate (bf16): %s" % result["sink"]["deflate"]["bf16"])
     print(json.dumps(result), flush=True)
 
 

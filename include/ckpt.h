@@ -346,10 +346,11 @@ int ckpt_restore_at(ckpt_ctx *ctx, void *stream, const ckpt_image *img, const ck
 
 /*
  * The restart path: restore the full image in file `path` (written by
- * ckpt_image_write_file or ckpt_image_serialize) at its recorded addresses.
- * The paper's restart re-creates every allocation before copying the data
- * back (Sec. 3.2), and so does this call: it reads the file into ordinary host
- * memory, checks its tables, reserves and maps every address range -- before
+ * ckpt_image_write_file, plain or compressed, or ckpt_image_serialize) at its
+ * recorded addresses.  The paper's restart re-creates every allocation before
+ * copying the data back (Sec. 3.2), and so does this call: it reads the
+ * file's header and tables into ordinary host memory, checks them, reserves
+ * and maps every address range -- before
  * it allocates any device or pinned memory of its own, so that a fresh
  * process's runtime has placed nothing there yet -- and only then loads the
  * image and refills the allocations in place, verifying every chunk.  Call
@@ -457,13 +458,29 @@ int ckpt_image_merge(const ckpt_image *base, const ckpt_image *delta, ckpt_image
  * host DATA.
  */
 #define CKPT_FILE_BUFFERED 0x1u   /* write through the page cache */
+/* Write a compressed container instead (always through the page cache):
+ * DATA in 4 MiB blocks, each compressed with zlib's fastest level by a pool
+ * of threads (up to 16) and stored raw when its first 64 KiB or the whole
+ * block do not shrink; header and tables stay uncompressed.  Layout in
+ * sink.cpp.  The paper's checkpointer compresses its images with gzip by
+ * default (Sec. 4.4, where it is turned off for the timings). */
+#define CKPT_FILE_DEFLATE 0x2u
 int ckpt_image_write_file(const ckpt_image *img, const char *path, uint32_t flags, uint64_t *bytes);
 
-/* Read an image file written by ckpt_image_write_file (or any serialized
- * image) and load it as ckpt_image_load does.  CKPT_E_NOTFOUND if the file
- * cannot be opened, CKPT_E_IO if it cannot be read, and ckpt_image_load's
- * errors for its contents. */
+/* Read an image file written by ckpt_image_write_file (plain or compressed)
+ * or any serialized image, and load it as ckpt_image_load does: header and
+ * tables first, then DATA by several threads straight into the image's pinned
+ * buffer (compressed blocks inflated there).  CKPT_E_NOTFOUND if the file
+ * cannot be opened, CKPT_E_IO if it cannot be read, CKPT_E_INVAL for a
+ * truncated or inconsistent file (a block that does not inflate to its size
+ * included), and ckpt_image_load's errors for its contents. */
 int ckpt_image_read_file(ckpt_ctx *ctx, const char *path, ckpt_image **out);
+
+/* The metadata of the image in file `path` (plain or compressed) from its
+ * header and tables alone, host memory only: e.g. n_allocs, to size the
+ * address array of ckpt_restore_file_at.  has_dense is 0 and drained 1.
+ * Errors as ckpt_image_read_file (the CRC section's digest is checked). */
+int ckpt_image_file_info(const char *path, ckpt_image_meta *out);
 
 int ckpt_image_info(const ckpt_image *img, ckpt_image_meta *out);
 

@@ -52,7 +52,7 @@ def build(verbose=False, extra=()):
         _run(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread", "-lz"]
     if verbose:
         print(" ".join(cmd))
     _run(cmd)

@@ -26,6 +26,7 @@ CKPT_E_INVAL, CKPT_E_NOTFOUND, CKPT_E_NOMEM, CKPT_E_HIP = -1, -2, -3, -4
 CKPT_E_MISMATCH, CKPT_E_CORRUPT, CKPT_E_AGAIN, CKPT_E_BUDGET = -5, -6, -7, -8
 CKPT_E_ADDR, CKPT_E_IO = -9, -10
 CKPT_FILE_BUFFERED = 0x1
+CKPT_FILE_DEFLATE = 0x2
 CKPT_STREAM_ORDERED = 0x1
 CKPT_KEEP_DENSE = 0x2
 CKPT_NO_DRAIN = 0x4
@@ -135,6 +136,7 @@ SIGNATURES = [
     ("ckpt_image_merge", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp)]),
     ("ckpt_image_write_file", ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]),
     ("ckpt_image_read_file", ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.POINTER(_vp)]),
+    ("ckpt_image_file_info", ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ckpt_image_meta)]),
     ("ckpt_checkpoint_batch", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
     ("ckpt_vmm_granularity", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     ("ckpt_vmm_alloc", ctypes.c_int, [_vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_uint64)]),
@@ -294,12 +296,13 @@ class Image:
                "ckpt_image_serialize")
         return bytes(buf)
 
-    def write_file(self, path, buffered=False):
-        """Write the serialized image to path (O_DIRECT unless buffered);
-        returns the file size."""
+    def write_file(self, path, buffered=False, deflate=False):
+        """Write the serialized image to path (O_DIRECT unless buffered; with
+        deflate, the compressed container); returns the file size."""
         n = ctypes.c_uint64()
-        _check(lib().ckpt_image_write_file(self.handle, os.fsencode(path), CKPT_FILE_BUFFERED if buffered else 0,
-                                           ctypes.byref(n)), "ckpt_image_write_file")
+        flags = (CKPT_FILE_BUFFERED if buffered else 0) | (CKPT_FILE_DEFLATE if deflate else 0)
+        _check(lib().ckpt_image_write_file(self.handle, os.fsencode(path), flags, ctypes.byref(n)),
+               "ckpt_image_write_file")
         return n.value
 
     @staticmethod
@@ -416,9 +419,7 @@ class Context:
         reserving them before any other device memory of this call.  Returns
         (status, report dict, addresses, Image)."""
         if n_allocs is None:
-            with open(path, "rb") as f:
-                head = f.read(32)
-            n_allocs = int.from_bytes(head[24:32], "little")
+            n_allocs = file_info(path)["n_allocs"]
         out = (_vp * max(n_allocs, 1))()
         rep = ckpt_verify_report()
         img = _vp()
@@ -433,6 +434,14 @@ class Context:
         t = ckpt_timing()
         _check(lib().ckpt_last_timing(self.handle, ctypes.byref(t)), "ckpt_last_timing")
         return {f: getattr(t, f) for f, _ in ckpt_timing._fields_ if f != "pad"}
+
+
+def file_info(path):
+    """Metadata of the image in a file (plain or compressed), from its header
+    and tables alone."""
+    m = ckpt_image_meta()
+    _check(lib().ckpt_image_file_info(os.fsencode(path), ctypes.byref(m)), "ckpt_image_file_info")
+    return {f: getattr(m, f) for f, _ in ckpt_image_meta._fields_}
 
 
 def merge(base, *deltas):

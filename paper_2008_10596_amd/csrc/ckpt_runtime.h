@@ -163,6 +163,12 @@ struct ImageFile {
     std::string path;
     std::vector<uint8_t> head;
     ImageHead h;
+    // a compressed container (CKPT_FILE_DEFLATE): DATA in blocks of zblock
+    // bytes, block b stored at zoff[b] as zlen[b] bytes, raw when zraw[b]
+    bool deflated = false;
+    uint32_t zblock = 0;
+    std::vector<uint64_t> zoff, zlen;
+    std::vector<uint8_t> zraw;
     ImageFile() = default;
     ImageFile(const ImageFile &) = delete;
     ImageFile &operator=(const ImageFile &) = delete;
@@ -172,6 +178,9 @@ int open_image_file(const char *path, ImageFile *f);
 // image_from_head, then DATA read from the file straight into the image's
 // pinned memory by several threads.
 int load_image_file(ckpt_ctx *ctx, ImageFile *f, ckpt_image **out);
+
+// Digest of an image's CRC section (ckpt_image_meta.crc_digest).
+uint64_t crc_digest(const void *p, size_t n);
 
 // The serialized form up to (not including) DATA, which follows it.
 size_t serialized_head_bytes(const ckpt_image *img);

@@ -169,9 +169,13 @@ uint64_t next_serial()
     return base | (++g_serial & 0xFFFFFFFFull);
 }
 
+
+uint64_t ru16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
+}  // namespace
+
 // Digest of an image's CRC section: FNV-1a over little-endian 64-bit words
 // (the last word zero-padded).  Computed when asked for, not per checkpoint.
-uint64_t crc_digest(const void *p, size_t n)
+uint64_t ckpt::crc_digest(const void *p, size_t n)
 {
     const uint8_t *b = (const uint8_t *)p;
     uint64_t h = 0xcbf29ce484222325ull;
@@ -188,9 +192,6 @@ uint64_t crc_digest(const void *p, size_t n)
     }
     return h;
 }
-
-uint64_t ru16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
-}  // namespace
 
 int PinnedBuf::ensure(size_t bytes)
 {

@@ -4,10 +4,23 @@
 // and read in large blocks.  Writes bypass the page cache (O_DIRECT) where the
 // file system allows it: the image is staged through aligned blocks, one
 // thread fills a block while another writes the previous one.
+//
+// With CKPT_FILE_DEFLATE the file is a compressed container instead.  DMTCP
+// gzips its images by default (the paper turns that off for its timings,
+// Sec. 4.4); here DATA is cut into 4 MiB blocks that a pool of threads
+// compresses with zlib's fastest level, each block kept raw when it does not
+// shrink, and read back by a pool that inflates straight into pinned memory.
+// Container layout, little-endian:
+//   magic "CKPTZIP1", u32 version (1), u32 block bytes, u64 head bytes,
+//   u64 DATA bytes, u64 block count, one u64 per block (stored bytes; top bit
+//   set: stored raw), the serialized head (header and tables, as in
+//   ckpt_image_serialize), then the blocks back to back.
 #include <fcntl.h>
 #include <sys/stat.h>
 #include <unistd.h>
+#include <zlib.h>
 
+#include <atomic>
 #include <cerrno>
 #include <condition_variable>
 #include <cstdlib>
@@ -26,6 +39,21 @@ namespace {
 
 constexpr size_t kBlock = size_t(64) << 20;   // bytes per write
 constexpr size_t kAlign = 4096;               // O_DIRECT alignment of buffer, offset and length
+
+constexpr char kZipMagic[8] = {'C', 'K', 'P', 'T', 'Z', 'I', 'P', '1'};
+constexpr uint32_t kZipVersion = 1;
+constexpr size_t kZipHeader = 8 + 4 + 4 + 8 + 8 + 8;
+constexpr uint32_t kZipBlock = 4u << 20;          // DATA bytes per compressed block
+constexpr uint64_t kZipRawBit = uint64_t(1) << 63;
+constexpr size_t kZipProbe = 64 << 10;            // bytes tried first
+constexpr double kZipProbeKeep = 0.97;            // a probe above this ratio: the block stays raw
+constexpr unsigned kZipThreads = 16;
+
+unsigned pool_threads(uint64_t jobs, unsigned cap)
+{
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>({jobs, cap, hw}));
+}
 
 // The image's serialized bytes as a list of (pointer, length) pieces in file
 // order, without copying the large DATA section.
@@ -63,19 +91,170 @@ int write_all(int fd, const uint8_t *p, size_t n, off_t off)
     return 0;
 }
 
+// The compressed container of pc at fd (buffered I/O).  Threads take blocks
+// in order, compress them, and write them in block order as their turn comes;
+// the block table is written last.  *total receives the file size.
+int write_deflated(int fd, const Pieces &pc, const std::string &tmp_path, uint64_t *total)
+{
+    const uint64_t nb = (pc.data_bytes + kZipBlock - 1) / kZipBlock;
+    std::vector<uint8_t> hdr(kZipHeader);
+    memcpy(hdr.data(), kZipMagic, 8);
+    const uint32_t h32[2] = {kZipVersion, kZipBlock};
+    const uint64_t h64[3] = {pc.head.size(), pc.data_bytes, nb};
+    memcpy(hdr.data() + 8, h32, 8);
+    memcpy(hdr.data() + 16, h64, 24);
+    const uint64_t table_off = kZipHeader, head_off = table_off + 8 * nb;
+    int err = write_all(fd, hdr.data(), hdr.size(), 0);
+    if (!err)
+        err = write_all(fd, pc.head.data(), pc.head.size(), (off_t)head_off);
+    if (err)
+        return set_error(CKPT_E_IO, "write of %s failed: %s", tmp_path.c_str(), strerror(err));
+    std::vector<uint64_t> table(nb, 0);
+    std::mutex mu;
+    std::condition_variable cv;
+    std::atomic<uint64_t> next{0};
+    uint64_t turn = 0, pos = head_off + pc.head.size();
+    int rc = CKPT_OK;
+    std::string msg;
+    auto worker = [&] {
+        const uLong cap = compressBound(kZipBlock);
+        std::vector<uint8_t> out(cap), probe(compressBound(kZipProbe));
+        for (;;) {
+            const uint64_t b = next.fetch_add(1);
+            if (b >= nb)
+                return;
+            const uint8_t *src = pc.data + b * kZipBlock;
+            const uint64_t n = std::min<uint64_t>(kZipBlock, pc.data_bytes - b * kZipBlock);
+            // a block whose first 64 KiB do not compress is stored as it is
+            bool raw = true;
+            uLongf got = 0;
+            uLongf pg = (uLongf)probe.size();
+            const uLong pn = (uLong)std::min<uint64_t>(n, kZipProbe);
+            if (compress2(probe.data(), &pg, src, pn, Z_BEST_SPEED) == Z_OK && pg < kZipProbeKeep * pn) {
+                got = cap;
+                raw = !(compress2(out.data(), &got, src, (uLong)n, Z_BEST_SPEED) == Z_OK && got < n);
+            }
+            const uint8_t *w = raw ? src : out.data();
+            const uint64_t wn = raw ? n : (uint64_t)got;
+            // blocks take their file offsets in order; the write itself can
+            // overlap the next blocks' writes
+            uint64_t at = 0;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return turn == b || rc != CKPT_OK; });
+                if (rc != CKPT_OK)
+                    return;
+                at = pos;
+                pos += wn;
+                turn = b + 1;
+                table[b] = wn | (raw ? kZipRawBit : 0);
+            }
+            cv.notify_all();
+            const int e = write_all(fd, w, wn, (off_t)at);
+            if (e) {
+                std::lock_guard<std::mutex> lk2(mu);
+                if (rc == CKPT_OK) {
+                    rc = CKPT_E_IO;
+                    msg = std::string("write of ") + tmp_path + " failed: " + strerror(e);
+                }
+                cv.notify_all();
+                return;
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    const unsigned nt = pool_threads(nb, kZipThreads);
+    for (unsigned t = 1; t < nt; t++)
+        th.emplace_back(worker);
+    worker();
+    for (auto &x : th)
+        x.join();
+    if (rc != CKPT_OK)
+        return set_error(rc, "%s", msg.c_str());
+    if (nb && (err = write_all(fd, (const uint8_t *)table.data(), 8 * nb, (off_t)table_off)))
+        return set_error(CKPT_E_IO, "write of %s failed: %s", tmp_path.c_str(), strerror(err));
+    *total = pos;
+    return CKPT_OK;
+}
+
+// The file's block table checked against its size and DATA bytes; fills the
+// container fields of f.
+int parse_zip(const uint8_t *hdr, uint64_t size, ImageFile *f, uint64_t *head_off, uint64_t *head_bytes,
+              uint64_t *data_bytes)
+{
+    uint32_t h32[2];
+    uint64_t h64[3];
+    memcpy(h32, hdr + 8, 8);
+    memcpy(h64, hdr + 16, 24);
+    const uint64_t nb = h64[2];
+    if (h32[0] != kZipVersion || h32[1] == 0 || h32[1] > (1u << 30))
+        return set_error(CKPT_E_INVAL, "bad compressed container header");
+    if (nb > size / 8 || nb != (h64[1] + h32[1] - 1) / h32[1] || h64[0] > size)
+        return set_error(CKPT_E_INVAL, "truncated compressed container");
+    std::vector<uint64_t> table(nb);
+    if (nb && pread(f->fd, table.data(), 8 * nb, (off_t)kZipHeader) != (ssize_t)(8 * nb))
+        return set_error(CKPT_E_INVAL, "truncated compressed container");
+    *head_off = kZipHeader + 8 * nb;
+    *head_bytes = h64[0];
+    *data_bytes = h64[1];
+    f->deflated = true;
+    f->zblock = h32[1];
+    f->zoff.resize(nb);
+    f->zlen.resize(nb);
+    f->zraw.resize(nb);
+    uint64_t pos = *head_off + h64[0];
+    for (uint64_t b = 0; b < nb; b++) {
+        const uint64_t want = std::min<uint64_t>(h32[1], h64[1] - b * h32[1]);
+        const bool raw = table[b] & kZipRawBit;
+        const uint64_t len = table[b] & ~kZipRawBit;
+        if ((raw && len != want) || (!raw && (len == 0 || len > compressBound((uLong)want))) || len > size ||
+            pos > size - len)
+            return set_error(CKPT_E_INVAL, "bad block %llu of the compressed container", (unsigned long long)b);
+        f->zoff[b] = pos;
+        f->zlen[b] = len;
+        f->zraw[b] = raw;
+        pos += len;
+    }
+    if (pos != size)
+        return set_error(CKPT_E_INVAL, "compressed container is %llu bytes, its table says %llu",
+                         (unsigned long long)size, (unsigned long long)pos);
+    return CKPT_OK;
+}
+
 }  // namespace
 
 extern "C" int ckpt_image_write_file(const ckpt_image *img, const char *path, uint32_t flags, uint64_t *bytes)
 {
     if (!img || !path)
         return set_error(CKPT_E_INVAL, "NULL argument");
-    if (flags & ~(uint32_t)CKPT_FILE_BUFFERED)
+    if (flags & ~(uint32_t)(CKPT_FILE_BUFFERED | CKPT_FILE_DEFLATE))
         return set_error(CKPT_E_INVAL, "unknown file flags 0x%x", flags);
     image_wait(img);
     Pieces pc;
     CKPT_TRY(image_pieces(img, &pc));
     const size_t total = pc.head.size() + pc.data_bytes;
     const std::string tmp_path = std::string(path) + ".partial";
+    if (flags & CKPT_FILE_DEFLATE) {
+        const int fd = open(tmp_path.c_str(), O_WRONLY | O_CREAT | O_TRUNC, 0644);
+        if (fd < 0)
+            return set_error(CKPT_E_IO, "cannot create %s: %s", tmp_path.c_str(), strerror(errno));
+        uint64_t n = 0;
+        int rc = write_deflated(fd, pc, tmp_path, &n);
+        if (rc == CKPT_OK && ftruncate(fd, (off_t)n) != 0)
+            rc = set_error(CKPT_E_IO, "truncate failed: %s", strerror(errno));
+        if (rc == CKPT_OK && fsync(fd) != 0)
+            rc = set_error(CKPT_E_IO, "fsync failed: %s", strerror(errno));
+        close(fd);
+        if (rc == CKPT_OK && rename(tmp_path.c_str(), path) != 0)
+            rc = set_error(CKPT_E_IO, "rename to %s failed: %s", path, strerror(errno));
+        if (rc != CKPT_OK) {
+            unlink(tmp_path.c_str());
+            return rc;
+        }
+        if (bytes)
+            *bytes = n;
+        return CKPT_OK;
+    }
 
     bool direct = !(flags & CKPT_FILE_BUFFERED);
     int fd = -1;
@@ -221,6 +400,16 @@ int ckpt::open_image_file(const char *path, ImageFile *f)
     uint8_t hdr[128];
     const size_t nh = (size_t)std::min<uint64_t>(size, sizeof hdr);
     CKPT_TRY(read_all(f->fd, hdr, nh, 0, path));
+    if (nh >= kZipHeader && memcmp(hdr, kZipMagic, 8) == 0) {
+        uint64_t head_off = 0, head_bytes = 0, data_bytes = 0;
+        CKPT_TRY(parse_zip(hdr, size, f, &head_off, &head_bytes, &data_bytes));
+        f->head.resize(head_bytes);
+        CKPT_TRY(read_all(f->fd, f->head.data(), head_bytes, head_off, path));
+        CKPT_TRY(parse_head(f->head.data(), head_bytes, &f->h, data_bytes));
+        if (f->h.head_bytes != head_bytes || f->h.ser_bytes != data_bytes)
+            return set_error(CKPT_E_INVAL, "compressed container does not match its image header");
+        return CKPT_OK;
+    }
     uint64_t head = 0, ser = 0;
     CKPT_TRY(head_layout(hdr, nh, size, &head, &ser));
     f->head.resize(head);
@@ -234,6 +423,55 @@ int ckpt::load_image_file(ckpt_ctx *ctx, ImageFile *f, ckpt_image **out)
     ckpt_image *img = nullptr;
     CKPT_TRY(image_from_head(ctx, &f->h, &img));
     std::unique_ptr<ckpt_image> guard(img);
+    if (f->deflated) {
+        // each block read and inflated straight into its place in the pinned buffer
+        const uint64_t nb = f->zoff.size();
+        std::atomic<uint64_t> next{0};
+        std::mutex mu;
+        int rc = CKPT_OK;
+        std::string msg;
+        auto worker = [&] {
+            std::vector<uint8_t> cbuf;
+            for (;;) {
+                const uint64_t b = next.fetch_add(1);
+                if (b >= nb)
+                    return;
+                uint8_t *dst = (uint8_t *)img->data.p + b * f->zblock;
+                const uint64_t want = std::min<uint64_t>(f->zblock, ser - b * f->zblock);
+                int r = CKPT_OK;
+                if (f->zraw[b]) {
+                    r = read_all(f->fd, dst, want, f->zoff[b], f->path.c_str());
+                } else {
+                    cbuf.resize(f->zlen[b]);
+                    r = read_all(f->fd, cbuf.data(), f->zlen[b], f->zoff[b], f->path.c_str());
+                    uLongf got = (uLongf)want;
+                    if (r == CKPT_OK && (uncompress(dst, &got, cbuf.data(), (uLong)f->zlen[b]) != Z_OK || got != want))
+                        r = set_error(CKPT_E_INVAL, "block %llu of %s does not inflate to %llu bytes",
+                                      (unsigned long long)b, f->path.c_str(), (unsigned long long)want);
+                }
+                if (r != CKPT_OK) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    if (rc == CKPT_OK) {
+                        rc = r;
+                        msg = ckpt_last_error();
+                    }
+                    next.store(nb);   // the other workers stop at their next block
+                    return;
+                }
+            }
+        };
+        std::vector<std::thread> th;
+        const unsigned nt = pool_threads(nb, kZipThreads);
+        for (unsigned t = 1; t < nt; t++)
+            th.emplace_back(worker);
+        worker();
+        for (auto &x : th)
+            x.join();
+        if (rc != CKPT_OK)
+            return set_error(rc, "%s", msg.c_str());
+        *out = guard.release();
+        return CKPT_OK;
+    }
     // DATA in kBlock pieces, dealt round-robin to up to 8 readers, each
     // reading straight into the pinned buffer (no staging copy)
     const uint64_t nblocks = (ser + kBlock - 1) / kBlock;
@@ -272,4 +510,28 @@ extern "C" int ckpt_image_read_file(ckpt_ctx *ctx, const char *path, ckpt_image 
     ImageFile f;
     CKPT_TRY(open_image_file(path, &f));
     return load_image_file(ctx, &f, out);
+}
+
+extern "C" int ckpt_image_file_info(const char *path, ckpt_image_meta *out)
+{
+    if (!path || !out)
+        return set_error(CKPT_E_INVAL, "NULL argument");
+    ImageFile f;
+    CKPT_TRY(open_image_file(path, &f));
+    const ImageHead &h = f.h;
+    if (crc_digest(h.rest, h.N * 4) != h.digest)
+        return set_error(CKPT_E_INVAL, "CRC section digest mismatch");
+    memset(out, 0, sizeof(*out));
+    out->mode = h.mode;
+    out->chunk_bytes = h.C;
+    out->n_allocs = h.allocs.size();
+    out->n_chunks = h.N;
+    out->data_bytes = h.data_bytes;
+    out->serialized_bytes = h.ser_bytes;
+    out->n_dirty = h.n_dirty;
+    out->serial = h.serial;
+    out->base_serial = h.base_serial;
+    out->crc_digest = h.digest;
+    out->drained = 1;
+    return CKPT_OK;
 }

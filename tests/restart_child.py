@@ -1,8 +1,10 @@
 """Child process of the restart test (run as `python -m tests.restart_child`).
 
-  save PATH     make address-stable allocations with seeded contents in a
+  save PATH [deflate]
+                make address-stable allocations with seeded contents in a
                 fresh process, checkpoint them, write the serialized image to
-                PATH and print the addresses and ids as JSON;
+                PATH (the compressed container with "deflate") and print the
+                addresses and ids as JSON;
   restore PATH  in another fresh process, restore the image file at the
                 addresses it was taken from (ranges reserved first), check the
                 bytes there, take an incremental checkpoint against the loaded
@@ -36,7 +38,7 @@ def contents():
     return out
 
 
-def save(path):
+def save(path, deflate=False):
     data = contents()
     ctx = K.Context(chunk_bytes=C)
     addrs, ids = [], []
@@ -46,7 +48,7 @@ def save(path):
         addrs.append(p)
         ids.append(i)
     img = ctx.checkpoint()
-    img.write_file(path)
+    img.write_file(path, deflate=deflate)
     print(json.dumps({"addrs": addrs, "ids": ids}), flush=True)
 
 
@@ -69,4 +71,7 @@ def restore(path):
 
 
 if __name__ == "__main__":
-    {"save": save, "restore": restore}[sys.argv[1]](sys.argv[2])
+    if sys.argv[1] == "save":
+        save(sys.argv[2], deflate=len(sys.argv) > 3 and sys.argv[3] == "deflate")
+    else:
+        restore(sys.argv[2])

@@ -142,3 +142,75 @@ def test_host_only_failures_before_any_device_work(ck, tmp_path):
     assert lib.ckpt_image_merge(None, None, ctypes.byref(out)) == ck.CKPT_E_INVAL
     assert lib.ckpt_restore_file_at(None, None, b"x", None, None, None) == ck.CKPT_E_INVAL
     assert lib.ckpt_image_write_file(None, b"x", 0, None) == ck.CKPT_E_INVAL
+    assert lib.ckpt_image_write_file(None, b"x", ck.CKPT_FILE_DEFLATE, None) == ck.CKPT_E_INVAL
+
+
+def _zip_container(version=1, block=4 << 20, head=b"", data_bytes=0, table=(), blocks=b""):
+    """A compressed container (the CKPT_FILE_DEFLATE layout), fields as given."""
+    out = bytearray(b"CKPTZIP1")
+    out += version.to_bytes(4, "little") + block.to_bytes(4, "little")
+    out += len(head).to_bytes(8, "little") + data_bytes.to_bytes(8, "little") + len(table).to_bytes(8, "little")
+    for t in table:
+        out += t.to_bytes(8, "little")
+    return bytes(out + head + blocks)
+
+
+def _empty_image_head(serial=7):
+    """The serialized form of an image with no allocations: the fixed header
+    alone (its CRC-section digest is FNV-1a's offset basis, no words)."""
+    hdr = bytearray(b"CKPTIMG1")
+    hdr += (2).to_bytes(4, "little") + (0).to_bytes(4, "little") + (4096).to_bytes(4, "little") + \
+        (16).to_bytes(4, "little")
+    for v in (0, 0, 0, 0, 0, serial, 0, 0xcbf29ce484222325):   # n N data ser n_dirty serial base digest
+        hdr += v.to_bytes(8, "little")
+    return bytes(hdr)
+
+
+def test_file_info_reads_plain_and_compressed_headers(ck, tmp_path):
+    """ckpt_image_file_info parses a file's header and tables alone, plain
+    or inside the compressed container, with no device."""
+    lib = ck.lib()
+    m = ck.ckpt_image_meta()
+    plain, zipped = tmp_path / "e.img", tmp_path / "e.imgz"
+    plain.write_bytes(_empty_image_head(serial=7))
+    zipped.write_bytes(_zip_container(head=_empty_image_head(serial=9)))
+    for path, serial in ((plain, 7), (zipped, 9)):
+        assert lib.ckpt_image_file_info(str(path).encode(), ctypes.byref(m)) == ck.CKPT_OK
+        assert (m.mode, m.chunk_bytes, m.n_allocs, m.n_chunks, m.serialized_bytes, m.serial, m.drained) == \
+            (ck.CKPT_FULL, 4096, 0, 0, 0, serial, 1)
+    assert ck.file_info(str(zipped))["serial"] == 9
+    bad = bytearray(_empty_image_head())
+    bad[-1] ^= 1                                               # digest no longer matches
+    plain.write_bytes(bytes(bad))
+    assert lib.ckpt_image_file_info(str(plain).encode(), ctypes.byref(m)) == ck.CKPT_E_INVAL
+    assert lib.ckpt_image_file_info(str(tmp_path / "none").encode(), ctypes.byref(m)) == ck.CKPT_E_NOTFOUND
+    assert lib.ckpt_image_file_info(None, ctypes.byref(m)) == ck.CKPT_E_INVAL
+    assert lib.ckpt_image_file_info(str(zipped).encode(), None) == ck.CKPT_E_INVAL
+
+
+def test_compressed_container_is_checked_before_any_device_work(ck, tmp_path):
+    """Malformed compressed containers fail on their header and block table
+    alone: nothing is allocated or inflated."""
+    lib = ck.lib()
+    out = ctypes.c_void_p()
+    path = tmp_path / "z.img"
+    raw = 1 << 63
+
+    def rc(data):
+        path.write_bytes(data)
+        return lib.ckpt_image_read_file(None, str(path).encode(), ctypes.byref(out))
+
+    assert rc(b"CKPTZIP1" + bytes(10)) == ck.CKPT_E_INVAL                    # header cut short
+    assert rc(_zip_container(version=2)) == ck.CKPT_E_INVAL                 # unknown version
+    assert rc(_zip_container(block=0)) == ck.CKPT_E_INVAL                   # zero block size
+    # the block count must be ceil(DATA / block)
+    assert rc(_zip_container(data_bytes=5 << 20, table=(raw | (4 << 20),))) == ck.CKPT_E_INVAL
+    # a raw block must hold exactly its share of DATA
+    assert rc(_zip_container(data_bytes=100, table=(raw | 99,), blocks=bytes(99))) == ck.CKPT_E_INVAL
+    # the table may not run past the end of the file
+    assert rc(_zip_container(data_bytes=100, table=(raw | 100,), blocks=bytes(60))) == ck.CKPT_E_INVAL
+    # nor leave bytes after the last block
+    assert rc(_zip_container(data_bytes=100, table=(raw | 100,), blocks=bytes(101))) == ck.CKPT_E_INVAL
+    # a consistent table around a head that is not an image header
+    assert rc(_zip_container(head=b"NOTANIMAGEHEAD" * 8, data_bytes=100, table=(raw | 100,),
+                             blocks=bytes(100))) == ck.CKPT_E_INVAL

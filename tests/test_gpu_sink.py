@@ -2,6 +2,7 @@
 read image equals the written one section by section, and restoring from it
 gives the original memory."""
 import os
+import zlib
 
 import numpy as np
 import pytest
@@ -76,4 +77,109 @@ def test_file_errors(tmp_path):
     for im in (img, dimg):
         im.close()
     nd.close()
+    ctx.close()
+
+
+def read_container(path):
+    """The compressed container read with Python's zlib, following the
+    documented layout: returns (head + inflated DATA, raw flags per block)."""
+    with open(path, "rb") as f:
+        b = f.read()
+    assert b[:8] == b"CKPTZIP1"
+    version, block = int.from_bytes(b[8:12], "little"), int.from_bytes(b[12:16], "little")
+    head_bytes, data_bytes, nb = (int.from_bytes(b[16 + 8 * i:24 + 8 * i], "little") for i in range(3))
+    assert version == 1 and nb == -(-data_bytes // block)
+    table = [int.from_bytes(b[40 + 8 * i:48 + 8 * i], "little") for i in range(nb)]
+    pos = 40 + 8 * nb
+    out = bytearray(b[pos:pos + head_bytes])
+    pos += head_bytes
+    raws = []
+    for i, t in enumerate(table):
+        raw, n = bool(t >> 63), t & ((1 << 63) - 1)
+        chunk = b[pos:pos + n]
+        piece = chunk if raw else zlib.decompress(chunk)
+        assert len(piece) == min(block, data_bytes - i * block)
+        out += piece
+        raws.append(raw)
+        pos += n
+    assert pos == len(b)
+    return bytes(out), raws
+
+
+def compressible_allocs(sizes, seed):
+    """bf16 values drawn from N(0, 1) (model-weight-like bytes), as uint8 views."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    out = []
+    for s in sizes:
+        t = torch.randn((s + 1) // 2, generator=g, device="cuda").to(torch.bfloat16)
+        out.append(t.view(torch.uint8)[:s].clone())
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("kind", ["random", "bf16"])
+def test_deflate_container_roundtrip(tmp_path, kind):
+    """The compressed file holds the serialized image block by block (checked
+    with an independent zlib reader), reads back section by section, and
+    restores the original memory.  Random data stays raw; bf16 data shrinks."""
+    sizes = [9 << 20, 3 << 20, 5000, 1, 0, 4096]
+    log("deflate container kind=%s" % kind)
+    if kind == "random":
+        tensors = random_allocs(sizes, seed=33, zero=(1,))
+    else:
+        tensors = compressible_allocs(sizes, seed=34)
+    ctx = K.Context(chunk_bytes=C)
+    for t in tensors:
+        ctx.register(t)
+    img = ctx.checkpoint()
+    path = str(tmp_path / "img.ckptz")
+    n = img.write_file(path, deflate=True)
+    assert n == os.path.getsize(path) and not os.path.exists(path + ".partial")
+    blob, raws = read_container(path)
+    assert blob == img.serialize()
+    ser = img.info()["serialized_bytes"]
+    assert len(raws) == -(-ser // (4 << 20)) and len(raws) >= 3
+    if kind == "random":
+        assert all(raws)
+    else:
+        assert not any(raws) and n < 0.9 * len(blob)
+    back = K.Image.read_file(path, ctx)
+    for key in ("allocs", "crc", "flags", "data", "addrs"):
+        assert np.array_equal(getattr(back, key), getattr(img, key)), key
+    ref = O.checkpoint([host(t) for t in tensors], C)
+    assert np.array_equal(back.crc, ref["crc"]) and np.array_equal(back.data, ref["serialized"])
+    dsts = [torch.empty_like(t) for t in tensors]
+    rc, _ = ctx.restore(back, dsts)
+    assert rc == K.CKPT_OK
+    check_restored(dsts, tensors)
+    for im in (img, back):
+        im.close()
+    ctx.close()
+
+
+def test_deflate_container_damage_is_refused(tmp_path):
+    tensors = compressible_allocs([6 << 20], seed=35)
+    ctx = K.Context(chunk_bytes=C)
+    ctx.register(tensors[0])
+    img = ctx.checkpoint()
+    path = str(tmp_path / "img.ckptz")
+    n = img.write_file(path, deflate=True)
+    # a flipped byte in the middle of the last compressed block
+    with open(path, "r+b") as f:
+        f.seek(n - 100)
+        x = f.read(1)
+        f.seek(n - 100)
+        f.write(bytes([x[0] ^ 0x40]))
+    with pytest.raises(K.CkptError) as e:
+        K.Image.read_file(path, ctx)
+    assert e.value.status == K.CKPT_E_INVAL
+    # and a file cut short
+    img.write_file(path, deflate=True)
+    with open(path, "r+b") as f:
+        f.truncate(n - 1)
+    with pytest.raises(K.CkptError) as e:
+        K.Image.read_file(path, ctx)
+    assert e.value.status == K.CKPT_E_INVAL
+    img.close()
     ctx.close()

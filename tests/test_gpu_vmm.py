@@ -300,10 +300,11 @@ def test_restore_file_at(tmp_path):
     ctx.close()
 
 
-def test_restart_in_a_fresh_process_at_the_same_addresses(tmp_path):
+@pytest.mark.parametrize("deflate", [False, True])
+def test_restart_in_a_fresh_process_at_the_same_addresses(tmp_path, deflate):
     """Save in one fresh process, restore in another: every allocation comes
     back at its address, with its id, and an incremental checkpoint against
-    the loaded image follows."""
+    the loaded image follows.  The file is plain or the compressed container."""
     path = str(tmp_path / "image.ckpt")
     env = dict(os.environ)
     env["PYTHONPATH"] = ROOT + os.pathsep + env.get("PYTHONPATH", "")
@@ -315,7 +316,7 @@ def test_restart_in_a_fresh_process_at_the_same_addresses(tmp_path):
         assert r.returncode == 0, r.stderr[-2000:]
         return json.loads(r.stdout.strip().splitlines()[-1])
 
-    a = child("save", path)
+    a = child("save", path, *(["deflate"] if deflate else []))
     b = child("restore", path)
     assert b["rc"] == K.CKPT_OK and b["n_bad"] == 0
     assert b["addrs"] == a["addrs"]
@@ -325,8 +326,7 @@ def test_restart_in_a_fresh_process_at_the_same_addresses(tmp_path):
     assert b["dirty"] == [2]   # the chunk rewritten after the restore
     # and the saved image is the oracle's
     from tests.restart_child import contents  # noqa: E402
-    with open(path, "rb") as f:
-        img = K.Image.load(f.read())
+    img = K.Image.read_file(path)
     check_image(img, contents())
     img.close()
 
