@@ -95,10 +95,11 @@ def algorithmic_bytes(sizes, C):
     return S, dense, N, S + dense + 5 * N
 
 
-def cpu_baseline(tensors, sizes, C, budget_bytes=2 << 30, reps=3):
+def cpu_baseline(tensors, sizes, C, budget_bytes=8 << 30, reps=3):
     """The oracle (plain C, bytewise table CRC) on a bounded sample of the
-    same workload: the first allocations up to budget_bytes.  Host copies are
-    made before timing."""
+    same workload: the first allocations up to budget_bytes (about 20 core-
+    seconds of oracle work per run on 16 cores).  Host copies are made before
+    timing."""
     import ctypes
 
     import numpy as np

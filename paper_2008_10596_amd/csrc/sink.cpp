@@ -187,7 +187,7 @@ int parse_zip(const uint8_t *hdr, uint64_t size, ImageFile *f, uint64_t *head_of
     memcpy(h32, hdr + 8, 8);
     memcpy(h64, hdr + 16, 24);
     const uint64_t nb = h64[2];
-    if (h32[0] != kZipVersion || h32[1] == 0 || h32[1] > (1u << 30))
+    if (h32[0] != kZipVersion || h32[1] == 0 || h32[1] > (1u << 30) || h64[1] >= (uint64_t(1) << 62))
         return set_error(CKPT_E_INVAL, "bad compressed container header");
     if (nb > size / 8 || nb != (h64[1] + h32[1] - 1) / h32[1] || h64[0] > size)
         return set_error(CKPT_E_INVAL, "truncated compressed container");

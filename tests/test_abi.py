@@ -203,6 +203,7 @@ def test_compressed_container_is_checked_before_any_device_work(ck, tmp_path):
     assert rc(b"CKPTZIP1" + bytes(10)) == ck.CKPT_E_INVAL                    # header cut short
     assert rc(_zip_container(version=2)) == ck.CKPT_E_INVAL                 # unknown version
     assert rc(_zip_container(block=0)) == ck.CKPT_E_INVAL                   # zero block size
+    assert rc(_zip_container(data_bytes=(1 << 64) - 1, table=(raw | 5,))) == ck.CKPT_E_INVAL   # DATA too large
     # the block count must be ceil(DATA / block)
     assert rc(_zip_container(data_bytes=5 << 20, table=(raw | (4 << 20),))) == ck.CKPT_E_INVAL
     # a raw block must hold exactly its share of DATA
