@@ -81,13 +81,15 @@ def test_full_checkpoint_at_scale_sampled():
     free()
 
 
-def test_incremental_at_scale_exact_dirty_set():
+@pytest.mark.parametrize("C", [65536, 4096])
+def test_incremental_at_scale_exact_dirty_set(C):
+    """The 8 GiB incremental workload in both chunk sizes bench.py times (64 KiB:
+    one wave per chunk; 4 KiB: four chunks per wave)."""
     w = synth.incremental()
     sizes = [int(s) for s in w["sizes"]]
-    C = 65536
     g = w["grid"]
-    assert g == C
-    log("incremental: %d allocations, %d cells rewritten" % (len(sizes), len(w["mut_alloc"])))
+    assert g % C == 0
+    log("incremental C=%d: %d allocations, %d cells rewritten" % (C, len(sizes), len(w["mut_alloc"])))
     tensors = synth.make_device_allocs(sizes, w["zero"], workload=3)
     ctx = K.Context(chunk_bytes=C)
     for t in tensors:
@@ -101,8 +103,12 @@ def test_incremental_at_scale_exact_dirty_set():
     torch.cuda.synchronize()
     delta = ctx.checkpoint(mode=K.CKPT_INCREMENTAL, base=base)
     _, cb, _, N = O.layout(sizes, C)
-    # with C equal to the mutation grid, the dirty set is exactly the rewritten cells
-    want = np.sort(cb[w["mut_alloc"]].astype(np.int64) + w["mut_cell"])
+    # every chunk of a rewritten cell (new random bytes) is dirty, and no other
+    want = []
+    for k, c in zip(w["mut_alloc"], w["mut_cell"]):
+        lo, hi = int(c) * g, min(sizes[int(k)], (int(c) + 1) * g)
+        want.extend(int(cb[int(k)]) + lo // C + j for j in range(-(-(hi - lo) // C)))
+    want = np.unique(np.array(want, np.int64))
     assert np.array_equal(delta.dirty_ids.astype(np.int64), want)
     # sampled oracle deltas
     dcrc, dflags, ddata = delta.crc, delta.flags, delta.data
