@@ -103,6 +103,21 @@ def run_cache(mode):
     out["hit"] = hook.cache_stats()["hits"] == h0 + 1
     torch.cuda.synchronize()
     out["after_reuse"] = check(ctx, live + [x], ctx.checkpoint())
+    # a block freed on one stream is handed out again on that stream only
+    side = torch.cuda.Stream()
+    n2 = 70000
+    with torch.cuda.stream(side):
+        y = torch.empty(n2, dtype=torch.uint8, device="cuda")
+        py = y.data_ptr()
+        del y
+    zt = torch.empty(n2, dtype=torch.uint8, device="cuda")   # default stream
+    out["other_stream_fresh"] = zt.data_ptr() != py
+    with torch.cuda.stream(side):
+        y2 = torch.empty(n2, dtype=torch.uint8, device="cuda")
+        out["same_stream_reused"] = y2.data_ptr() == py
+        del y2
+    del zt
+    torch.cuda.synchronize()
     if stable:
         # x's block goes back to the cache; the image still has e at that address
         del x

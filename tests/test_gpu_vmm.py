@@ -376,6 +376,7 @@ def test_hook_cache_keeps_the_log_exact(mode):
     assert out["cached_after_frees"] >= 1
     assert out["reused"] and out["hit"]
     _check_logged(out["after_reuse"])
+    assert out["other_stream_fresh"] and out["same_stream_reused"]
     if mode == "stable":
         # the restore at the recorded addresses gives the cached block back first
         assert out["restore_rc"] == K.CKPT_OK and out["restore_bad"] == 0
