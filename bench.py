@@ -420,6 +420,30 @@ def bench_restore_at(K, torch, tensors, sizes, C, stream, reps=3):
     return out
 
 
+def copy_reference(torch, nbytes, reps=5):
+    """A plain device-to-device copy (torch copy_, i.e. the runtime's own copy)
+    of nbytes into a fresh buffer, timed with events on the current stream:
+    what moving the same read + write bytes costs without the method."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    m = statistics.median(ms)
+    return {"bytes_read_plus_written": 2 * nbytes, "ms": round(m, 4), "gbps": round(2 * nbytes / (m * 1e-3) / 1e9, 1),
+            "kind": "device-to-device copy_ of %.0f GiB into a fresh buffer, median of %d" % (nbytes / 2**30, reps)}
+
+
 def sink_deflate(K, img, ctx, path):
     """Write img as the compressed container and read it back; rates are
     per byte of the serialized image (what a caller saves), file bytes apart."""
@@ -783,6 +807,8 @@ def main():
     ms_wide = (time.perf_counter() - t0) * 1e3 / nwide
     wctx.close()
     log("device-wide drain mode: %.3f ms per step" % ms_wide)
+    copy_ref = copy_reference(torch, int((8 << 30) * args.scale))
+    log("copy reference: %s" % copy_ref)
     if args.copy_probe:
         a = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
         b = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
@@ -805,7 +831,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved / 1e9, 2), "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4), "traffic": None,
                      "kernel": "k_chunks<pack>", "algorithmic_bytes_per_launch": alg,
-                     "kernel_ms": round(pack_avg, 4)},
+                     "kernel_ms": round(pack_avg, 4),
+                     "copy_reference": dict(copy_ref, pack_vs_copy=round(achieved / 1e9 / copy_ref["gbps"], 4))},
     }
     prof = profiled_traffic()
     if prof is not None and prof[1] == alg:
