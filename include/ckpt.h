@@ -459,10 +459,11 @@ int ckpt_image_merge(const ckpt_image *base, const ckpt_image *delta, ckpt_image
  */
 #define CKPT_FILE_BUFFERED 0x1u   /* write through the page cache */
 /* Write a compressed container instead (always through the page cache):
- * DATA in 4 MiB blocks, each compressed with zlib's fastest level by a pool
- * of threads (up to 16) and stored raw when its first 64 KiB or the whole
- * block do not shrink; header and tables stay uncompressed.  Layout in
- * sink.cpp.  The paper's checkpointer compresses its images with gzip by
+ * DATA in 4 MiB blocks, compressed by a pool of threads (up to 16), each
+ * block either deflated at zlib's fastest level or split into byte planes of
+ * 2- or 4-byte elements and Huffman-coded, whichever codes its first 64 KiB
+ * smallest, and stored raw when that or the whole block does not shrink;
+ * header and tables stay uncompressed.  Layout in sink.cpp.  The paper's checkpointer compresses its images with gzip by
  * default (Sec. 4.4, where it is turned off for the timings). */
 #define CKPT_FILE_DEFLATE 0x2u
 int ckpt_image_write_file(const ckpt_image *img, const char *path, uint32_t flags, uint64_t *bytes);

@@ -168,7 +168,7 @@ struct ImageFile {
     bool deflated = false;
     uint32_t zblock = 0;
     std::vector<uint64_t> zoff, zlen;
-    std::vector<uint8_t> zraw;
+    std::vector<uint8_t> zraw, zplanes;   // zplanes: element width of the byte planes (1: none)
     ImageFile() = default;
     ImageFile(const ImageFile &) = delete;
     ImageFile &operator=(const ImageFile &) = delete;

@@ -8,13 +8,19 @@
 // With CKPT_FILE_DEFLATE the file is a compressed container instead.  DMTCP
 // gzips its images by default (the paper turns that off for its timings,
 // Sec. 4.4); here DATA is cut into 4 MiB blocks that a pool of threads
-// compresses with zlib's fastest level, each block kept raw when it does not
-// shrink, and read back by a pool that inflates straight into pinned memory.
+// compresses, each block kept raw when it does not shrink, and read back by a
+// pool that inflates straight into pinned memory.  Device memory is mostly
+// arrays of 2- or 4-byte numbers, whose high bytes (sign and exponent) repeat
+// far more than the low ones: a block may first be split into byte planes
+// (byte j of every w-byte element together) and then entropy-coded only
+// (zlib's Huffman-only deflate, no string matching), or be deflated as it is
+// at zlib's fastest level.  A 64 KiB trial of each picks the block's form.
 // Container layout, little-endian:
 //   magic "CKPTZIP1", u32 version (1), u32 block bytes, u64 head bytes,
-//   u64 DATA bytes, u64 block count, one u64 per block (stored bytes; top bit
-//   set: stored raw), the serialized head (header and tables, as in
-//   ckpt_image_serialize), then the blocks back to back.
+//   u64 DATA bytes, u64 block count, one u64 per block (bits 0-60: stored
+//   bytes; bits 61-62: planes, 0 none, 1 two, 2 four; bit 63: stored raw),
+//   the serialized head (header and tables, as in ckpt_image_serialize), then
+//   the blocks back to back, each a zlib stream of the (split) block.
 #include <fcntl.h>
 #include <sys/stat.h>
 #include <unistd.h>
@@ -45,6 +51,53 @@ constexpr uint32_t kZipVersion = 1;
 constexpr size_t kZipHeader = 8 + 4 + 4 + 8 + 8 + 8;
 constexpr uint32_t kZipBlock = 4u << 20;          // DATA bytes per compressed block
 constexpr uint64_t kZipRawBit = uint64_t(1) << 63;
+constexpr int kZipPlaneShift = 61;
+constexpr uint64_t kZipSizeMask = (uint64_t(1) << kZipPlaneShift) - 1;
+constexpr unsigned kZipPlanes[3] = {1, 2, 4};   // element width for plane codes 0, 1, 2
+
+// Byte planes of w-byte elements: out[j * m + i] = in[i * w + j] for the m
+// whole elements; the n - w m trailing bytes follow as they are.
+void split_planes(const uint8_t *in, uint64_t n, unsigned w, uint8_t *out)
+{
+    const uint64_t m = n / w;
+    for (unsigned j = 0; j < w; j++) {
+        uint8_t *o = out + j * m;
+        const uint8_t *p = in + j;
+        for (uint64_t i = 0; i < m; i++)
+            o[i] = p[i * w];
+    }
+    memcpy(out + w * m, in + w * m, n - w * m);
+}
+
+void join_planes(const uint8_t *in, uint64_t n, unsigned w, uint8_t *out)
+{
+    const uint64_t m = n / w;
+    for (unsigned j = 0; j < w; j++) {
+        const uint8_t *p = in + j * m;
+        uint8_t *o = out + j;
+        for (uint64_t i = 0; i < m; i++)
+            o[i * w] = p[i];
+    }
+    memcpy(out + w * m, in + w * m, n - w * m);
+}
+
+// One zlib stream of src[0, n) in out (cap bytes) at level 1 with the given
+// strategy; its size, or 0 when it does not fit.
+uint64_t zlib_pack(const uint8_t *src, uint64_t n, uint8_t *out, uint64_t cap, int strategy)
+{
+    z_stream zs;
+    memset(&zs, 0, sizeof(zs));
+    if (deflateInit2(&zs, Z_BEST_SPEED, Z_DEFLATED, 15, 8, strategy) != Z_OK)
+        return 0;
+    zs.next_in = const_cast<Bytef *>(src);
+    zs.avail_in = (uInt)n;
+    zs.next_out = out;
+    zs.avail_out = (uInt)cap;
+    const int r = deflate(&zs, Z_FINISH);
+    const uint64_t got = zs.total_out;
+    deflateEnd(&zs);
+    return r == Z_STREAM_END ? got : 0;
+}
 constexpr size_t kZipProbe = 64 << 10;            // bytes tried first
 constexpr double kZipProbeKeep = 0.97;            // a probe above this ratio: the block stays raw
 constexpr unsigned kZipThreads = 16;
@@ -117,25 +170,45 @@ int write_deflated(int fd, const Pieces &pc, const std::string &tmp_path, uint64
     int rc = CKPT_OK;
     std::string msg;
     auto worker = [&] {
-        const uLong cap = compressBound(kZipBlock);
-        std::vector<uint8_t> out(cap), probe(compressBound(kZipProbe));
+        const uint64_t cap = compressBound(kZipBlock);
+        std::vector<uint8_t> out(cap), planes(kZipBlock), probe(compressBound(kZipProbe)), pplanes(kZipProbe);
         for (;;) {
             const uint64_t b = next.fetch_add(1);
             if (b >= nb)
                 return;
             const uint8_t *src = pc.data + b * kZipBlock;
             const uint64_t n = std::min<uint64_t>(kZipBlock, pc.data_bytes - b * kZipBlock);
-            // a block whose first 64 KiB do not compress is stored as it is
-            bool raw = true;
-            uLongf got = 0;
-            uLongf pg = (uLongf)probe.size();
-            const uLong pn = (uLong)std::min<uint64_t>(n, kZipProbe);
-            if (compress2(probe.data(), &pg, src, pn, Z_BEST_SPEED) == Z_OK && pg < kZipProbeKeep * pn) {
-                got = cap;
-                raw = !(compress2(out.data(), &got, src, (uLong)n, Z_BEST_SPEED) == Z_OK && got < n);
+            // the form that codes the first 64 KiB smallest: as it is at
+            // level 1, or split into 2 or 4 planes and Huffman-coded
+            const uint64_t pn = std::min<uint64_t>(n, kZipProbe);
+            int code = -1;
+            uint64_t best = pn;
+            for (int c = 0; c < 3; c++) {
+                const uint8_t *in = src;
+                if (c > 0) {
+                    split_planes(src, pn, kZipPlanes[c], pplanes.data());
+                    in = pplanes.data();
+                }
+                const uint64_t g = zlib_pack(in, pn, probe.data(), probe.size(), c ? Z_HUFFMAN_ONLY : Z_DEFAULT_STRATEGY);
+                if (g && g < best) {
+                    best = g;
+                    code = c;
+                }
+            }
+            // a block whose trial does not shrink below 97% is stored as it is
+            bool raw = code < 0 || best >= kZipProbeKeep * pn;
+            uint64_t got = 0;
+            if (!raw) {
+                const uint8_t *in = src;
+                if (code > 0) {
+                    split_planes(src, n, kZipPlanes[code], planes.data());
+                    in = planes.data();
+                }
+                got = zlib_pack(in, n, out.data(), cap, code ? Z_HUFFMAN_ONLY : Z_DEFAULT_STRATEGY);
+                raw = got == 0 || got >= n;
             }
             const uint8_t *w = raw ? src : out.data();
-            const uint64_t wn = raw ? n : (uint64_t)got;
+            const uint64_t wn = raw ? n : got;
             // blocks take their file offsets in order; the write itself can
             // overlap the next blocks' writes
             uint64_t at = 0;
@@ -147,7 +220,7 @@ int write_deflated(int fd, const Pieces &pc, const std::string &tmp_path, uint64
                 at = pos;
                 pos += wn;
                 turn = b + 1;
-                table[b] = wn | (raw ? kZipRawBit : 0);
+                table[b] = wn | (raw ? kZipRawBit : (uint64_t)code << kZipPlaneShift);
             }
             cv.notify_all();
             const int e = write_all(fd, w, wn, (off_t)at);
@@ -202,17 +275,20 @@ int parse_zip(const uint8_t *hdr, uint64_t size, ImageFile *f, uint64_t *head_of
     f->zoff.resize(nb);
     f->zlen.resize(nb);
     f->zraw.resize(nb);
+    f->zplanes.resize(nb);
     uint64_t pos = *head_off + h64[0];
     for (uint64_t b = 0; b < nb; b++) {
         const uint64_t want = std::min<uint64_t>(h32[1], h64[1] - b * h32[1]);
         const bool raw = table[b] & kZipRawBit;
-        const uint64_t len = table[b] & ~kZipRawBit;
-        if ((raw && len != want) || (!raw && (len == 0 || len > compressBound((uLong)want))) || len > size ||
-            pos > size - len)
+        const unsigned code = (unsigned)((table[b] >> kZipPlaneShift) & 3);
+        const uint64_t len = table[b] & kZipSizeMask;
+        if ((raw && (len != want || code != 0)) || (!raw && (len == 0 || len > compressBound((uLong)want))) ||
+            code > 2 || len > size || pos > size - len)
             return set_error(CKPT_E_INVAL, "bad block %llu of the compressed container", (unsigned long long)b);
         f->zoff[b] = pos;
         f->zlen[b] = len;
         f->zraw[b] = raw;
+        f->zplanes[b] = (uint8_t)kZipPlanes[code];
         pos += len;
     }
     if (pos != size)
@@ -431,7 +507,7 @@ int ckpt::load_image_file(ckpt_ctx *ctx, ImageFile *f, ckpt_image **out)
         int rc = CKPT_OK;
         std::string msg;
         auto worker = [&] {
-            std::vector<uint8_t> cbuf;
+            std::vector<uint8_t> cbuf, planes;
             for (;;) {
                 const uint64_t b = next.fetch_add(1);
                 if (b >= nb)
@@ -444,10 +520,17 @@ int ckpt::load_image_file(ckpt_ctx *ctx, ImageFile *f, ckpt_image **out)
                 } else {
                     cbuf.resize(f->zlen[b]);
                     r = read_all(f->fd, cbuf.data(), f->zlen[b], f->zoff[b], f->path.c_str());
+                    // planes are inflated aside and joined into place
+                    const unsigned w = f->zplanes[b];
+                    if (w > 1)
+                        planes.resize(want);
+                    uint8_t *to = w > 1 ? planes.data() : dst;
                     uLongf got = (uLongf)want;
-                    if (r == CKPT_OK && (uncompress(dst, &got, cbuf.data(), (uLong)f->zlen[b]) != Z_OK || got != want))
+                    if (r == CKPT_OK && (uncompress(to, &got, cbuf.data(), (uLong)f->zlen[b]) != Z_OK || got != want))
                         r = set_error(CKPT_E_INVAL, "block %llu of %s does not inflate to %llu bytes",
                                       (unsigned long long)b, f->path.c_str(), (unsigned long long)want);
+                    if (r == CKPT_OK && w > 1)
+                        join_planes(planes.data(), want, w, dst);
                 }
                 if (r != CKPT_OK) {
                     std::lock_guard<std::mutex> lk(mu);

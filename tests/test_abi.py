@@ -206,8 +206,12 @@ def test_compressed_container_is_checked_before_any_device_work(ck, tmp_path):
     assert rc(_zip_container(data_bytes=(1 << 64) - 1, table=(raw | 5,))) == ck.CKPT_E_INVAL   # DATA too large
     # the block count must be ceil(DATA / block)
     assert rc(_zip_container(data_bytes=5 << 20, table=(raw | (4 << 20),))) == ck.CKPT_E_INVAL
-    # a raw block must hold exactly its share of DATA
+    # a raw block must hold exactly its share of DATA, and carry no plane code
     assert rc(_zip_container(data_bytes=100, table=(raw | 99,), blocks=bytes(99))) == ck.CKPT_E_INVAL
+    assert rc(_zip_container(data_bytes=100, table=(raw | (1 << 61) | 100,), blocks=bytes(100))) == \
+        ck.CKPT_E_INVAL
+    # plane code 3 is not defined
+    assert rc(_zip_container(data_bytes=100, table=((3 << 61) | 20,), blocks=bytes(20))) == ck.CKPT_E_INVAL
     # the table may not run past the end of the file
     assert rc(_zip_container(data_bytes=100, table=(raw | 100,), blocks=bytes(60))) == ck.CKPT_E_INVAL
     # nor leave bytes after the last block

@@ -80,9 +80,17 @@ def test_file_errors(tmp_path):
     ctx.close()
 
 
+def join_planes(piece, w):
+    """Inverse of the byte-plane split: plane j holds byte j of every w-byte
+    element; trailing bytes follow as they are."""
+    m = len(piece) // w
+    a = np.frombuffer(piece, np.uint8)
+    return a[:w * m].reshape(w, m).T.reshape(-1).tobytes() + piece[w * m:]
+
+
 def read_container(path):
     """The compressed container read with Python's zlib, following the
-    documented layout: returns (head + inflated DATA, raw flags per block)."""
+    documented layout: returns (head + DATA, (raw, element width) per block)."""
     with open(path, "rb") as f:
         b = f.read()
     assert b[:8] == b"CKPTZIP1"
@@ -95,30 +103,32 @@ def read_container(path):
     pos += head_bytes
     raws = []
     for i, t in enumerate(table):
-        raw, n = bool(t >> 63), t & ((1 << 63) - 1)
+        raw, code, n = bool(t >> 63), (t >> 61) & 3, t & ((1 << 61) - 1)
+        w = (1, 2, 4)[code]
         chunk = b[pos:pos + n]
         piece = chunk if raw else zlib.decompress(chunk)
         assert len(piece) == min(block, data_bytes - i * block)
-        out += piece
-        raws.append(raw)
+        out += join_planes(piece, w) if w > 1 else piece
+        raws.append((raw, w))
         pos += n
     assert pos == len(b)
     return bytes(out), raws
 
 
-def compressible_allocs(sizes, seed):
-    """bf16 values drawn from N(0, 1) (model-weight-like bytes), as uint8 views."""
+def compressible_allocs(sizes, seed, dtype=torch.bfloat16):
+    """Values drawn from N(0, 1) in dtype (model-weight-like bytes), as uint8 views."""
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
+    w = torch.empty(0, dtype=dtype).element_size()
     out = []
     for s in sizes:
-        t = torch.randn((s + 1) // 2, generator=g, device="cuda").to(torch.bfloat16)
+        t = torch.randn((s + w - 1) // w, generator=g, device="cuda").to(dtype)
         out.append(t.view(torch.uint8)[:s].clone())
     torch.cuda.synchronize()
     return out
 
 
-@pytest.mark.parametrize("kind", ["random", "bf16"])
+@pytest.mark.parametrize("kind", ["random", "bf16", "f32"])
 def test_deflate_container_roundtrip(tmp_path, kind):
     """The compressed file holds the serialized image block by block (checked
     with an independent zlib reader), reads back section by section, and
@@ -128,7 +138,7 @@ def test_deflate_container_roundtrip(tmp_path, kind):
     if kind == "random":
         tensors = random_allocs(sizes, seed=33, zero=(1,))
     else:
-        tensors = compressible_allocs(sizes, seed=34)
+        tensors = compressible_allocs(sizes, seed=34, dtype=torch.bfloat16 if kind == "bf16" else torch.float32)
     ctx = K.Context(chunk_bytes=C)
     for t in tensors:
         ctx.register(t)
@@ -136,14 +146,16 @@ def test_deflate_container_roundtrip(tmp_path, kind):
     path = str(tmp_path / "img.ckptz")
     n = img.write_file(path, deflate=True)
     assert n == os.path.getsize(path) and not os.path.exists(path + ".partial")
-    blob, raws = read_container(path)
+    blob, forms = read_container(path)
     assert blob == img.serialize()
     ser = img.info()["serialized_bytes"]
-    assert len(raws) == -(-ser // (4 << 20)) and len(raws) >= 3
+    assert len(forms) == -(-ser // (4 << 20)) and len(forms) >= 3
     if kind == "random":
-        assert all(raws)
+        assert all(raw for raw, _ in forms)
     else:
-        assert not any(raws) and n < 0.9 * len(blob)
+        # 2- or 4-byte values: that many byte planes, entropy-coded
+        width = 2 if kind == "bf16" else 4
+        assert all(not raw and w == width for raw, w in forms[:-1]) and n < 0.9 * len(blob)
     back = K.Image.read_file(path, ctx)
     for key in ("allocs", "crc", "flags", "data", "addrs"):
         assert np.array_equal(getattr(back, key), getattr(img, key)), key
