@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=60, help="measured requests per rate")
     ap.add_argument("--serving-rates", default="10,50,150", help="arrival rates (req/s)")
     ap.add_argument("--serving-shapes", type=int, default=24)
+    ap.add_argument("--serving-warmup", type=int, default=10, help="warm-up requests per rate")
     ap.add_argument("--sections-only", action="store_true",
                     help="diagnostic runs (e.g. counter passes): skip the headline at-scale steps and "
                          "print only the --only sections as JSON")
@@ -619,9 +620,13 @@ def bench_serving(K, synth, torch, args):
             img.close()
             del refs[id(img)]
 
+    fail_status = {}   # status -> count of failed requests (per rate)
+
     def done(tk_entry, r):
         _, si, img_used = tk_entry
         inflight[si] -= 1
+        if r["status"] not in (K.CKPT_OK, K.CKPT_E_CORRUPT):
+            fail_status[r["status"]] = fail_status.get(r["status"], 0) + 1
         if img_used is not None:
             e = refs[id(img_used)]
             e[1] -= 1
@@ -679,11 +684,14 @@ def bench_serving(K, synth, torch, args):
         return srv.stats()
 
     for lam in [float(x) for x in args.serving_rates.split(",")]:
-        st = run_rate(lam, args.serving_requests + 10, 10)
+        fail_status.clear()
+        st = run_rate(lam, args.serving_requests + args.serving_warmup, args.serving_warmup)
         res = {"p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
                "mean_ms": round(st["mean_ms"], 2), "completed": st["completed"], "failed": st["failed"],
                "gbps": round(st["gbps"], 2), "makespan_s": round(st["makespan_s"], 3),
                "steps": st["steps"], "max_concurrent": st["max_concurrent"]}
+        if fail_status:
+            res["failed_by_status"] = {K.STATUS_NAMES.get(k, str(k)): v for k, v in fail_status.items()}
         out["rates"]["%g" % lam] = res
         log("serving rate %g/s: %s" % (lam, res))
     out["managed_prefetch_to_host"] = bool(prefetch_ok)
