@@ -405,7 +405,9 @@ int ckpt_hook_install(ckpt_ctx *ctx, uint32_t flags);
  * order, all work queued on that stream before the free.  As with any
  * stream-ordered caching allocator, a caller that used the memory on other
  * streams synchronizes them before freeing.  When the device runs out of
- * memory the cached blocks are released and the allocation tried again. */
+ * memory the cached blocks are released and the allocation tried again, and
+ * then, if it still fails, a block of the request's own size (rounded to 2
+ * MiB or the granularity) is tried; such a block is released when freed. */
 void *ckpt_hook_malloc(size_t bytes, int device, void *stream);
 
 /* Unregister memory from ckpt_hook_malloc and free it: without

@@ -33,6 +33,7 @@ struct Block {
     uintptr_t stream = 0;    // the stream it was first allocated for
     bool vmm = false;        // address-stable mapping of the context
     bool live = false;       // registered and handed out
+    bool keep = true;        // cached when freed (false: a block of its request's size, released)
 };
 std::unordered_map<uint64_t, Block> g_blocks;                            // every cache block
 std::map<std::pair<uintptr_t, uint64_t>, std::vector<uint64_t>> g_bins;   // free ones
@@ -129,17 +130,25 @@ void *cache_malloc(size_t bytes, void *stream)
         g_hits++;
     }
     if (!p) {
+        Block b;
+        b.cap = cap;
+        b.stream = (uintptr_t)stream;
+        b.vmm = vmm;
         int rc = new_block(cap, vmm, &p);
         if (rc != CKPT_OK && g_cached_blocks) {
             trim_locked();   // out of memory: give the cached blocks back and try once more
             rc = new_block(cap, vmm, &p);
         }
-        if (rc != CKPT_OK)
-            return nullptr;
-        Block b;
-        b.cap = cap;
-        b.stream = (uintptr_t)stream;
-        b.vmm = vmm;
+        if (rc != CKPT_OK) {
+            // the class rounds up by as much as a quarter: a request that fits
+            // only at its own size gets a block of that size, released when freed
+            const uint64_t unit = vmm ? g_gran : uint64_t(2) << 20;
+            const uint64_t exact = (bytes + unit - 1) / unit * unit;
+            if (exact >= cap || new_block(exact, vmm, &p) != CKPT_OK)
+                return nullptr;
+            b.cap = exact;
+            b.keep = false;
+        }
         g_blocks[p] = b;
     }
     uint64_t id = 0;
@@ -169,6 +178,17 @@ bool cache_free(uint64_t p)
             g_blocks.erase(it);
             return true;
         }
+    }
+    if (!b.keep) {
+        // not a class size: released at once (after the device's queued work)
+        DeviceGuard dg(g_ctx->cfg.device);
+        (void)hipDeviceSynchronize();
+        if (b.vmm)
+            vmm_block_unmap(g_ctx, p);
+        else
+            (void)hipFree((void *)(uintptr_t)p);
+        g_blocks.erase(it);
+        return true;
     }
     b.live = false;
     g_bins[std::make_pair(b.stream, b.cap)].push_back(p);

@@ -15,7 +15,11 @@ mode runs in a fresh process and prints one JSON line:
                 allocation of its class, registered with its own size; with
                 "stable", an image taken before a free is restored at its
                 addresses while the freed block sits in the cache;
-  save_cache PATH  "save" with the cache on.
+  save_cache PATH  "save" with the cache on;
+  oom           the cache under memory pressure: a cached block is released
+                when a new allocation does not fit beside it, and a request
+                that fits only at its own size (not at its class size) gets
+                a block of that size, released again when freed.
 """
 import hashlib
 import json
@@ -141,6 +145,46 @@ def run_cache(mode):
     print(json.dumps(out), flush=True)
 
 
+def class_bytes(b):
+    """The cache's size class of a request (four classes per power of two)."""
+    if b <= 512:
+        return 512
+    e = (b - 1).bit_length() - 1
+    step = 1 << (e - 2)
+    return -(-b // step) * step
+
+
+def run_oom():
+    from paper_2008_10596_amd import hook
+    ctx = K.Context(chunk_bytes=C)
+    hook.install(ctx, cache=True)
+    free, _ = torch.cuda.mem_get_info()
+    out = {"free": free}
+    a = torch.empty(int(0.4 * free), dtype=torch.uint8, device="cuda")
+    del a
+    torch.cuda.synchronize()
+    out["cached_a"] = hook.cache_stats()["blocks"]
+    b = torch.empty(int(0.7 * free), dtype=torch.uint8, device="cuda")   # does not fit beside a's block
+    out["after_b"] = {"cached": hook.cache_stats()["blocks"], "live": ctx.live_count()}
+    del b
+    torch.cuda.synchronize()
+    out["trimmed_b"] = hook.trim() > 0
+    # a request below the free memory whose class is above it
+    free2, _ = torch.cuda.mem_get_info()
+    r = free2 - (4 << 30)
+    while r > free2 // 2 and class_bytes(r) <= free2:
+        r -= 1 << 30
+    out["exact_case"] = class_bytes(r) > free2
+    if out["exact_case"]:
+        d = torch.empty(r, dtype=torch.uint8, device="cuda")
+        out["after_d"] = {"cached": hook.cache_stats()["blocks"], "live": ctx.live_count()}
+        del d
+        torch.cuda.synchronize()
+    out["end"] = {"cached": hook.cache_stats()["blocks"], "live": ctx.live_count()}
+    out["failures"] = hook.stats()["failures"]
+    print(json.dumps(out), flush=True)
+
+
 def run_save(path, cache=False):
     from paper_2008_10596_amd import hook
     ctx = K.Context(chunk_bytes=C)
@@ -173,5 +217,7 @@ if __name__ == "__main__":
         run_save(sys.argv[2], cache=True)
     elif mode == "cache":
         run_cache(sys.argv[2])
+    elif mode == "oom":
+        run_oom()
     else:
         run_restore(sys.argv[2])

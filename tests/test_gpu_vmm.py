@@ -397,3 +397,18 @@ def test_hook_cache_address_stable_restart(tmp_path):
     assert b["rc"] == K.CKPT_OK and b["n_bad"] == 0
     assert b["addrs"] == a["addrs"]
     assert b["sha"] == a["sha"]
+
+
+def test_hook_cache_under_memory_pressure():
+    """A cached block gives way to an allocation that does not fit beside it;
+    a request that fits only at its own size is served at that size and not
+    cached.  Nothing fails."""
+    out = _child("tests.hook_child", "oom")
+    log("memory pressure: %s" % out)
+    assert out["cached_a"] == 1
+    assert out["after_b"] == {"cached": 0, "live": 1}
+    assert out["trimmed_b"]
+    if out["exact_case"]:
+        assert out["after_d"] == {"cached": 0, "live": 1}
+    assert out["end"] == {"cached": 0, "live": 0}
+    assert out["failures"] == 0
