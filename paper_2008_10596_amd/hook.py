@@ -48,7 +48,9 @@ def cache_stats():
 
 
 def trim():
-    """Release every cached block; returns their bytes."""
+    """Release every cached block; returns their bytes.  torch.cuda.empty_cache()
+    does not reach the hook's cache (torch's pluggable allocator passes only
+    allocations and frees), so this is the way to hand the memory back."""
     n = ctypes.c_uint64()
     K._check(K.lib().ckpt_hook_trim(ctypes.byref(n)), "ckpt_hook_trim")
     return n.value
