@@ -12,9 +12,9 @@
  *     allocations made and not yet freed, never the allocator's arena
  *     (Sec. 3.2, "Saving the library-allocated arena"), and handles them in
  *     the order in which they were allocated (Sec. 3.1, "Log-and-replay");
- *   - device (cudaMalloc) and managed (cudaMallocManaged) regions are saved at
- *     checkpoint time and copied back at restart (Sec. 3.2, "restoring the
- *     CUDA library-allocated regions");
+ *   - device (cudaMalloc) and managed (cudaMallocManaged) regions are written
+ *     out when the checkpoint is taken and put back on restart (Sec. 3.2,
+ *     "restoring the CUDA library-allocated regions");
  *   - before copying, the queue of pending GPU work is drained, as CheCUDA's
  *     first step does with a device-wide synchronize (Sec. 2.2).
  * Here the caller mirrors its allocation calls with ckpt_register /
