@@ -253,3 +253,114 @@ def test_restore_rejects_short_serialized_data(oracle):
     r = oracle.checkpoint(allocs, 256)
     with pytest.raises(ValueError):
         oracle.restore([1000], 256, r["crc"], r["flags"], r["serialized"][:-16])
+
+
+# ------------------------------------------- delta restore: its bad-chunk report
+#
+# The overlay of an increment verifies each DIRTY chunk against the
+# increment's CRC and reports failures by global chunk id, exactly as the full
+# restore does.  The cases below have dirty ids that do not start at 0 and a
+# ZERO dirty chunk among them, so a report by position in the id list (or by
+# position in the increment's data) differs from the report by chunk id.
+
+def _delta_case(oracle, seed):
+    rng = np.random.default_rng(seed)
+    C = 256
+    sizes = [1500, 900, 700]                 # chunks 0-5 | 6-9 | 10-12
+    allocs = rand_allocs(rng, sizes)
+    base = oracle.checkpoint(allocs, C)
+    allocs[0][3 * C + 5] ^= 0x40             # chunk 3
+    allocs[1][C:2 * C] = 0                   # chunk 7 becomes ZERO (and DIRTY)
+    allocs[1][3 * C] ^= 1                    # chunk 9, the 132-byte tail of allocation 1
+    allocs[2][2 * C + 10] ^= 0x80            # chunk 12, the 188-byte tail of allocation 2
+    d = oracle.delta(allocs, C, base["crc"])
+    assert list(d["dirty_ids"]) == [3, 7, 9, 12]
+    assert d["flags"][7] & FLAG_ZERO
+    # increment pieces: chunk 3 at [0, 256), chunk 9 at [256, 400), chunk 12 at [400, 592)
+    assert d["delta"].size == 256 + 144 + 192
+    return C, sizes, allocs, base, d
+
+
+def _restore_base(oracle, C, sizes, base, ser=None, crc=None):
+    return oracle.restore(sizes, C, base["crc"] if crc is None else crc, base["flags"],
+                          base["serialized"] if ser is None else ser)
+
+
+def test_delta_restore_clean_overlay(oracle):
+    C, sizes, allocs, base, d = _delta_case(oracle, 20)
+    bufs, bad, _ = _restore_base(oracle, C, sizes, base)
+    assert bad == 0
+    bad, ids = oracle.restore_delta(bufs, sizes, C, d["crc"], d["flags"], d["dirty_ids"], d["delta"])
+    assert bad == 0 and ids.size == 0
+    for a, b in zip(allocs, bufs):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("piece,g,pos", [(0, 3, 17), (1, 9, 256 + 131), (2, 12, 400 + 5)])
+def test_delta_restore_reports_flipped_piece_by_chunk_id(oracle, piece, g, pos):
+    C, sizes, allocs, base, d = _delta_case(oracle, 21)
+    bufs, bad, _ = _restore_base(oracle, C, sizes, base)
+    assert bad == 0
+    data = d["delta"].copy()
+    data[pos] ^= 0x20
+    bad, ids = oracle.restore_delta(bufs, sizes, C, d["crc"], d["flags"], d["dirty_ids"], data)
+    assert bad == 1 and list(ids) == [g]
+    # the flipped byte is still written where the chunk belongs
+    _, cb_, _, _ = oracle.layout(sizes, C)
+    k = int(np.searchsorted(cb_, g, side="right")) - 1
+    at = (g - int(cb_[k])) * C + (pos - [0, 256, 400][piece])
+    assert bufs[k][at] == allocs[k][at] ^ 0x20
+
+
+def test_delta_restore_reports_zero_chunk_crc(oracle):
+    C, sizes, allocs, base, d = _delta_case(oracle, 22)
+    bufs, _, _ = _restore_base(oracle, C, sizes, base)
+    crc = d["crc"].copy()
+    crc[7] ^= 0x1000
+    bad, ids = oracle.restore_delta(bufs, sizes, C, crc, d["flags"], d["dirty_ids"], d["delta"])
+    assert bad == 1 and list(ids) == [7]
+    assert not bufs[1][C:2 * C].any()          # the ZERO chunk is still filled with zeros
+
+
+def test_delta_restore_reports_every_bad_dirty_chunk(oracle):
+    C, sizes, allocs, base, d = _delta_case(oracle, 23)
+    bufs, _, _ = _restore_base(oracle, C, sizes, base)
+    crc = d["crc"] ^ np.uint32(1)              # every chunk's stored CRC is wrong
+    bad, ids = oracle.restore_delta(bufs, sizes, C, crc, d["flags"], d["dirty_ids"], d["delta"])
+    # only the overlaid (DIRTY) chunks are checked in this pass
+    assert bad == 4 and list(ids) == [3, 7, 9, 12]
+
+
+def test_delta_and_base_reports_are_separate_passes(oracle):
+    """A chunk can fail in the base pass, in the overlay, or in both; each pass
+    reports the chunks it checked.  A bad base chunk that the increment
+    overwrites with good data fails the base pass only."""
+    C, sizes, allocs, base, d = _delta_case(oracle, 24)
+    lens = [min(C, s - st) for s in sizes for st in range(0, s, C)]
+    at = [sum(r16(x) for x in lens[:g]) for g in range(len(lens))]   # all base chunks are non-ZERO
+    ser = base["serialized"].copy()
+    for g in (3, 5, 9):                         # 3 and 9 are overlaid, 5 is not
+        ser[at[g] + 7] ^= 0x01
+    data = d["delta"].copy()
+    data[256 + 9] ^= 0x01                       # chunk 9 bad in the overlay too
+    bufs, bad_b, ids_b = _restore_base(oracle, C, sizes, base, ser=ser)
+    assert bad_b == 3 and list(ids_b) == [3, 5, 9]
+    bad_d, ids_d = oracle.restore_delta(bufs, sizes, C, d["crc"], d["flags"], d["dirty_ids"], data)
+    assert bad_d == 1 and list(ids_d) == [9]
+    # chunk 3 was repaired by the overlay; chunk 5 keeps the base's bad byte
+    assert np.array_equal(bufs[0][3 * C:4 * C], allocs[0][3 * C:4 * C])
+    assert bufs[0][5 * C + 7] == allocs[0][5 * C + 7] ^ 0x01
+
+
+def test_delta_restore_many_bad_report_first_64_ascending(oracle):
+    rng = np.random.default_rng(25)
+    C = 16
+    allocs = rand_allocs(rng, [16 * 120])
+    base = oracle.checkpoint(allocs, C)
+    allocs[0][16 * 10:] = rng.integers(0, 256, 16 * 110, dtype=np.uint8)   # chunks 10-119 change
+    d = oracle.delta(allocs, C, base["crc"])
+    assert list(d["dirty_ids"]) == list(range(10, 120))
+    bufs, _, _ = oracle.restore([16 * 120], C, base["crc"], base["flags"], base["serialized"])
+    bad, ids = oracle.restore_delta(bufs, [16 * 120], C, d["crc"] ^ np.uint32(0x10), d["flags"],
+                                    d["dirty_ids"], d["delta"])
+    assert bad == 110 and list(ids) == list(range(10, 74))

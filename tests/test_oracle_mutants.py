@@ -50,6 +50,17 @@ MUTANTS = [
      "        if (!(flags[g] & ORACLE_FLAG_DIRTY) || (flags[g] & ORACLE_FLAG_ZERO))\n            continue;\n        if (dirty_ids)"),
     ("restore_skips_zero_fill", "        memset(dst, 0, len);\n    else", "        ;\n    else"),
     ("restore_never_reports", "        report_bad(rep, g);\n", "        (void)rep;\n"),
+    ("delta_report_uses_list_position",
+     "            piece = delta + s;\n            s += round_up16(len);\n        }\n"
+     "        restore_chunk(dst[k] + c * C, len, flags[g], crc[g], piece, g, &rep);",
+     "            piece = delta + s;\n            s += round_up16(len);\n        }\n"
+     "        restore_chunk(dst[k] + c * C, len, flags[g], crc[g], piece, i - 1, &rep);"),
+    ("delta_pass_never_reports",
+     "            piece = delta + s;\n            s += round_up16(len);\n        }\n"
+     "        restore_chunk(dst[k] + c * C, len, flags[g], crc[g], piece, g, &rep);",
+     "            piece = delta + s;\n            s += round_up16(len);\n        }\n"
+     "        { bad_report unused; memset(&unused, 0, sizeof(unused));\n"
+     "          restore_chunk(dst[k] + c * C, len, flags[g], crc[g], piece, g, &unused); }"),
 ]
 
 
