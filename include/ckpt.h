@@ -259,10 +259,13 @@ int ckpt_checkpoint(ckpt_ctx *ctx, void *stream, int mode, const ckpt_image *bas
 
 /*
  * Refill n_dst destination buffers from an image, and optionally overlay an
- * incremental image (delta) on top.  dst[k] receives allocation k (id order);
- * each dst[k] must be 16-byte aligned device memory of at least the
- * allocation's size (dst_bytes[k] gives the buffer sizes; NULL = assume
- * equal).  Every chunk is written (ZERO chunks as zeros) and its CRC
+ * incremental image (delta) on top.  dst[k] receives allocation k (id order)
+ * and must be 16-byte aligned device memory of exactly the allocation's size.
+ * dst_bytes[k] gives each destination's size, which must equal the
+ * allocation's; dst_bytes NULL declares that every destination has exactly
+ * its allocation's size (a raw device pointer's extent cannot be learned in
+ * general -- a tensor may be carved out of a larger block -- so the caller's
+ * word is taken).  Every chunk is written (ZERO chunks as zeros) and its CRC
  * recomputed on the device and compared with the stored one; a chunk that
  * fails is still written.  The delta's chunks are applied after the base's,
  * each verified against the delta's CRC.  Runs on `stream` and returns when
@@ -272,8 +275,8 @@ int ckpt_checkpoint(ckpt_ctx *ctx, void *stream, int mode, const ckpt_image *bas
  * first (ckpt_image_merge) and dst follows the delta's table.
  *
  * CKPT_E_MISMATCH: n_dst differs from the image's allocation count, a
- *   dst_bytes entry is smaller than its allocation, or the delta's chunk size
- *   or base serial does not match img.
+ *   dst_bytes entry differs from its allocation's size (larger or smaller),
+ *   or the delta's chunk size or base serial does not match img.
  * CKPT_E_INVAL: image without host DATA, misaligned dst.
  * CKPT_E_CORRUPT: some chunk failed; rep (if given) holds the number of
  *   distinct failing chunk ids and the smallest 64, ascending.

@@ -1197,8 +1197,8 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
     std::vector<Row> rows(n);
     for (uint64_t k = 0; k < n; k++) {
         const uint64_t d = (uint64_t)(uintptr_t)dst[k], sz = img->allocs[k].size;
-        if (dst_bytes && dst_bytes[k] < sz)
-            return set_error(CKPT_E_MISMATCH, "dst[%llu] holds %zu of %llu bytes", (unsigned long long)k,
+        if (dst_bytes && dst_bytes[k] != sz)
+            return set_error(CKPT_E_MISMATCH, "dst[%llu] has %zu bytes, the allocation %llu", (unsigned long long)k,
                              dst_bytes[k], (unsigned long long)sz);
         if (d % 16 != 0 || (sz && d == 0))
             return set_error(CKPT_E_INVAL, "dst[%llu] is NULL or not 16-byte aligned", (unsigned long long)k);

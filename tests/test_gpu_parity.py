@@ -11,7 +11,7 @@ import torch
 import synth
 from oracle import oracle as O
 from paper_2008_10596_amd import ckpt as K
-from tests.gpu_common import (FLAG_ZERO, check_full, check_restored, d2h, host, log, random_allocs,
+from tests.gpu_common import (FLAG_ZERO, check_full, check_restored, d2h, host, log, r16, random_allocs,
                               register_all)
 
 pytestmark = pytest.mark.gpu
@@ -341,6 +341,41 @@ def test_restore_errors():
     assert e.value.status == K.CKPT_E_MISMATCH
 
 
+def test_restore_size_rule():
+    """Every destination must have exactly its allocation's size: larger and
+    smaller are refused before anything is written; without sizes (raw
+    addresses, dst_bytes NULL) the caller's word is taken and exactly the
+    allocations' bytes are written."""
+    ctx = K.Context()
+    tensors = random_allocs([10000, 5000], seed=16)
+    register_all(ctx, tensors)
+    img = ctx.checkpoint()
+    for sizes in ([10000, 5001], [10000, 4999], [10016, 5000], [9999, 5000]):
+        dsts = [torch.full((s,), 0x77, dtype=torch.uint8, device="cuda") for s in sizes]
+        with pytest.raises(K.CkptError) as e:
+            ctx.restore(img, dsts)
+        assert e.value.status == K.CKPT_E_MISMATCH, sizes
+        assert all(bool((d == 0x77).all()) for d in dsts), "a refused restore wrote memory"
+    buf = torch.full((20000,), 0x77, dtype=torch.uint8, device="cuda")
+    ptrs = [buf.data_ptr(), buf.data_ptr() + 10240]
+    for db in ([10000, 5008], [10000, 4992], [10240, 5000]):
+        with pytest.raises(K.CkptError) as e:
+            ctx.restore(img, ptrs, dst_bytes=db)
+        assert e.value.status == K.CKPT_E_MISMATCH, db
+    assert bool((buf == 0x77).all())
+    rc, rep = ctx.restore(img, ptrs, dst_bytes=[10000, 5000])
+    assert rc == K.CKPT_OK, rep
+    buf.fill_(0x77)
+    rc, rep = ctx.restore(img, ptrs)          # dst_bytes NULL
+    assert rc == K.CKPT_OK, rep
+    h = host(buf)
+    assert np.array_equal(h[:10000], host(tensors[0]))
+    assert np.array_equal(h[10240:15240], host(tensors[1]))
+    assert (h[10000:10240] == 0x77).all() and (h[15240:] == 0x77).all(), "bytes past an allocation written"
+    img.close()
+    ctx.close()
+
+
 def test_corruption_is_reported_exactly():
     C = 1024
     sizes = [C * 9 + 40, C * 4]
@@ -373,6 +408,90 @@ def test_corruption_is_reported_exactly():
     rc, rep = ctx.restore(img, dsts)
     assert rc == K.CKPT_E_CORRUPT and rep["n_bad"] == img.info()["n_chunks"]
     assert rep["ids"] == list(range(min(64, img.info()["n_chunks"])))
+
+
+def _flip(t, i, bit):
+    t[i:i + 1] = torch.bitwise_xor(t[i:i + 1], bit)
+
+
+def test_delta_corruption_is_the_union_of_both_passes():
+    """Restore of a base plus an increment: a chunk is bad when it fails the
+    base pass or the overlay, and is counted once.  Every case is compared
+    with the union of the oracle's two reports, and the restored memory with
+    the oracle's."""
+    C = 1024
+    sizes = [C * 9 + 40, C * 4, C * 3 + 500]   # chunks 0-9 (9: 40 B) | 10-13 | 14-17 (17: 500 B)
+    tensors = random_allocs(sizes, seed=18)
+    ctx = K.Context(chunk_bytes=C)
+    register_all(ctx, tensors)
+    base = ctx.checkpoint()
+    h0 = [host(t) for t in tensors]
+    ref_base = O.checkpoint(h0, C)
+    check_full(base, ref_base, tensors, C)
+    _flip(tensors[0], 2 * C + 5, 0x40)           # chunk 2
+    _flip(tensors[0], 9 * C + 3, 0x01)           # chunk 9, a tail
+    tensors[1][:C] = 0                           # chunk 10 becomes ZERO
+    _flip(tensors[2], 3 * C + 100, 0x80)         # chunk 17, a tail
+    d = ctx.checkpoint(mode=K.CKPT_INCREMENTAL, base=base)
+    h1 = [host(t) for t in tensors]
+    dref = O.delta(h1, C, ref_base["crc"])
+    assert list(dref["dirty_ids"]) == [2, 9, 10, 17]
+    assert np.array_equal(d.dirty_ids, dref["dirty_ids"]) and np.array_equal(d.data, dref["delta"])
+    assert np.array_equal(d.crc, dref["crc"]) and np.array_equal(d.flags, dref["flags"])
+    lens = [min(C, s - st) for s in sizes for st in range(0, s, C)]
+    b_at = [sum(r16(x) for x in lens[:g]) for g in range(len(lens))]   # no ZERO chunk in the base
+    d_at = {2: 0, 9: 1024, 17: 1072}                                   # increment pieces
+    # (name, base data bytes to flip, base CRCs to change, increment data bytes, increment CRCs)
+    cases = [
+        ("increment byte", [], [], [d_at[9] + 7], []),
+        ("increment CRC of the ZERO chunk", [], [], [], [10]),
+        ("same chunk in both passes", [b_at[9] + 1], [], [d_at[9] + 2], []),
+        ("base repaired by the increment, base only, increment only",
+         [b_at[2] + 9, b_at[5]], [], [], [17]),
+        ("every increment CRC", [], [], [], [2, 9, 10, 17]),
+        ("base CRC and increment byte", [], [12, 13], [d_at[17] + 499], []),
+    ]
+    for name, bdata, bcrc, ddata, dcrc in cases:
+        ser_b, crc_b = ref_base["serialized"].copy(), ref_base["crc"].copy()
+        ser_d, crc_d = dref["delta"].copy(), dref["crc"].copy()
+        for i in bdata:
+            base.data[i] ^= 0x08
+            ser_b[i] ^= 0x08
+        for g in bcrc:
+            base.crc[g] ^= 0x100
+            crc_b[g] ^= 0x100
+        for i in ddata:
+            d.data[i] ^= 0x08
+            ser_d[i] ^= 0x08
+        for g in dcrc:
+            d.crc[g] ^= 0x100
+            crc_d[g] ^= 0x100
+        bufs, _, ids_b = O.restore(sizes, C, crc_b, ref_base["flags"], ser_b)
+        _, ids_d = O.restore_delta(bufs, sizes, C, crc_d, dref["flags"], dref["dirty_ids"], ser_d)
+        want = sorted(set(int(x) for x in ids_b) | set(int(x) for x in ids_d))
+        dsts = [torch.full((s,), 0x5A, dtype=torch.uint8, device="cuda") for s in sizes]
+        rc, rep = ctx.restore(base, dsts, delta=d)
+        log("%s: gpu %s, oracle base %s + increment %s" % (name, rep, list(ids_b), list(ids_d)))
+        assert want, name
+        assert rc == K.CKPT_E_CORRUPT, name
+        assert rep["n_bad"] == len(want) and rep["ids"] == want, (name, rep, want)
+        for k, dst in enumerate(dsts):
+            assert np.array_equal(host(dst), bufs[k]), (name, k)
+        for i in bdata:
+            base.data[i] ^= 0x08
+        for g in bcrc:
+            base.crc[g] ^= 0x100
+        for i in ddata:
+            d.data[i] ^= 0x08
+        for g in dcrc:
+            d.crc[g] ^= 0x100
+    dsts = [torch.empty_like(t) for t in tensors]
+    rc, rep = ctx.restore(base, dsts, delta=d)
+    assert rc == K.CKPT_OK, rep
+    check_restored(dsts, tensors)
+    d.close()
+    base.close()
+    ctx.close()
 
 
 @pytest.mark.parametrize("C", [1024, 4096, 65536])
@@ -612,3 +731,57 @@ def test_batch_no_drain_dense_views():
         assert np.array_equal(img.crc, ref["crc"]) and np.array_equal(img.flags, ref["flags"])
         p, nb = img.dense_ptr
         assert np.array_equal(d2h(p, nb), ref["dense"])
+
+
+# ---------------------------------------------------------------- autotuner
+
+def test_autotuner_shapes_match_the_oracle(tmp_path):
+    """autotune.tune on a small uneven batch; then, for every chunk size it
+    swept, a batch run in that size's best (waves, block) shape -- the global
+    best among them -- must give each context the oracle's image.  A second
+    tune call with the same cache file reuses the result."""
+    from paper_2008_10596_amd import autotune
+    rng = np.random.default_rng(31)
+    sets, hosts = [], []
+    for i in range(9):
+        n = int(rng.integers(1, 7))
+        sizes = [int(x) for x in rng.integers(0, 700000, n)]
+        t = random_allocs(sizes, seed=300 + i)
+        for k, a in enumerate(t):                 # some zero 64 KiB cells
+            for cell in range(0, a.numel(), 65536):
+                if rng.random() < 0.2:
+                    a[cell:cell + 65536] = 0
+        sets.append(t)
+        hosts.append([host(a) for a in t])
+    alloc_sets = [[(a.data_ptr(), a.numel()) for a in t] for t in sets]
+    chunks = (4096, 16384, 65536, 262144)
+    cache = str(tmp_path / "tune.json")
+    res = autotune.tune(alloc_sets, chunks=chunks, waves=(1, 2, 4), blocks=(256, 1024), reps=1,
+                        cache_path=cache)
+    assert not res["cached"]
+    assert {t["chunk_bytes"] for t in res["trials"]} == set(chunks)
+    best_per_c = {}
+    for t in res["trials"]:
+        c = t["chunk_bytes"]
+        if c not in best_per_c or t["gbps"] > best_per_c[c]["gbps"]:
+            best_per_c[c] = t
+    assert res["best"] in best_per_c.values()
+    for C, t in sorted(best_per_c.items()):
+        W, B = t["waves_per_chunk"], t["block_threads"]
+        log("C=%d: best W=%d block=%d (%.0f GB/s)" % (C, W, B, t["gbps"]))
+        members = []
+        for tens in sets:
+            c = K.Context(chunk_bytes=C)
+            register_all(c, tens)
+            members.append(c)
+        leader = K.Context(chunk_bytes=C, waves_per_chunk=W, block_threads=B)
+        imgs = K.checkpoint_batch([leader] + members)
+        for i, tens in enumerate(sets):
+            check_full(imgs[i + 1], O.checkpoint(hosts[i], C), tens, C)
+        for im in imgs:
+            im.close()
+        for c in members + [leader]:
+            c.close()
+    again = autotune.tune(alloc_sets, chunks=chunks, waves=(1, 2, 4), blocks=(256, 1024), reps=1,
+                          cache_path=cache)
+    assert again["cached"] and again["best"] == res["best"]

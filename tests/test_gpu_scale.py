@@ -138,9 +138,12 @@ def test_incremental_at_scale_exact_dirty_set(C):
     free()
 
 
-def test_batched_at_scale_sampled():
+@pytest.mark.parametrize("C,W,B", [(4096, 1, 0), (65536, 4, 1024)])
+def test_batched_at_scale_sampled(C, W, B):
+    """The batched workload in the bench's default shape (4 KiB chunks) and in
+    the autotuner's best shape of the recorded runs (64 KiB chunks, four waves
+    per chunk, 1024-thread workgroups)."""
     spec = synth.batched()
-    C = 4096
     sets, k = [], 0
     for cs in spec:
         allocs = []
@@ -160,7 +163,7 @@ def test_batched_at_scale_sampled():
         for t in allocs:
             c.register(t)
         members.append(c)
-    leader = K.Context(chunk_bytes=C)
+    leader = K.Context(chunk_bytes=C, waves_per_chunk=W, block_threads=B)
     imgs = K.checkpoint_batch([leader] + members)
     for i in sample(len(sets), 12, 4):
         alone = members[i].checkpoint()
