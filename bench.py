@@ -52,10 +52,12 @@ def parse():
     ap.add_argument("--drain-steps", type=int, default=5)
     ap.add_argument("--only", default="", help="comma list of extra sections to run "
                     "(drain,restore_at,incremental,batched,serving,hook); default: all")
-    ap.add_argument("--serving-requests", type=int, default=60, help="measured requests per rate")
-    ap.add_argument("--serving-rates", default="10,50,150", help="arrival rates (req/s)")
+    ap.add_argument("--serving-requests", type=int, default=200, help="measured requests per rate")
+    ap.add_argument("--serving-rates", default="10,25,50,100,150,200", help="arrival rates (req/s)")
     ap.add_argument("--serving-shapes", type=int, default=24)
-    ap.add_argument("--serving-warmup", type=int, default=10, help="warm-up requests per rate")
+    ap.add_argument("--serving-warmup", type=int, default=20, help="warm-up requests per rate")
+    ap.add_argument("--serving-host-budget-gib", type=float, default=0,
+                    help="server host budget for images (0: the library's default)")
     ap.add_argument("--sections-only", action="store_true",
                     help="diagnostic runs (e.g. counter passes): skip the headline at-scale steps and "
                          "print only the --only sections as JSON")
@@ -600,9 +602,11 @@ def bench_serving(K, synth, torch, args):
                     prefetch_ok = rc == 0
                 if rc != 0:
                     return
-    srv = K.Server(chunk_bytes=4096, staging_budget=64 * GiB, step_bytes=256 * MiB, max_active=16)
-    out = {"workload": "serving (reduced): %d request shapes, %.1f GiB of allocations, 1-256 allocations "
-                       "per request, 25%% managed" % (len(shapes), total / GiB),
+    srv = K.Server(chunk_bytes=4096, staging_budget=64 * GiB, step_bytes=256 * MiB, max_active=16,
+                   host_budget=int(args.serving_host_budget_gib * GiB))
+    out = {"workload": "serving: %d request shapes reused, %.1f GiB of allocations, 1-256 allocations "
+                       "per request, 25%% managed; %d warm-up + %d measured requests per rate"
+                       % (len(shapes), total / GiB, args.serving_warmup, args.serving_requests),
            "rates": {}}
     # An image stays open while a restore that reads it is in flight, and a
     # shape's managed pages are only moved host-side while none of its
@@ -620,13 +624,16 @@ def bench_serving(K, synth, torch, args):
             img.close()
             del refs[id(img)]
 
-    fail_status = {}   # status -> count of failed requests (per rate)
+    fail_status = {}   # status -> count of failed measured requests (per rate)
+    warm_failed = {}   # the same for the warm-up requests
+    offered = []       # algorithmic bytes of each measured request
 
     def done(tk_entry, r):
-        _, si, img_used = tk_entry
+        _, si, img_used, warm = tk_entry
         inflight[si] -= 1
         if r["status"] not in (K.CKPT_OK, K.CKPT_E_CORRUPT):
-            fail_status[r["status"]] = fail_status.get(r["status"], 0) + 1
+            tally = warm_failed if warm else fail_status
+            tally[r["status"]] = tally.get(r["status"], 0) + 1
         if img_used is not None:
             e = refs[id(img_used)]
             e[1] -= 1
@@ -661,15 +668,20 @@ def bench_serving(K, synth, torch, args):
             si = int(which[i])
             sh = shapes[si]
             img = sh["image"]
+            warm_req = i < warm
             if ops[i] or img is None:
                 if inflight[si] == 0:
                     move_host(sh)
                 tk = srv.submit(K.CKPT_REQ_CHECKPOINT, sh["ptrs"], sizes=sh["sizes"], kinds=sh["kinds"])
-                tickets.append((tk, si, None))
+                tickets.append((tk, si, None, warm_req))
+                if not warm_req:
+                    offered.append(2 * sh["bytes"])
             else:
                 refs[id(img)][1] += 1
                 tk = srv.submit(K.CKPT_REQ_RESTORE, sh["dst"], image=img)
-                tickets.append((tk, si, img))
+                tickets.append((tk, si, img, warm_req))
+                if not warm_req:
+                    offered.append(sh["bytes"] + img.info()["serialized_bytes"])
             inflight[si] += 1
             still = []
             for entry in tickets:
@@ -683,17 +695,31 @@ def bench_serving(K, synth, torch, args):
             done(entry, srv.wait(entry[0]))
         return srv.stats()
 
+    knee = None
     for lam in [float(x) for x in args.serving_rates.split(",")]:
         fail_status.clear()
+        warm_failed.clear()
+        offered.clear()
         st = run_rate(lam, args.serving_requests + args.serving_warmup, args.serving_warmup)
+        # offered load: the measured requests' algorithmic bytes at the arrival rate
+        offered_gbps = statistics.mean(offered) * lam / 1e9 if offered else 0.0
         res = {"p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
                "mean_ms": round(st["mean_ms"], 2), "completed": st["completed"], "failed": st["failed"],
-               "gbps": round(st["gbps"], 2), "makespan_s": round(st["makespan_s"], 3),
-               "steps": st["steps"], "max_concurrent": st["max_concurrent"]}
-        if fail_status:
-            res["failed_by_status"] = {K.STATUS_NAMES.get(k, str(k)): v for k, v in fail_status.items()}
+               "gbps": round(st["gbps"], 2), "offered_gbps": round(offered_gbps, 2),
+               "makespan_s": round(st["makespan_s"], 3), "steps": st["steps"],
+               "max_concurrent": st["max_concurrent"], "host_waits": st["host_waits"],
+               "host_peak_gib": round(st["host_peak"] / GiB, 2),
+               "warmup_failed": sum(warm_failed.values())}
+        if fail_status or warm_failed:
+            res["failed_by_status"] = {K.STATUS_NAMES.get(k, str(k)): v
+                                       for k, v in list(fail_status.items()) + list(warm_failed.items())}
+        if knee is None and offered_gbps and st["gbps"] < 0.9 * offered_gbps:
+            knee = lam
         out["rates"]["%g" % lam] = res
         log("serving rate %g/s: %s" % (lam, res))
+    out["knee_rate"] = knee
+    out["knee_rule"] = "lowest rate whose aggregate GB/s falls below 0.9 x the offered GB/s"
+    out["failed_total"] = sum(r["failed"] + r["warmup_failed"] for r in out["rates"].values())
     out["managed_prefetch_to_host"] = bool(prefetch_ok)
     srv.close()
     for e in list(refs.values()):

@@ -533,7 +533,16 @@ int ckpt_checkpoint_batch(ckpt_ctx *const *ctxs, size_t n, void *stream, ckpt_im
  * arrival order while fewer than max_active are admitted and the request's
  * device staging fits in what is left of staging_budget (checkpoint: dense
  * image + drain buffer + per-chunk arrays, about 2x its bytes; restore: the
- * serialized bytes + per-chunk arrays).  Every step is one kernel launch that
+ * serialized bytes + per-chunk arrays).  A checkpoint also needs pinned host
+ * memory for its image: it is admitted only while the pinned bytes the library
+ * has handed out (to images anywhere in the process, the caller's included),
+ * plus the most that the admitted checkpoints' images can take, plus its own
+ * stay within host_budget.  A checkpoint waiting for host memory lets the
+ * restores behind it pass (they need none, and finishing them is what lets a
+ * caller release older images); requests behind a request whose device
+ * staging does not fit wait.  So a backlog queues instead of failing, and
+ * images the caller keeps hold back later checkpoints until it frees them.
+ * Every step is one kernel launch that
  * processes up to step_bytes of each admitted request, checkpoints and
  * restores together, so requests overlap on the device; a request that
  * arrives during a step joins the next one.  Results are the same as a
@@ -557,6 +566,8 @@ typedef struct ckpt_server_config {
     uint32_t block_threads;    /* 0 selects 256                                         */
     uint32_t lane_pieces;      /* as in ckpt_config; 0 selects 1 (then replicated
                                   tables and 1024-thread workgroups)                    */
+    uint64_t host_budget;      /* pinned host bytes for images (see above); 0 selects
+                                  64 GiB                                                */
 } ckpt_server_config;
 
 typedef struct ckpt_request {
@@ -592,6 +603,8 @@ typedef struct ckpt_stats {
     uint64_t steps;             /* step launches                                        */
     uint32_t max_concurrent;    /* most requests admitted at once                       */
     uint32_t pad;
+    uint64_t host_waits;        /* checkpoints held back for host memory                */
+    uint64_t host_peak;         /* most pinned bytes held plus reserved at an admission */
 } ckpt_stats;
 
 /* CKPT_E_INVAL: bad config; CKPT_E_NOMEM: the staging budget could not be
@@ -599,7 +612,8 @@ typedef struct ckpt_stats {
 int ckpt_server_create(const ckpt_server_config *cfg, ckpt_server **out);
 
 /* Queue a request; *ticket identifies it.  CKPT_E_INVAL / CKPT_E_MISMATCH on
- * a malformed request (checked here), CKPT_E_BUDGET if it can never fit. */
+ * a malformed request (checked here), CKPT_E_BUDGET if it can never fit the
+ * staging budget or (checkpoint) the host budget. */
 int ckpt_server_submit(ckpt_server *srv, const ckpt_request *req, uint64_t *ticket);
 
 /* CKPT_E_AGAIN until the request is done; then fills *out (out may be NULL to
@@ -620,6 +634,14 @@ void ckpt_server_destroy(ckpt_server *srv);
 /* --------------------------------------------------------------- timing */
 
 int ckpt_last_timing(const ckpt_ctx *ctx, ckpt_timing *out);
+
+/* Pinned host memory of the process-wide pool the library draws images' host
+ * sections and its staging from: *live (may be NULL) = bytes handed out and
+ * not yet returned (images the caller holds included), *cached (may be NULL)
+ * = freed buffers kept for reuse (at most 32 GiB, given back first when a
+ * pinned allocation fails).  A server's host budget counts the live bytes.
+ * Host memory only; no device is touched. */
+int ckpt_host_memory(uint64_t *live, uint64_t *cached);
 
 /* ------------------------------------------------------------ diagnostics */
 

@@ -90,7 +90,8 @@ class ckpt_server_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("chunk_bytes", ctypes.c_uint32),
                 ("staging_budget", ctypes.c_uint64), ("step_bytes", ctypes.c_uint64),
                 ("max_active", ctypes.c_uint32), ("aux_threads", ctypes.c_uint32),
-                ("block_threads", ctypes.c_uint32), ("lane_pieces", ctypes.c_uint32)]
+                ("block_threads", ctypes.c_uint32), ("lane_pieces", ctypes.c_uint32),
+                ("host_budget", ctypes.c_uint64)]
 
 
 class ckpt_request(ctypes.Structure):
@@ -112,7 +113,7 @@ class ckpt_stats(ctypes.Structure):
                 ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
                 ("makespan_s", ctypes.c_double), ("gbps", ctypes.c_double),
                 ("steps", ctypes.c_uint64), ("max_concurrent", ctypes.c_uint32),
-                ("pad", ctypes.c_uint32)]
+                ("pad", ctypes.c_uint32), ("host_waits", ctypes.c_uint64), ("host_peak", ctypes.c_uint64)]
 
 
 _vp = ctypes.c_void_p
@@ -151,6 +152,7 @@ SIGNATURES = [
     ("ckpt_restore_file_at", ctypes.c_int, [_vp, _vp, ctypes.c_char_p, ctypes.POINTER(_vp),
                                              ctypes.POINTER(ckpt_verify_report), ctypes.POINTER(_vp)]),
     ("ckpt_last_timing", ctypes.c_int, [_vp, ctypes.POINTER(ckpt_timing)]),
+    ("ckpt_host_memory", ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
     ("ckpt_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("ckpt_last_hip_error", ctypes.c_int, []),
     ("ckpt_last_error", ctypes.c_char_p, []),
@@ -457,6 +459,13 @@ def merge(base, *deltas):
     return img
 
 
+def host_memory():
+    """(live, cached) pinned bytes of the library's pool (ckpt_host_memory)."""
+    live, cached = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().ckpt_host_memory(ctypes.byref(live), ctypes.byref(cached)), "ckpt_host_memory")
+    return live.value, cached.value
+
+
 def checkpoint_batch(ctxs, stream=None):
     n = len(ctxs)
     hs = (_vp * n)(*[c.handle for c in ctxs])
@@ -471,9 +480,9 @@ class Server:
     """Continuous-batching server (ckpt_server_*)."""
 
     def __init__(self, device=0, chunk_bytes=4096, staging_budget=0, step_bytes=0, max_active=0,
-                 aux_threads=0, block_threads=0, lane_pieces=0):
+                 aux_threads=0, block_threads=0, lane_pieces=0, host_budget=0):
         cfg = ckpt_server_config(device, chunk_bytes, staging_budget, step_bytes, max_active, aux_threads,
-                                 block_threads, lane_pieces)
+                                 block_threads, lane_pieces, host_budget)
         h = _vp()
         _check(lib().ckpt_server_create(ctypes.byref(cfg), ctypes.byref(h)), "ckpt_server_create")
         self.handle = h.value

@@ -64,6 +64,11 @@ struct PinnedBuf {
     void release();
 };
 
+// Pinned host bytes handed out by the process-wide pool (images' sections,
+// staging) and not yet returned; the buffers it keeps for reuse are not
+// counted.
+uint64_t pinned_live_bytes();
+
 // Completion of an asynchronous copy into host memory, shared by the images
 // it fills.
 struct MetaEvent {

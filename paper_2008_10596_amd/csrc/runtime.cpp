@@ -103,10 +103,11 @@ public:
         {
             std::lock_guard<std::mutex> lk(mu_);
             auto it = free_.lower_bound(bytes);
-            if (it != free_.end() && it->first <= 2 * bytes + (64u << 20)) {
+            if (it != free_.end() && it->first <= bytes + bytes / 4 + (4u << 20)) {
                 void *p = it->second;
                 *cap_out = it->first;
                 cached_ -= it->first;
+                live_ += it->first;
                 free_.erase(it);
                 return p;
             }
@@ -119,6 +120,8 @@ public:
                 return nullptr;
         }
         *cap_out = rounded;
+        std::lock_guard<std::mutex> lk(mu_);
+        live_ += rounded;
         return p;
     }
     void put(void *p, size_t cap)
@@ -128,7 +131,18 @@ public:
         std::lock_guard<std::mutex> lk(mu_);
         free_.emplace(cap, p);
         cached_ += cap;
+        live_ -= cap;
         trim_locked(kMaxCached);
+    }
+    uint64_t live()
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        return live_;
+    }
+    uint64_t cached()
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        return cached_;
     }
     void trim(size_t keep)
     {
@@ -146,10 +160,13 @@ private:
             free_.erase(it);
         }
     }
-    static constexpr size_t kMaxCached = size_t(96) << 30;
+    // freed buffers kept for reuse; pinning gigabytes again costs far more
+    // than keeping them, but they are host memory nobody else can use
+    static constexpr size_t kMaxCached = size_t(32) << 30;
     std::mutex mu_;
     std::multimap<size_t, void *> free_;
     size_t cached_ = 0;
+    size_t live_ = 0;   // handed out and not yet returned
 };
 
 PinnedPool &pinned_pool()
@@ -172,6 +189,17 @@ uint64_t next_serial()
 
 uint64_t ru16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
 }  // namespace
+
+uint64_t ckpt::pinned_live_bytes() { return pinned_pool().live(); }
+
+extern "C" int ckpt_host_memory(uint64_t *live, uint64_t *cached)
+{
+    if (live)
+        *live = pinned_pool().live();
+    if (cached)
+        *cached = pinned_pool().cached();
+    return CKPT_OK;
+}
 
 // Digest of an image's CRC section: FNV-1a over little-endian 64-bit words
 // (the last word zero-padded).  Computed when asked for, not per checkpoint.

@@ -11,7 +11,9 @@
 // an auxiliary worker (checkpoint: selection scan, gather, copy of the
 // serialized image to pinned host memory; restore: the verification count)
 // while later steps keep the GPU busy with the other requests.  Requests that
-// arrive meanwhile join at the next step.
+// arrive meanwhile join at the next step.  Admission (admission.h) counts the
+// device staging of every request and, for a checkpoint, the pinned host
+// memory of the image it will produce.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -25,6 +27,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "admission.h"
 #include "ckpt.h"
 #include "ckpt_runtime.h"
 
@@ -40,54 +43,25 @@ double ms_between(Clock::time_point a, Clock::time_point b)
     return std::chrono::duration<double, std::milli>(b - a).count();
 }
 
-// First-fit allocator over one device block.
+// The staging budget: one device block, carved by an ArenaMap.
 class Arena {
 public:
     int init(uint64_t bytes)
     {
         CKPT_TRY(mem_.ensure(bytes));
-        free_.clear();
-        free_[0] = bytes;
-        size_ = bytes;
+        map_.reset(bytes);
         return CKPT_OK;
     }
-    void release() { mem_.release(); free_.clear(); }
-    uint64_t size() const { return size_; }
-    // offset of a block of `bytes`, or UINT64_MAX when no hole is large enough
-    uint64_t alloc(uint64_t bytes)
-    {
-        for (auto it = free_.begin(); it != free_.end(); ++it)
-            if (it->second >= bytes) {
-                const uint64_t off = it->first, rest = it->second - bytes;
-                free_.erase(it);
-                if (rest)
-                    free_[off + bytes] = rest;
-                return off;
-            }
-        return UINT64_MAX;
-    }
-    void free(uint64_t off, uint64_t bytes)
-    {
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
+    void release() { mem_.release(); map_.reset(0); }
+    uint64_t size() const { return map_.size(); }
+    uint64_t alloc(uint64_t bytes) { return map_.alloc(bytes); }
+    void free(uint64_t off, uint64_t bytes) { map_.free(off, bytes); }
+    const ArenaMap &map() const { return map_; }
     uint8_t *base() const { return (uint8_t *)mem_.p; }
 
 private:
     DevBuf mem_;
-    std::map<uint64_t, uint64_t> free_;
-    uint64_t size_ = 0;
+    ArenaMap map_;
 };
 
 enum State { kQueued, kPrep, kStepping, kFinish, kDone };
@@ -99,6 +73,8 @@ struct Req {
     const ckpt_image *image = nullptr;
     std::vector<uint64_t> off, cb;  // host layout, n + 1 each
     uint64_t N = 0, data_bytes = 0, live = 0, ser_bytes = 0;
+    uint64_t host_charge = 0;       // checkpoint: most pinned bytes its image can take
+    bool waited_host = false;       // was held back for host memory
     // device block and its parts
     uint64_t block_off = 0, block_bytes = 0;
     uint64_t *d_addr = nullptr, *d_size = nullptr, *d_off = nullptr, *d_cb = nullptr, *d_soff = nullptr;
@@ -135,7 +111,8 @@ struct ckpt_server {
     std::vector<Req *> active;                    // admitted, not done
     std::unordered_map<uint64_t, Req *> by_ticket;
     std::deque<Task> aux_tasks;
-    uint32_t n_active = 0;
+    AdmitState adm;                               // slots and host reservations
+    bool host_blocked = false;                    // a checkpoint waits for host memory
 
     // step buffers (owned by the step thread)
     PinnedBuf h_step;
@@ -146,6 +123,7 @@ struct ckpt_server {
 
     // statistics
     uint64_t submitted = 0, completed = 0, failed = 0, bytes = 0, steps = 0;
+    uint64_t host_waits = 0, host_peak = 0;
     uint32_t max_concurrent = 0;
     std::vector<double> lat_ms;
     bool have_first = false;
@@ -285,6 +263,18 @@ int finish_request(ckpt_server *sv, Req *r, hipStream_t s, PinnedBuf &up)
         return CKPT_OK;
     }
     std::unique_ptr<ckpt_image> img(new ckpt_image());
+    // On an error return, wait for the copies already queued into the image's
+    // pinned buffers before they go back to the pool (declared after img, so
+    // it runs before img is destroyed).
+    struct SyncOnError {
+        hipStream_t s;
+        bool ok = false;
+        ~SyncOnError()
+        {
+            if (!ok)
+                (void)hipStreamSynchronize(s);
+        }
+    } sync_on_error{s};
     img->device = sv->cfg.device;
     img->mode = CKPT_FULL;
     img->C = C;
@@ -341,6 +331,7 @@ int finish_request(ckpt_server *sv, Req *r, hipStream_t s, PinnedBuf &up)
         REQ_HIP(r, hipMemcpyAsync(img->flags, r->d_flags, N, hipMemcpyDeviceToHost, s));
     }
     REQ_HIP(r, hipStreamSynchronize(s));
+    sync_on_error.ok = true;
     static std::atomic<uint64_t> serial{0};
     img->serial = (0x5E5Full << 48) | (++serial);
     r->result.image = img.release();
@@ -351,14 +342,16 @@ int finish_request(ckpt_server *sv, Req *r, hipStream_t s, PinnedBuf &up)
 
 void complete(ckpt_server *sv, Req *r)
 {
-    // caller holds sv->mu
+    // caller holds sv->mu; no device work of r is queued any more
     r->t_done = Clock::now();
     r->state = kDone;
     r->result.latency_ms = ms_between(r->t_submit, r->t_done);
     r->result.queue_ms = ms_between(r->t_submit, r->t_admit);
     sv->arena.free(r->block_off, r->block_bytes);
+    if (r->op == CKPT_REQ_CHECKPOINT)
+        sv->adm.host_reserved -= r->host_charge;
     sv->active.erase(std::remove(sv->active.begin(), sv->active.end(), r), sv->active.end());
-    sv->n_active--;
+    sv->adm.n_active--;
     sv->t_last = r->t_done;
     if (r->result.status == CKPT_OK || r->result.status == CKPT_E_CORRUPT) {
         sv->completed++;
@@ -371,22 +364,49 @@ void complete(ckpt_server *sv, Req *r)
     sv->cv_step.notify_all();
 }
 
-// Admit queued requests in arrival order while a slot and staging are free.
+AdmitInfo admit_info(const Req *r)
+{
+    AdmitInfo a;
+    a.checkpoint = r->op == CKPT_REQ_CHECKPOINT;
+    a.dev_bytes = r->block_bytes;
+    a.host_bytes = r->host_charge;
+    return a;
+}
+
+// Admit queued requests (admission.h): in arrival order while a slot and
+// staging are free; restores may pass a checkpoint that waits for host memory.
 void admit_locked(ckpt_server *sv)
 {
-    while (!sv->queue.empty() && sv->n_active < sv->cfg.max_active) {
-        Req *r = sv->queue.front();
+    for (;;) {
+        const uint64_t host_live = pinned_live_bytes();
+        bool blocked = false;
+        const long i = next_admissible(sv->queue, sv->adm, sv->arena.map(), host_live, admit_info, &blocked);
+        sv->host_blocked = blocked;
+        if (blocked)
+            for (Req *q : sv->queue)
+                if (q->op == CKPT_REQ_CHECKPOINT && !q->waited_host) {
+                    q->waited_host = true;   // the first queued checkpoint is the one held back
+                    sv->host_waits++;
+                    break;
+                }
+        if (i < 0)
+            return;
+        Req *r = sv->queue[(size_t)i];
         const uint64_t off = sv->arena.alloc(r->block_bytes);
         if (off == UINT64_MAX)
-            break;   // the head waits for memory; later requests do not pass it
-        sv->queue.pop_front();
+            return;   // cannot happen: next_admissible checked that it fits
+        sv->queue.erase(sv->queue.begin() + i);
         r->block_off = off;
         plan_block(r, sv->arena.base() + off);
         r->state = kPrep;
         r->t_admit = Clock::now();
+        if (r->op == CKPT_REQ_CHECKPOINT) {
+            sv->adm.host_reserved += r->host_charge;
+            sv->host_peak = std::max(sv->host_peak, host_live + sv->adm.host_reserved);
+        }
         sv->active.push_back(r);
-        sv->n_active++;
-        sv->max_concurrent = std::max(sv->max_concurrent, sv->n_active);
+        sv->adm.n_active++;
+        sv->max_concurrent = std::max(sv->max_concurrent, sv->adm.n_active);
         sv->aux_tasks.push_back({r, true});
         sv->cv_aux.notify_one();
     }
@@ -410,6 +430,8 @@ void aux_loop(ckpt_server *sv)
         }
         Req *r = t.req;
         int rc = t.prep ? prep_request(sv, r, s, up) : finish_request(sv, r, s, up);
+        if (rc != CKPT_OK)
+            (void)hipStreamSynchronize(s);   // nothing of r may still be queued when its block is freed
         std::lock_guard<std::mutex> lk(sv->mu);
         if (rc != CKPT_OK || !t.prep) {
             if (rc != CKPT_OK && r->result.status == CKPT_OK)
@@ -428,11 +450,83 @@ void aux_loop(ckpt_server *sv)
 }
 
 // Build and run one step over every stepping request.
+// Where a step row came from: request, allocation, first chunk, chunk count.
+struct RowSrc {
+    size_t req;
+    size_t k;
+    uint64_t c, nc;
+};
+
+bool inside(uint64_t p, uint64_t bytes, uint64_t lo, uint64_t lo_bytes)
+{
+    return p >= lo && bytes <= lo_bytes && p - lo <= lo_bytes - bytes;
+}
+
+// Checks every address a step will hand the row kernel against the request
+// it belongs to: each stepping request's block lies in the arena, is not part
+// of a free hole and overlaps no other stepping request's block; every row's
+// per-chunk arrays, dense image, staging and source or destination ranges lie
+// inside that request's block or its allocations.  A violation is reported as
+// an error instead of being launched.
+int audit_step(const ckpt_server *sv, const std::vector<Req *> &reqs, const std::vector<StepRow> &rows,
+               const std::vector<RowSrc> &src)
+{
+    const uint32_t C = sv->cfg.chunk_bytes;
+    const uint64_t base = (uint64_t)sv->arena.base(), asz = sv->arena.size();
+    std::vector<std::pair<uint64_t, uint64_t>> blocks;
+    for (const Req *r : reqs) {
+        if (r->state != kStepping || !inside(r->block_off, r->block_bytes, 0, asz))
+            return set_error(CKPT_E_INVAL, "step audit: request %llu is not stepping in the arena",
+                             (unsigned long long)r->ticket);
+        for (const auto &h : sv->arena.map().holes())
+            if (h.first < r->block_off + r->block_bytes && r->block_off < h.first + h.second)
+                return set_error(CKPT_E_INVAL, "step audit: request %llu's block is free in the arena",
+                                 (unsigned long long)r->ticket);
+        blocks.emplace_back(r->block_off, r->block_bytes);
+    }
+    std::sort(blocks.begin(), blocks.end());
+    for (size_t i = 1; i < blocks.size(); i++)
+        if (blocks[i - 1].first + blocks[i - 1].second > blocks[i].first)
+            return set_error(CKPT_E_INVAL, "step audit: two stepping requests share arena bytes");
+    for (size_t j = 0; j < rows.size(); j++) {
+        const StepRow &row = rows[j];
+        const RowSrc &rs = src[j];
+        const Req *r = reqs[rs.req];
+        const uint64_t blk = base + r->block_off, N = r->N;
+        const Row &al = r->rows[rs.k];
+        const uint64_t start = (rs.c - r->cb[rs.k]) * C;
+        const uint64_t span = std::min<uint64_t>(row.rem, rs.nc * C);   // data bytes of the row's chunks
+        bool ok = inside((uint64_t)r->d_crc, 4 * N, blk, r->block_bytes) &&
+                  inside((uint64_t)r->d_flags, N, blk, r->block_bytes) && rs.c + rs.nc <= N &&
+                  rs.c >= r->cb[rs.k] && rs.c + rs.nc <= r->cb[rs.k + 1] && row.rem == al.size - start &&
+                  row.crc == (uint64_t)(r->d_crc + rs.c) && row.flags == (uint64_t)(r->d_flags + rs.c);
+        if (ok && row.mode == kModePack) {
+            ok = r->op == CKPT_REQ_CHECKPOINT && inside(row.src, span, al.ptr, al.size) &&
+                 inside((uint64_t)r->d_dense, r->data_bytes, blk, r->block_bytes) &&
+                 inside(row.dst, ru16(span), (uint64_t)r->d_dense, r->data_bytes);
+        } else if (ok) {
+            ok = row.mode == kModeRestore && r->op == CKPT_REQ_RESTORE && inside(row.dst, span, al.ptr, al.size) &&
+                 row.src == (uint64_t)r->d_staging &&
+                 inside((uint64_t)r->d_staging, std::max<uint64_t>(r->ser_bytes, 1), blk, r->block_bytes) &&
+                 inside((uint64_t)r->d_soff, 8 * N, blk, r->block_bytes) &&
+                 inside((uint64_t)r->d_bad, N, blk, r->block_bytes) && row.soff == (uint64_t)(r->d_soff + rs.c) &&
+                 row.bad == (uint64_t)(r->d_bad + rs.c) && row.bad_count == (uint64_t)&r->d_plan->bad_count &&
+                 inside((uint64_t)r->d_plan, sizeof(DevPlan), blk, r->block_bytes);
+        }
+        if (!ok)
+            return set_error(CKPT_E_INVAL, "step audit: row %zu of request %llu (allocation %zu, chunks %llu+%llu) "
+                             "points outside its request", j, (unsigned long long)r->ticket, rs.k,
+                             (unsigned long long)rs.c, (unsigned long long)rs.nc);
+    }
+    return CKPT_OK;
+}
+
 int run_step(ckpt_server *sv, const std::vector<Req *> &reqs, std::vector<uint64_t> &ends)
 {
     const uint32_t C = sv->cfg.chunk_bytes;
     const uint64_t q = std::max<uint64_t>(1, sv->cfg.step_bytes / C);
     std::vector<StepRow> rows;
+    std::vector<RowSrc> row_src;
     std::vector<uint64_t> row_cb;
     uint64_t items = 0;
     ends.resize(reqs.size());
@@ -466,6 +560,7 @@ int run_step(ckpt_server *sv, const std::vector<Req *> &reqs, std::vector<uint64
                 row.bad_count = (uint64_t)&r->d_plan->bad_count;
             }
             rows.push_back(row);
+            row_src.push_back({i, k, c, c1 - c});
             row_cb.push_back(items);
             items += c1 - c;
             c = c1;
@@ -473,6 +568,12 @@ int run_step(ckpt_server *sv, const std::vector<Req *> &reqs, std::vector<uint64
     }
     if (!items)
         return CKPT_OK;
+    {
+        // the step thread reads the arena's holes while aux threads may
+        // free other requests' blocks
+        std::lock_guard<std::mutex> lk(sv->mu);
+        CKPT_TRY(audit_step(sv, reqs, rows, row_src));
+    }
     const uint64_t nr = rows.size();
     row_cb.push_back(items);
     const size_t bytes = sizeof(DevPlan) + nr * sizeof(StepRow) + (nr + 1) * 8;
@@ -522,12 +623,19 @@ void step_loop(ckpt_server *sv)
                         reqs.push_back(r);
                 if (sv->stop || !reqs.empty())
                     break;
-                sv->cv_step.wait(lk);
+                // host memory is released by whoever frees an image: poll
+                // while a checkpoint waits for it
+                if (sv->host_blocked)
+                    sv->cv_step.wait_for(lk, std::chrono::milliseconds(1));
+                else
+                    sv->cv_step.wait(lk);
             }
             if (sv->stop)
                 break;
         }
         int rc = run_step(sv, reqs, ends);
+        if (rc != CKPT_OK)
+            (void)hipStreamSynchronize(sv->step_stream);
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->steps++;
         for (size_t i = 0; i < reqs.size(); i++) {
@@ -569,6 +677,8 @@ extern "C" int ckpt_server_create(const ckpt_server_config *cfg_in, ckpt_server 
         cfg.step_bytes = uint64_t(256) << 20;
     if (cfg.max_active == 0)
         cfg.max_active = 16;
+    if (cfg.host_budget == 0)
+        cfg.host_budget = uint64_t(64) << 30;
     if (cfg.lane_pieces == 0)
         cfg.lane_pieces = 1;
     if (cfg.block_threads == 0)
@@ -592,6 +702,8 @@ extern "C" int ckpt_server_create(const ckpt_server_config *cfg_in, ckpt_server 
     DeviceGuard g(cfg.device);
     auto *sv = new ckpt_server();
     sv->cfg = cfg;
+    sv->adm.max_active = cfg.max_active;
+    sv->adm.host_budget = cfg.host_budget;
     auto fail = [&](int rc) {
         ckpt_server_destroy(sv);
         return rc;
@@ -676,6 +788,16 @@ extern "C" int ckpt_server_submit(ckpt_server *sv, const ckpt_request *req, uint
     if (r->block_bytes > sv->arena.size())
         return set_error(CKPT_E_BUDGET, "request needs %llu B of staging, the budget is %llu B",
                          (unsigned long long)r->block_bytes, (unsigned long long)sv->arena.size());
+    if (r->op == CKPT_REQ_CHECKPOINT) {
+        // the image's DATA (at most the dense bytes) and CRC/flag block, as
+        // the pinned pool may hand them out: rounded up to 2 MiB, or a reused
+        // buffer up to a quarter and 4 MiB larger
+        const uint64_t meta = 5 * r->N;
+        r->host_charge = r->data_bytes + r->data_bytes / 4 + meta + meta / 4 + (uint64_t(8) << 20) + 64;
+        if (r->host_charge > sv->cfg.host_budget)
+            return set_error(CKPT_E_BUDGET, "the image may need %llu B of pinned memory, the host budget is %llu B",
+                             (unsigned long long)r->host_charge, (unsigned long long)sv->cfg.host_budget);
+    }
     r->result.op = r->op;
     std::lock_guard<std::mutex> lk(sv->mu);
     r->ticket = sv->next_ticket++;
@@ -739,6 +861,8 @@ extern "C" int ckpt_server_stats(const ckpt_server *csv, ckpt_stats *out)
     out->bytes = sv->bytes;
     out->steps = sv->steps;
     out->max_concurrent = sv->max_concurrent;
+    out->host_waits = sv->host_waits;
+    out->host_peak = sv->host_peak;
     std::vector<double> v = sv->lat_ms;
     if (!v.empty()) {
         std::sort(v.begin(), v.end());
@@ -769,7 +893,9 @@ extern "C" int ckpt_server_reset_stats(ckpt_server *sv)
         return set_error(CKPT_E_INVAL, "server is NULL");
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->submitted = sv->completed = sv->failed = sv->bytes = sv->steps = 0;
-    sv->max_concurrent = sv->n_active;
+    sv->max_concurrent = sv->adm.n_active;
+    sv->host_waits = 0;
+    sv->host_peak = 0;
     sv->lat_ms.clear();
     sv->have_first = false;
     return CKPT_OK;
@@ -788,7 +914,7 @@ extern "C" void ckpt_server_destroy(ckpt_server *sv)
         }
         sv->queue.clear();
         if (sv->step_thread.joinable())
-            sv->cv_done.wait(lk, [&] { return sv->n_active == 0; });
+            sv->cv_done.wait(lk, [&] { return sv->adm.n_active == 0; });
         sv->stop = true;
         sv->cv_step.notify_all();
         sv->cv_aux.notify_all();

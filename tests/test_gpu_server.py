@@ -168,3 +168,73 @@ def test_managed_allocations_checkpoint_and_restore():
         torch.cuda.synchronize()
         for p in ptrs:
             managed_free(p)
+
+
+def test_server_host_budget_queues_checkpoints():
+    """A checkpoint is admitted only while the pinned bytes handed out (images
+    the caller holds included) plus the admitted checkpoints' charges plus its
+    own stay within the host budget.  With room for two images: A and B run,
+    C waits while their images are held, a restore R behind C passes it, and
+    C and D run once A's and B's images are freed.  Every image equals the
+    oracle's."""
+    import gc
+    import time
+    MiB = 1 << 20
+    reqs = [random_allocs([16 * MiB] * 4, seed=700 + i) for i in range(4)]      # A, B, C, D
+    hosts = [[host(b) for b in bufs] for bufs in reqs]
+    ctx = K.Context(chunk_bytes=C)
+    small = random_allocs([300000, 5000], seed=710)
+    for b in small:
+        ctx.register(b)
+    rimg = ctx.checkpoint()                                   # the image R restores from
+    srv = K.Server(chunk_bytes=C, staging_budget=1 << 30, aux_threads=1, host_budget=1 << 40)
+    srv.wait(srv.submit(K.CKPT_REQ_CHECKPOINT, small))["image"].close()   # server buffers warm
+    srv.close()
+    gc.collect()
+    gc.disable()
+    try:
+        data = 64 * MiB
+        N = data // C
+        charge = data + data // 4 + 5 * N + (5 * N) // 4 + 8 * MiB + 64
+        base, _ = K.host_memory()
+        budget = base + 2 * charge + 4 * MiB + 8 * MiB       # two charges, server buffers, slack
+        log("host memory: live %d B before; charge %d B; budget %d B" % (base, charge, budget))
+        srv = K.Server(chunk_bytes=C, staging_budget=1 << 30, aux_threads=1, host_budget=budget)
+        dsts = [torch.full_like(b, 0x77) for b in small]
+        ta = srv.submit(K.CKPT_REQ_CHECKPOINT, reqs[0])
+        tb = srv.submit(K.CKPT_REQ_CHECKPOINT, reqs[1])
+        tc = srv.submit(K.CKPT_REQ_CHECKPOINT, reqs[2])
+        tr = srv.submit(K.CKPT_REQ_RESTORE, dsts, image=rimg)
+        td = srv.submit(K.CKPT_REQ_CHECKPOINT, reqs[3])
+        ra, rb = srv.wait(ta), srv.wait(tb)
+        assert ra["status"] == K.CKPT_OK and rb["status"] == K.CKPT_OK
+        rr = srv.wait(tr)                                     # passes the waiting checkpoint
+        assert rr["status"] == K.CKPT_OK
+        check_restored(dsts, small)
+        time.sleep(0.3)
+        assert srv.poll(tc) is None, "C ran while A's and B's images were held"
+        assert srv.poll(td) is None
+        st = srv.stats()
+        log("held: %s" % st)
+        assert st["host_waits"] >= 1 and st["host_peak"] <= budget
+        ra["image"].close()
+        rb["image"].close()
+        rc_, rd = srv.wait(tc), srv.wait(td)
+        assert rc_["status"] == K.CKPT_OK and rd["status"] == K.CKPT_OK
+        for i, r in enumerate((ra, rb, rc_, rd)):
+            if i >= 2:
+                check_full(r["image"], O.checkpoint(hosts[i], C), reqs[i], C, ids=[1, 2, 3, 4])
+                r["image"].close()
+        assert srv.stats()["failed"] == 0
+        srv.close()
+        # a checkpoint that can never fit the host budget is refused at submit
+        # (its device staging fits)
+        srv = K.Server(chunk_bytes=C, staging_budget=1 << 30, host_budget=8 * MiB)
+        with pytest.raises(K.CkptError) as e:
+            srv.submit(K.CKPT_REQ_CHECKPOINT, reqs[0][:1])
+        assert e.value.status == K.CKPT_E_BUDGET
+        srv.close()
+    finally:
+        gc.enable()
+    rimg.close()
+    ctx.close()
