@@ -423,6 +423,67 @@ def bench_restore_at(K, torch, tensors, sizes, C, stream, reps=3):
     return out
 
 
+def hbm_ceilings(torch, nbytes, reps=3):
+    """Plain read, write and copy kernels (libckpt_probe.so, not on the path)
+    swept over pieces per lane in flight, workgroups per CU and load/store
+    hints: the most this GPU moves for each kind of traffic.  read and write
+    touch nbytes; copy reads nbytes / 2 and writes nbytes / 2."""
+    import ctypes
+    from paper_2008_10596_amd import build as B
+    if not os.path.exists(B.PROBE_LIB):
+        raise RuntimeError("libckpt_probe.so is not built")
+    lib = ctypes.CDLL(B.PROBE_LIB)
+    lib.probe_launch.restype = ctypes.c_int
+    lib.probe_launch.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a.fill_(3)
+    b.fill_(5)
+    sink = torch.zeros(4, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    half = nbytes // 2 // 16 * 16
+    table, best = [], {}
+    for kind, name in ((0, "read"), (1, "write"), (2, "copy")):
+        for loads in (4, 8, 16):
+            for per_cu in (1, 2):
+                for nt in (0, 1):
+                    if kind == 0:
+                        args = (a.data_ptr(), sink.data_ptr(), nbytes)
+                    elif kind == 1:
+                        args = (None, b.data_ptr(), nbytes)
+                    else:
+                        args = (a.data_ptr(), a.data_ptr() + half, half)
+                    def launch():
+                        rc = lib.probe_launch(kind, args[0], args[1], args[2], loads, nt, cus * per_cu, 1024,
+                                              ctypes.c_void_p(stream.cuda_stream))
+                        if rc != 0:
+                            raise RuntimeError("probe_launch: %d" % rc)
+                    launch()
+                    ms = []
+                    for _ in range(reps):
+                        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        e0.record()
+                        launch()
+                        e1.record()
+                        e1.synchronize()
+                        ms.append(e0.elapsed_time(e1))
+                    m = statistics.median(ms)
+                    moved = nbytes if kind != 2 else 2 * half
+                    row = {"kind": name, "loads_per_lane": loads, "wgs_per_cu": per_cu, "nontemporal": nt,
+                           "ms": round(m, 4), "gbps": round(moved / (m * 1e-3) / 1e9, 1)}
+                    table.append(row)
+                    if name not in best or row["gbps"] > best[name]["gbps"]:
+                        best[name] = row
+    del a, b, sink
+    torch.cuda.empty_cache()
+    return {"best": {k: dict(v, frac=round(v["gbps"] * 1e9 / HBM_PEAK, 4)) for k, v in best.items()},
+            "bytes_moved": nbytes, "workgroup_threads": 1024,
+            "sweep": [[r["kind"], r["loads_per_lane"], r["wgs_per_cu"], r["nontemporal"], r["gbps"]] for r in table],
+            "sweep_columns": ["kind", "loads_per_lane", "wgs_per_cu", "nontemporal", "gbps"]}
+
+
 def copy_reference(torch, nbytes, reps=5):
     """A plain device-to-device copy (torch copy_, i.e. the runtime's own copy)
     of nbytes into a fresh buffer, timed with events on the current stream:
@@ -843,6 +904,8 @@ def main():
     log("device-wide drain mode: %.3f ms per step" % ms_wide)
     copy_ref = copy_reference(torch, int((8 << 30) * args.scale))
     log("copy reference: %s" % copy_ref)
+    ceilings = hbm_ceilings(torch, int((16 << 30) * args.scale) // 16 * 16)
+    log("hbm ceilings: %s" % ceilings["best"])
     if args.copy_probe:
         a = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
         b = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
@@ -866,7 +929,8 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4), "traffic": None,
                      "kernel": "k_chunks<pack>", "algorithmic_bytes_per_launch": alg,
                      "kernel_ms": round(pack_avg, 4),
-                     "copy_reference": dict(copy_ref, pack_vs_copy=round(achieved / 1e9 / copy_ref["gbps"], 4))},
+                     "copy_reference": dict(copy_ref, pack_vs_copy=round(achieved / 1e9 / copy_ref["gbps"], 4)),
+                     "ceilings": ceilings},
     }
     prof = profiled_traffic()
     if prof is not None and prof[1] == alg:

@@ -129,7 +129,14 @@ typedef struct ckpt_config {
                                   per CU; lane_pieces 1 only); 0 selects 2 when
                                   lane_pieces is 1, else 1.  block_threads 0 then
                                   selects 1024 (replicated) or 256 (compact)          */
-    uint32_t pad;
+    uint32_t segment_mib;      /* a full checkpoint's drain (gather, then copy to the
+                                  host) and a restore's refill (copy to the device,
+                                  then scatter) go in segments of about this many MiB,
+                                  so that the device work of one segment overlaps the
+                                  host-link copy of another and at most four segments
+                                  are staged on the device; 0 selects 256;
+                                  0xFFFFFFFF: one pass (the whole serialized image is
+                                  staged)                                              */
 } ckpt_config;
 
 /* One row of an image's allocation table (section CKPT_SEC_ALLOCS). */
@@ -191,10 +198,12 @@ typedef struct ckpt_timing {
                              replayed graph, the whole graph (upload, scan, map,
                              pack) and layout_ms is 0                              */
     float select_ms;      /* flag scan / compaction                                */
-    float gather_ms;      /* gather of selected chunks                             */
-    float d2h_ms;         /* device-to-host copy of data + metadata                */
-    float h2d_ms;         /* restore: host-to-device copy                          */
-    float scatter_ms;     /* restore: scatter + verify kernel(s)                   */
+    float gather_ms;      /* gather of selected chunks, summed over the segments    */
+    float d2h_ms;         /* device-to-host copy of data + metadata: from the start
+                             of the first copy to the end of the last            */
+    float h2d_ms;         /* restore: host-to-device copy, first start to last end */
+    float scatter_ms;     /* restore: scatter + verify kernel(s), summed over the
+                             segments                                              */
     float total_ms;       /* whole call                                            */
     float pad;
     uint64_t pack_read_bytes;     /* algorithmic bytes read by the pack kernel      */

@@ -12,6 +12,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libckpt.so")
+# plain HBM read/write/copy kernels for the bench's ceilings (not on the path)
+PROBE_LIB = os.path.join(HERE, "libckpt_probe.so")
+PROBE_SOURCE = "probe.hip"
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["kernels.hip", "crc_tables.cpp", "runtime.cpp", "server.cpp", "vmm.cpp", "hook.cpp", "sink.cpp"]
@@ -36,9 +39,11 @@ def _run(cmd):
 
 
 def build(verbose=False, extra=()):
-    """Compile every source and link libckpt.so.  Always recompiles."""
+    """Compile every source (in parallel) and link libckpt.so and
+    libckpt_probe.so.  Always recompiles."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD_DIR, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         if not os.path.exists(path):
@@ -49,14 +54,25 @@ def build(verbose=False, extra=()):
             cmd[1:1] = ["-x", "hip"]
         if verbose:
             print(" ".join(cmd))
-        _run(cmd)
+        cmds.append(cmd)
         objs.append(obj)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0") or 0) or (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for f in [ex.submit(_run, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread", "-lz"]
     if verbose:
         print(" ".join(cmd))
     _run(cmd)
     os.replace(tmp, LIB)
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [HIPCC, "--offload-arch=" + ARCH, *COMMON, *extra, "-shared", "-o", tmp,
+           os.path.join(CSRC, PROBE_SOURCE)]
+    if verbose:
+        print(" ".join(cmd))
+    _run(cmd)
+    os.replace(tmp, PROBE_LIB)
     return LIB
 
 

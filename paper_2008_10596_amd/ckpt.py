@@ -52,7 +52,7 @@ class ckpt_config(ctypes.Structure):
                 ("block_threads", ctypes.c_uint32), ("waves_per_chunk", ctypes.c_uint32),
                 ("wgs_per_cu", ctypes.c_uint32), ("lane_pieces", ctypes.c_uint32),
                 ("load_hint", ctypes.c_uint32), ("table_mode", ctypes.c_uint32),
-                ("pad", ctypes.c_uint32)]
+                ("segment_mib", ctypes.c_uint32)]
 
 
 class ckpt_alloc_rec(ctypes.Structure):
@@ -327,9 +327,9 @@ class Image:
 
 class Context:
     def __init__(self, device=0, chunk_bytes=4096, staging_budget=0, flags=0, block_threads=0,
-                 waves_per_chunk=0, wgs_per_cu=0, lane_pieces=0, load_hint=0, table_mode=0):
+                 waves_per_chunk=0, wgs_per_cu=0, lane_pieces=0, load_hint=0, table_mode=0, segment_mib=0):
         cfg = ckpt_config(device, chunk_bytes, staging_budget, flags, block_threads, waves_per_chunk,
-                          wgs_per_cu, lane_pieces, load_hint, table_mode, 0)
+                          wgs_per_cu, lane_pieces, load_hint, table_mode, segment_mib)
         h = _vp()
         _check(lib().ckpt_init(ctypes.byref(cfg), ctypes.byref(h)), "ckpt_init")
         self.handle = h.value

@@ -214,7 +214,9 @@ struct ckpt_ctx {
     bool ready = false;           // streams, events, tables made (ctx_ready)
     hipStream_t side = nullptr;   // drain stream
     hipStream_t cap = nullptr;    // graph capture stream
+    hipStream_t gat = nullptr;    // gather stream of a segmented drain
     hipEvent_t ev[8] = {};
+    std::vector<hipEvent_t> seg_ev;   // segment pipelines: slot ordering and timing
     hipEvent_t meta_ev = nullptr;   // last asynchronous CRC/flag copy to the host
     bool meta_pending = false;
 
@@ -284,6 +286,11 @@ int alloc_meta(ckpt_image *img, uint64_t N);
 void image_wait(const ckpt_image *img);
 int order_after_meta(ckpt_ctx *ctx, hipStream_t s);
 int ctx_ready(ckpt_ctx *ctx);
+// Segment size of drains and restores (0: one pass) and the device slots.
+uint64_t segment_bytes(const ckpt_config &cfg);
+constexpr int kSegSlots = 4;
+// At least n events in ctx->seg_ev.
+int seg_events(ckpt_ctx *ctx, size_t n);
 int graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, uint64_t N, uint64_t data_bytes);
 int upload_table(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, bool dst_side, uint64_t N_host,
                  uint64_t n_items);

@@ -110,6 +110,10 @@ struct ChunkArgs {
     uint32_t pad0;
     uint8_t *bad;             // per chunk, set to 1 when verification fails
     DevPlan *plan_rw;         // bad_count lives here
+    // restore by segments: items [item_begin, item_end) when item_end != 0
+    // (else all items of the plan); staging holds the serialized bytes from
+    // offset soff_base on
+    uint64_t item_begin, item_end, soff_base;
 };
 
 // Row-mode chunk launch (the serving loop): each row is a run of chunks of
@@ -181,6 +185,10 @@ struct GatherArgs {
     const uint8_t *flags;
     const uint64_t *soff;
     uint8_t *out;             // device buffer or mapped pinned host buffer
+    int out_host;             // 1: out is pinned host memory
+    // by segments: chunks [g_begin, g_end) when g_end != 0 (else all chunks
+    // of the plan); out holds the serialized bytes from offset soff_base on
+    uint64_t g_begin, g_end, soff_base;
 };
 
 // Launch wrappers (kernels.hip).  All return the hipError_t of the launch.
@@ -191,6 +199,7 @@ hipError_t launch_chunk_map(hipStream_t s, const DevPlan *plan, const uint64_t *
 hipError_t launch_chunks(hipStream_t s, int mode, const ChunkArgs &a, int grid, int block);
 hipError_t launch_rows(hipStream_t s, const RowArgs &a, int grid, int block);
 hipError_t launch_select(hipStream_t s, const SelArgs &a, uint64_t max_items);
+// grid: workgroups of 1024 threads (persistent; two per CU fill the chip)
 hipError_t launch_gather(hipStream_t s, const GatherArgs &a, int grid);
 hipError_t launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t n_words, uint64_t value);
 hipError_t launch_pick_u64(hipStream_t s, const uint64_t *src, const uint64_t *idx, uint64_t *out,

@@ -623,6 +623,8 @@ struct Rounds {
 template <int MODE>
 __device__ __forceinline__ Desc make_desc(const ChunkArgs &a, uint64_t i, uint32_t C)
 {
+    if (MODE == kModeRestore)
+        i += a.item_begin;
     const uint64_t g = (MODE == kModeRestore && a.ids) ? a.ids[i] : i;
     const uint32_t k = a.map[g];
     const uint64_t start = (g - a.cb[k]) * C;
@@ -634,7 +636,7 @@ __device__ __forceinline__ Desc make_desc(const ChunkArgs &a, uint64_t i, uint32
     if (MODE == kModeRestore) {
         d.zero = a.want_flags[g] & kFlagZero;
         d.want = a.want_crc[g];
-        d.src = d.zero ? 0 : (uint64_t)(a.staging + a.soff[i]);
+        d.src = d.zero ? 0 : (uint64_t)(a.staging + (a.soff[i] - a.soff_base));
         d.dst = a.dst[k] + start;
     } else {
         d.zero = 0;
@@ -787,7 +789,8 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
     const uint32_t r_full = (C + round_bytes - 1) / round_bytes;
     const uint32_t rw = (r_full + W - 1) / W;            // rounds per wave
     const uint32_t r_win = rw * W;
-    const uint64_t M = (MODE == kModeRestore) ? a.plan->n_items : a.plan->n_chunks;
+    const uint64_t M = (MODE != kModeRestore) ? a.plan->n_chunks
+                       : a.item_end ? a.item_end - a.item_begin : a.plan->n_items;
 
     // The items go in rounds of at most gridDim.x * kTile, each split evenly
     // over the workgroups, so the whole grid sweeps one window of memory at a
@@ -1194,33 +1197,77 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_down(SelArgs a)
 //
 // Copies each selected chunk (roundup16(len) bytes) to out + soff[g], from the
 // dense image or straight from the allocation (zero pad written, never read).
+// Each wave takes 64 consecutive chunks: lane l fetches the descriptor of
+// chunk t0 + l, so the descriptor loads of all 64 are in flight together.
+// The wave then copies its selected chunks one after the other (their
+// addresses read from the owning lane), each lane issuing up to
+// kGatherLoads 16-byte loads before its first store.
 
-__global__ __launch_bounds__(256) void k_gather(GatherArgs a)
+constexpr int kGatherLoads = 8;
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int j)
 {
-    const uint64_t N = a.plan->n_chunks;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <bool NT_ST>
+__device__ __forceinline__ void gather_copy(const uint8_t *s, uint8_t *d, uint32_t n, bool whole, int lane)
+{
+    const uint32_t np = (n + 15) >> 4;
+    for (uint32_t p0 = 0; p0 < np; p0 += 64 * kGatherLoads) {
+        uint4 v[kGatherLoads];
+#pragma unroll
+        for (int u = 0; u < kGatherLoads; u++) {
+            const uint32_t p = p0 + u * 64 + lane;
+            v[u] = make_uint4(0u, 0u, 0u, 0u);
+            if (p < np) {
+                const uint32_t o = 16 * p;
+                // the dense image's pad is zero and may be read; an allocation's tail may not
+                v[u] = (whole || o + 16 <= n) ? ld16<true>(s + o) : load_partial(s + o, n - o);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherLoads; u++) {
+            const uint32_t p = p0 + u * 64 + lane;
+            if (p < np)
+                st16<NT_ST>(d + 16 * p, v[u]);
+        }
+    }
+}
+
+template <bool NT_ST>
+__global__ __launch_bounds__(1024) void k_gather(GatherArgs a)
+{
+    const uint64_t N = a.g_end ? a.g_end : a.plan->n_chunks;
     const int lane = threadIdx.x & 63;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    for (uint64_t g = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g < N; g += waves) {
-        const uint8_t f = a.flags[g];
-        const bool take = a.mode == kSelNonZero ? !(f & kFlagZero) : ((f & kFlagDirty) && !(f & kFlagZero));
-        if (!take)
-            continue;
-        const uint32_t k = a.map[g];
-        const uint64_t start = (g - a.cb[k]) * a.C;
-        const uint64_t rest = a.size[k] - start;
-        const uint32_t len = (uint32_t)(rest < a.C ? rest : a.C);
-        const uint32_t np = (len + 15) >> 4;
-        uint8_t *out = a.out + a.soff[g];
-        if (a.from_dense) {
-            const uint8_t *in = a.dense + a.off[k] + start;
-            for (uint32_t p = lane; p < np; p += 64)
-                *(uint4 *)(out + 16 * p) = *(const uint4 *)(in + 16 * p);
-        } else {
-            const uint8_t *in = (const uint8_t *)a.src[k] + start;
-            for (uint32_t p = lane; p < np; p += 64) {
-                const uint32_t s = 16 * p;
-                *(uint4 *)(out + s) = s + 16 <= len ? *(const uint4 *)(in + s) : load_partial(in + s, len - s);
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    for (uint64_t t0 = a.g_begin + wave * 64; t0 < N; t0 += waves * 64) {
+        const uint64_t g = t0 + lane;
+        bool take = false;
+        uint64_t src = 0, dst = 0;
+        uint32_t len = 0;
+        if (g < N) {
+            const uint8_t f = a.flags[g];
+            const uint32_t k = a.map[g];
+            const uint64_t so = a.soff[g];
+            take = a.mode == kSelNonZero ? !(f & kFlagZero) : ((f & kFlagDirty) && !(f & kFlagZero));
+            if (take) {
+                const uint64_t start = (g - a.cb[k]) * a.C;
+                const uint64_t rest = a.size[k] - start;
+                len = (uint32_t)(rest < a.C ? rest : a.C);
+                src = a.from_dense ? (uint64_t)(a.dense + a.off[k] + start) : a.src[k] + start;
+                dst = (uint64_t)(a.out + (so - a.soff_base));
             }
+        }
+        uint64_t m = __ballot(take);
+        while (m) {
+            const int j = __builtin_ctzll(m);   // uniform over the wave
+            m &= m - 1;
+            gather_copy<NT_ST>((const uint8_t *)readlane_u64(src, j), (uint8_t *)readlane_u64(dst, j),
+                               (uint32_t)__builtin_amdgcn_readlane((int)len, j), a.from_dense != 0, lane);
         }
     }
 }
@@ -1363,7 +1410,11 @@ hipError_t launch_select(hipStream_t s, const SelArgs &a, uint64_t max_items)
 
 hipError_t launch_gather(hipStream_t s, const GatherArgs &a, int grid)
 {
-    hipLaunchKernelGGL(k_gather, dim3(grid), dim3(256), 0, s, a);
+    // stores into pinned host memory (the direct drain) keep the default policy
+    if (a.out_host)
+        hipLaunchKernelGGL(k_gather<false>, dim3(grid), dim3(1024), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_gather<true>, dim3(grid), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 

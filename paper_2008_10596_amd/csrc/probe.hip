@@ -1,0 +1,142 @@
+// probe.hip -- plain HBM read, write and copy kernels for measurement only
+// (libckpt_probe.so, loaded by bench.py): they give the ceilings that the
+// drain/refill kernels of libckpt are compared with.  None of them is on the
+// checkpoint path.
+//
+// Each kernel sweeps one buffer with a grid of persistent workgroups: in
+// iteration i, wave w of W handles the U * 1 KiB at ((i * W + w) * U) KiB, lane
+// l the 16-byte pieces l, l + 64, ..., so the whole grid moves through memory
+// one window of W * U KiB at a time.  U loads are issued before any of them is
+// used (read: OR-reduced; copy: stored).  NT selects non-temporal loads and
+// stores.  Sizes must be multiples of 16 bytes; the tail of a window is
+// guarded.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ u32x4 ld(const u32x4 *p)
+{
+    if (NT)
+        return __builtin_nontemporal_load(p);
+    return *p;
+}
+
+template <bool NT>
+__device__ __forceinline__ void st(u32x4 *p, u32x4 v)
+{
+    if (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+template <int U, bool NT>
+__global__ __launch_bounds__(1024) void k_read(const u32x4 *__restrict__ src, uint64_t n16, uint32_t *__restrict__ sink)
+{
+    const uint64_t lane = threadIdx.x & 63;
+    const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t W = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    u32x4 acc = {0u, 0u, 0u, 0u};
+    for (uint64_t base = w * 64 * U; base < n16; base += W * 64 * U) {
+        u32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint64_t p = base + u * 64 + lane;
+            v[u] = p < n16 ? ld<NT>(src + p) : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            acc |= v[u];
+    }
+    const uint32_t r = acc.x | acc.y | acc.z | acc.w;
+    if (r == 0x9E3779B9u)   // practically never: keeps the loads without a store per thread
+        sink[0] = r;
+}
+
+template <int U, bool NT>
+__global__ __launch_bounds__(1024) void k_write(u32x4 *__restrict__ dst, uint64_t n16, uint32_t value)
+{
+    const uint64_t lane = threadIdx.x & 63;
+    const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t W = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const u32x4 v = {value, value, value, value};
+    for (uint64_t base = w * 64 * U; base < n16; base += W * 64 * U) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint64_t p = base + u * 64 + lane;
+            if (p < n16)
+                st<NT>(dst + p, v);
+        }
+    }
+}
+
+template <int U, bool NT>
+__global__ __launch_bounds__(1024) void k_copy(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, uint64_t n16)
+{
+    const uint64_t lane = threadIdx.x & 63;
+    const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t W = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t base = w * 64 * U; base < n16; base += W * 64 * U) {
+        u32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint64_t p = base + u * 64 + lane;
+            v[u] = p < n16 ? ld<NT>(src + p) : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint64_t p = base + u * 64 + lane;
+            if (p < n16)
+                st<NT>(dst + p, v[u]);
+        }
+    }
+}
+
+template <int U, bool NT>
+void launch(int kind, const void *src, void *dst, uint64_t n16, int grid, int block, hipStream_t s)
+{
+    if (kind == 0)
+        hipLaunchKernelGGL((k_read<U, NT>), dim3(grid), dim3(block), 0, s, (const u32x4 *)src, n16, (uint32_t *)dst);
+    else if (kind == 1)
+        hipLaunchKernelGGL((k_write<U, NT>), dim3(grid), dim3(block), 0, s, (u32x4 *)dst, n16, 0u);
+    else
+        hipLaunchKernelGGL((k_copy<U, NT>), dim3(grid), dim3(block), 0, s, (const u32x4 *)src, (u32x4 *)dst, n16);
+}
+
+}  // namespace
+
+// kind: 0 read (dst: a 4-byte sink), 1 write, 2 copy.  bytes: a multiple of
+// 16.  loads: 1, 2, 4, 8 or 16 pieces per lane per iteration; nt: 0/1.
+// Returns 0, or -1 for bad arguments, or the hipError_t of the launch.
+extern "C" int probe_launch(int kind, const void *src, void *dst, uint64_t bytes, int loads, int nt, int grid,
+                            int block, void *stream)
+{
+    if (kind < 0 || kind > 2 || bytes % 16 || grid <= 0 || (block != 256 && block != 512 && block != 1024))
+        return -1;
+    if ((kind != 1 && !src) || !dst)
+        return -1;
+    const uint64_t n16 = bytes / 16;
+    hipStream_t s = (hipStream_t)stream;
+#define CASE(U)                                                                          \
+    case U:                                                                              \
+        if (nt)                                                                          \
+            launch<U, true>(kind, src, dst, n16, grid, block, s);                        \
+        else                                                                             \
+            launch<U, false>(kind, src, dst, n16, grid, block, s);                       \
+        break;
+    switch (loads) {
+        CASE(1)
+        CASE(2)
+        CASE(4)
+        CASE(8)
+        CASE(16)
+    default:
+        return -1;
+    }
+#undef CASE
+    return (int)hipGetLastError();
+}

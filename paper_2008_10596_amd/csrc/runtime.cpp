@@ -375,6 +375,7 @@ int ckpt::ctx_ready(ckpt_ctx *ctx)
     const ckpt_config &cfg = ctx->cfg;
     HIP_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&ctx->gat, hipStreamNonBlocking));
     for (auto &ev : ctx->ev)
         HIP_TRY(hipEventCreate(&ev));
     HIP_TRY(hipEventCreateWithFlags(&ctx->meta_ev, hipEventDisableTiming));
@@ -397,6 +398,23 @@ int ckpt::ctx_ready(ckpt_ctx *ctx)
     return CKPT_OK;
 }
 
+uint64_t ckpt::segment_bytes(const ckpt_config &cfg)
+{
+    if (cfg.segment_mib == 0xFFFFFFFFu)
+        return 0;
+    return (uint64_t)(cfg.segment_mib ? cfg.segment_mib : 256) << 20;
+}
+
+int ckpt::seg_events(ckpt_ctx *ctx, size_t n)
+{
+    while (ctx->seg_ev.size() < n) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipEventCreate(&e));
+        ctx->seg_ev.push_back(e);
+    }
+    return CKPT_OK;
+}
+
 extern "C" void ckpt_destroy(ckpt_ctx *ctx)
 {
     if (!ctx)
@@ -406,7 +424,7 @@ extern "C" void ckpt_destroy(ckpt_ctx *ctx)
         DeviceGuard g(ctx->cfg.device);
         if (ctx->g_exec)
             (void)hipGraphExecDestroy(ctx->g_exec);
-        for (hipStream_t st : {ctx->side, ctx->cap})
+        for (hipStream_t st : {ctx->side, ctx->cap, ctx->gat})
             if (st) {
                 (void)hipStreamSynchronize(st);
                 (void)hipStreamDestroy(st);
@@ -414,6 +432,8 @@ extern "C" void ckpt_destroy(ckpt_ctx *ctx)
         for (auto &ev : ctx->ev)
             if (ev)
                 (void)hipEventDestroy(ev);
+        for (hipEvent_t ev : ctx->seg_ev)
+            (void)hipEventDestroy(ev);
         if (ctx->meta_ev)
             (void)hipEventDestroy(ctx->meta_ev);
         for (DevBuf *b : ctx->all_dev())
@@ -916,14 +936,16 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     std::vector<PinnedBuf> data(outs.size());
     PinnedBuf all_data;              // one pinned buffer when there is a single output
 
-    hipStream_t ds = ctx->side;      // drain stream
+    hipStream_t ds = ctx->side;      // drain stream: the copies to the host
+    hipStream_t gs = ctx->side;      // the stream the gather runs on
     bool snap = false;               // the host copies read the snapshot buffers
     if (incremental) {
         // The delta is gathered from the allocations themselves, so it must be
-        // taken before `s` may run new work: hash, select and gather all on s.
+        // taken before `s` may run new work: hash, select and gather on s.
+        // The copies to the host then run on the side stream.
         CKPT_TRY(run_select(ctx, s, kSelDirtyNonZero, a.flags, nullptr, N, d_soff, (uint64_t *)ctx->d_ids.p, N));
         CKPT_TRY(read_plan(ctx, s, &P));
-        ds = s;
+        gs = s;
     } else {
         if (no_drain && N) {
             // Snapshot the CRC and flag arrays for the host copies, which then
@@ -948,7 +970,7 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
         }
     }
     if (timing)
-        HIP_TRY(hipEventRecord(ctx->ev[4], ds));
+        HIP_TRY(hipEventRecord(ctx->ev[4], gs));
 
     // Per-output slices: rows [parts[i], parts[i+1]) -> chunks [cb_i, cb_i+1)
     // -> serialized bytes [soff(cb_i), soff(cb_i+1)).
@@ -960,40 +982,63 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     for (size_t i = 0; i <= nout; i++)
         part_chunk[i] = L.cb[part_row[i]];
     const uint64_t sel_bytes = no_drain ? 0 : P.sel_bytes;
+    // A full checkpoint drains in segments of seg_chunks chunks: each
+    // segment's gather (on the gather stream, into one of kSegSlots device
+    // slots) overlaps the copy of earlier segments to the host (on the side
+    // stream), and at most kSegSlots segments are staged.  An increment is
+    // gathered on s in one pass (it is small, and s must not wait for the host
+    // link); CKPT_DRAIN_DIRECT stores to the host from the gather itself.
+    const uint64_t seg_b = segment_bytes(cfg);
+    const uint64_t seg_chunks = seg_b ? std::max<uint64_t>(1, seg_b / C) : 0;
+    const uint64_t n_seg = (!no_drain && sel_bytes && !incremental && !direct && seg_b)
+                               ? (N + seg_chunks - 1) / seg_chunks : 0;
+    const bool segmented = n_seg > 1;
+    const uint64_t slot_bytes = seg_chunks * C;   // a segment's serialized bytes never exceed this
+    std::vector<uint64_t> seg_data;               // serialized offset of each segment's first chunk
     if (!no_drain) {
-        if (nout == 1) {
+        if (nout == 1 && !segmented) {
             part_data[1] = sel_bytes;
         } else {
-            // serialized offset of each part's first chunk: soff[cb_i] (or the total)
-            CKPT_TRY(ctx->d_pick.ensure((nout + 1) * 16));
-            std::vector<uint64_t> idx(nout + 1);
-            for (size_t i = 0; i <= nout; i++)
-                idx[i] = std::min<uint64_t>(part_chunk[i], N ? N - 1 : 0);
-            uint64_t *d_idx = (uint64_t *)ctx->d_pick.p, *d_val = d_idx + nout + 1;
-            HIP_TRY(hipMemcpyAsync(d_idx, idx.data(), idx.size() * 8, hipMemcpyHostToDevice, ds));
-            HIP_TRY(launch_pick_u64(ds, d_soff, d_idx, d_val, (uint32_t)(nout + 1)));
-            std::vector<uint64_t> val(nout + 1);
-            HIP_TRY(hipMemcpyAsync(val.data(), d_val, val.size() * 8, hipMemcpyDeviceToHost, ds));
+            // serialized offsets (soff) at the outputs' and segments' first chunks
+            std::vector<uint64_t> want(part_chunk.begin(), part_chunk.end());
+            if (segmented)
+                for (uint64_t k = 0; k <= n_seg; k++)
+                    want.push_back(std::min<uint64_t>(N, k * seg_chunks));
+            const size_t m = want.size();
+            CKPT_TRY(ctx->d_pick.ensure(m * 16));
+            std::vector<uint64_t> idx(m), val(m);
+            for (size_t i = 0; i < m; i++)
+                idx[i] = std::min<uint64_t>(want[i], N ? N - 1 : 0);
+            uint64_t *d_idx = (uint64_t *)ctx->d_pick.p, *d_val = d_idx + m;
+            HIP_TRY(hipMemcpyAsync(d_idx, idx.data(), m * 8, hipMemcpyHostToDevice, ds));
+            HIP_TRY(launch_pick_u64(ds, d_soff, d_idx, d_val, (uint32_t)m));
+            HIP_TRY(hipMemcpyAsync(val.data(), d_val, m * 8, hipMemcpyDeviceToHost, ds));
             HIP_TRY(hipStreamSynchronize(ds));
+            for (size_t i = 0; i < m; i++)
+                val[i] = want[i] >= N ? sel_bytes : val[i];
             for (size_t i = 0; i <= nout; i++)
-                part_data[i] = part_chunk[i] >= N ? sel_bytes : val[i];
+                part_data[i] = val[i];
+            seg_data.assign(val.begin() + (nout + 1), val.end());
         }
     }
 
     // Drain: gather the selected chunks, then copy them to pinned host memory.
+    uint64_t n_timed = 0;   // segments with per-segment gather events
     if (!no_drain && sel_bytes) {
-        if (cfg.staging_budget && !direct &&
-            (incremental ? 0 : L.data_bytes) + sel_bytes > cfg.staging_budget)
+        const uint64_t stage = segmented ? std::min<uint64_t>(sel_bytes, kSegSlots * slot_bytes) : sel_bytes;
+        if (cfg.staging_budget && !direct && (incremental ? 0 : L.data_bytes) + stage > cfg.staging_budget)
             return set_error(CKPT_E_BUDGET, "drain staging %llu B exceeds the budget",
-                             (unsigned long long)((incremental ? 0 : L.data_bytes) + sel_bytes));
+                             (unsigned long long)((incremental ? 0 : L.data_bytes) + stage));
         if (direct) {
             if (nout != 1)
                 return set_error(CKPT_E_INVAL, "CKPT_DRAIN_DIRECT is not available for batches");
             CKPT_TRY(data[0].ensure(sel_bytes));
             d_out = (uint8_t *)data[0].p;
         } else {
-            CKPT_TRY(ctx->d_compact.ensure(sel_bytes));
+            CKPT_TRY(ctx->d_compact.ensure(stage));
             d_out = (uint8_t *)ctx->d_compact.p;
+            for (size_t i = 0; i < nout; i++)
+                CKPT_TRY(data[i].ensure(part_data[i + 1] - part_data[i]));
         }
         GatherArgs ga;
         memset(&ga, 0, sizeof(ga));
@@ -1010,24 +1055,76 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
         ga.flags = a.flags;
         ga.soff = d_soff;
         ga.out = d_out;
-        HIP_TRY(launch_gather(ds, ga, ctx->grid_small));
-        if (incremental) {
-            HIP_TRY(hipEventRecord(ctx->ev[3], s));   // delta taken: the caller's stream is free
-        }
-        if (timing)
-            HIP_TRY(hipEventRecord(ctx->ev[5], ds));
-        if (!direct)
-            for (size_t i = 0; i < nout; i++) {
-                const uint64_t b = part_data[i + 1] - part_data[i];
-                CKPT_TRY(data[i].ensure(b));
-                if (b)
-                    HIP_TRY(hipMemcpyAsync(data[i].p, d_out + part_data[i], b, hipMemcpyDeviceToHost, ds));
+        ga.out_host = direct ? 1 : 0;
+        if (segmented) {
+            // The pack and the select are complete (the side stream was
+            // synchronized above).  slot_full[j]: slot j gathered; slot_free[j]:
+            // slot j copied out.
+            CKPT_TRY(seg_events(ctx, 2 * kSegSlots + (timing ? 2 * n_seg : 0)));
+            hipEvent_t *slot_full = ctx->seg_ev.data(), *slot_free = slot_full + kSegSlots;
+            hipEvent_t *tev = slot_free + kSegSlots;
+            hipStream_t gst = ctx->gat;
+            uint64_t used = 0;
+            for (uint64_t k = 0; k < n_seg; k++) {
+                const uint64_t b0 = seg_data[k], b1 = seg_data[k + 1];
+                if (b1 == b0)
+                    continue;   // only ZERO chunks
+                const int j = (int)(used % kSegSlots);
+                if (used >= (uint64_t)kSegSlots)
+                    HIP_TRY(hipStreamWaitEvent(gst, slot_free[j], 0));
+                ga.g_begin = k * seg_chunks;
+                ga.g_end = std::min<uint64_t>(N, (k + 1) * seg_chunks);
+                ga.out = d_out + (uint64_t)j * slot_bytes;
+                ga.soff_base = b0;
+                if (timing)
+                    HIP_TRY(hipEventRecord(tev[2 * used], gst));
+                HIP_TRY(launch_gather(gst, ga, 2 * ctx->cu_count));
+                if (timing)
+                    HIP_TRY(hipEventRecord(tev[2 * used + 1], gst));
+                HIP_TRY(hipEventRecord(slot_full[j], gst));
+                HIP_TRY(hipStreamWaitEvent(ds, slot_full[j], 0));
+                if (timing && used == 0)
+                    HIP_TRY(hipEventRecord(ctx->ev[7], ds));
+                for (size_t i = 0; i < nout; i++) {   // the segment's bytes, cut at the outputs' bounds
+                    const uint64_t lo = std::max(b0, part_data[i]), hi = std::min(b1, part_data[i + 1]);
+                    if (lo < hi)
+                        HIP_TRY(hipMemcpyAsync((uint8_t *)data[i].p + (lo - part_data[i]), ga.out + (lo - b0), hi - lo,
+                                               hipMemcpyDeviceToHost, ds));
+                }
+                HIP_TRY(hipEventRecord(slot_free[j], ds));
+                used++;
             }
+            n_timed = timing ? used : 0;
+            if (timing)
+                HIP_TRY(hipEventRecord(ctx->ev[5], gst));
+        } else {
+            HIP_TRY(launch_gather(gs, ga, 2 * ctx->cu_count));
+            if (incremental) {
+                HIP_TRY(hipEventRecord(ctx->ev[3], s));   // delta taken: the caller's stream is free
+                HIP_TRY(hipStreamWaitEvent(ds, ctx->ev[3], 0));
+            }
+            if (timing) {
+                HIP_TRY(hipEventRecord(ctx->ev[5], gs));
+                HIP_TRY(hipStreamWaitEvent(ds, ctx->ev[5], 0));
+                HIP_TRY(hipEventRecord(ctx->ev[7], ds));
+            }
+            if (!direct)
+                for (size_t i = 0; i < nout; i++) {
+                    const uint64_t b = part_data[i + 1] - part_data[i];
+                    if (b)
+                        HIP_TRY(hipMemcpyAsync(data[i].p, d_out + part_data[i], b, hipMemcpyDeviceToHost, ds));
+                }
+        }
     } else {
-        if (incremental)
+        if (incremental) {
             HIP_TRY(hipEventRecord(ctx->ev[3], s));
-        if (timing)
-            HIP_TRY(hipEventRecord(ctx->ev[5], ds));
+            HIP_TRY(hipStreamWaitEvent(ds, ctx->ev[3], 0));
+        }
+        if (timing) {
+            HIP_TRY(hipEventRecord(ctx->ev[5], gs));
+            HIP_TRY(hipStreamWaitEvent(ds, ctx->ev[5], 0));
+            HIP_TRY(hipEventRecord(ctx->ev[7], ds));
+        }
     }
 
     // Metadata: CRC, flags, dirty ids, layout.
@@ -1085,8 +1182,7 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     // keep this CRC array on the device as the base of the next increment
     // (the snapshot already is)
     if (nout == 1 && N && !snap) {
-        if (ds == s)
-            CKPT_TRY(order_after_meta(ctx, s));   // earlier host copies may read d_prev_crc
+        // on the side stream, after the earlier host copies that may read d_prev_crc
         CKPT_TRY(ctx->d_prev_crc.ensure(N * 4));
         HIP_TRY(hipMemcpyAsync(ctx->d_prev_crc.p, ctx->d_crc.p, N * 4, hipMemcpyDeviceToDevice, ds));
     }
@@ -1096,7 +1192,9 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     // flag copies to the host finish on the side stream while the caller goes
     // on.  Each image waits for its own copy before it exposes host sections,
     // and the next call on this context orders its work after them.
-    const bool async_meta = no_drain && ds != s;
+    // (An increment's copies read d_crc / d_flags themselves, which the next
+    // call overwrites, so an increment always waits for them.)
+    const bool async_meta = no_drain && !incremental;
     if (async_meta) {
         auto ev = std::make_shared<MetaEvent>();
         HIP_TRY(hipEventCreateWithFlags(&ev->e, hipEventDisableTiming));
@@ -1108,8 +1206,7 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
         HIP_TRY(hipStreamSynchronize(s));
     } else {
         HIP_TRY(hipStreamSynchronize(ds));
-        if (ds != s)
-            HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipStreamSynchronize(s));
     }
     ctx->prev_serial = nout == 1 && N ? imgs[0]->serial : 0;
 
@@ -1118,8 +1215,13 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
         T.pack_ms = graph ? ev_ms(ctx->ev[0], ctx->ev[2]) : ev_ms(ctx->ev[1], ctx->ev[2]);
         if (!async_meta) {
             T.select_ms = incremental ? ev_ms(ctx->ev[2], ctx->ev[4]) : ev_ms(ctx->ev[3], ctx->ev[4]);
-            T.gather_ms = ev_ms(ctx->ev[4], ctx->ev[5]);
-            T.d2h_ms = ev_ms(ctx->ev[5], ctx->ev[6]);
+            if (n_timed) {
+                for (uint64_t u = 0; u < n_timed; u++)
+                    T.gather_ms += ev_ms(ctx->seg_ev[2 * kSegSlots + 2 * u], ctx->seg_ev[2 * kSegSlots + 2 * u + 1]);
+            } else {
+                T.gather_ms = ev_ms(ctx->ev[4], ctx->ev[5]);
+            }
+            T.d2h_ms = ev_ms(ctx->ev[7], ctx->ev[6]);
         }
     }
     T.link_bytes = sel_bytes + 5 * N;
@@ -1248,7 +1350,17 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
                                  (unsigned long long)img->N);
     }
     const uint64_t N = img->N;
-    const uint64_t stage = img->ser_bytes + (delta ? delta->ser_bytes : 0);
+    // The base image is refilled in segments of seg_chunks chunks: each
+    // segment's copy to the device (side stream, into one of kSegSlots slots)
+    // overlaps the scatter of earlier segments (on `stream`), and at most
+    // kSegSlots segments are staged.
+    const uint64_t seg_b = segment_bytes(ctx->cfg);
+    const uint64_t seg_chunks = seg_b ? std::max<uint64_t>(1, seg_b / img->C) : 0;
+    const uint64_t n_seg = seg_b && N ? (N + seg_chunks - 1) / seg_chunks : 0;
+    const bool segmented = n_seg > 1;
+    const uint64_t slot_bytes = seg_chunks * img->C;   // a segment's serialized bytes never exceed this
+    const uint64_t base_stage = segmented ? std::min<uint64_t>(img->ser_bytes, kSegSlots * slot_bytes) : img->ser_bytes;
+    const uint64_t stage = base_stage + (delta ? delta->ser_bytes : 0);
     if (ctx->cfg.staging_budget && stage > ctx->cfg.staging_budget)
         return set_error(CKPT_E_BUDGET, "restore staging %llu B exceeds the budget", (unsigned long long)stage);
 
@@ -1278,7 +1390,7 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
         HIP_TRY(hipMemcpyAsync(ctx->d_flags.p, img->flags, N, hipMemcpyHostToDevice, s));
         HIP_TRY(launch_fill_u64(s, (uint64_t *)ctx->d_bad.p, (N + 7) / 8, 0));
     }
-    if (img->ser_bytes)
+    if (img->ser_bytes && !segmented)
         HIP_TRY(hipMemcpyAsync(staging, img->data.p, img->ser_bytes, hipMemcpyHostToDevice, s));
     if (timing)
         HIP_TRY(hipEventRecord(ctx->ev[1], s));
@@ -1305,7 +1417,54 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
         if (P.sel_bytes != img->ser_bytes)
             return set_error(CKPT_E_INVAL, "flags select %llu serialized bytes, image holds %llu",
                              (unsigned long long)P.sel_bytes, (unsigned long long)img->ser_bytes);
-        HIP_TRY(launch_chunks(s, kModeRestore, a, ctx->grid_chunks, ctx->cfg.block_threads));
+        if (!segmented) {
+            HIP_TRY(launch_chunks(s, kModeRestore, a, ctx->grid_chunks, ctx->cfg.block_threads));
+        } else {
+            // serialized offset of each segment's first chunk
+            std::vector<uint64_t> idx(n_seg + 1), seg_data(n_seg + 1);
+            for (uint64_t k = 0; k <= n_seg; k++)
+                idx[k] = std::min<uint64_t>(k * seg_chunks, N - 1);
+            CKPT_TRY(ctx->d_pick.ensure((n_seg + 1) * 16));
+            uint64_t *d_idx = (uint64_t *)ctx->d_pick.p, *d_val = d_idx + n_seg + 1;
+            HIP_TRY(hipMemcpyAsync(d_idx, idx.data(), (n_seg + 1) * 8, hipMemcpyHostToDevice, s));
+            HIP_TRY(launch_pick_u64(s, (const uint64_t *)ctx->d_soff.p, d_idx, d_val, (uint32_t)(n_seg + 1)));
+            HIP_TRY(hipMemcpyAsync(seg_data.data(), d_val, (n_seg + 1) * 8, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            seg_data[n_seg] = img->ser_bytes;
+            // slot_full[j]: slot j copied in; slot_free[j]: slot j scattered
+            CKPT_TRY(seg_events(ctx, 2 * kSegSlots + (timing ? 2 * n_seg : 0)));
+            hipEvent_t *slot_full = ctx->seg_ev.data(), *slot_free = slot_full + kSegSlots;
+            hipEvent_t *tev = slot_free + kSegSlots;
+            hipStream_t cs = ctx->side;
+            HIP_TRY(hipEventRecord(ctx->ev[3], s));   // the staging's earlier readers are done
+            HIP_TRY(hipStreamWaitEvent(cs, ctx->ev[3], 0));
+            if (timing)
+                HIP_TRY(hipEventRecord(ctx->ev[7], cs));
+            for (uint64_t k = 0; k < n_seg; k++) {
+                const uint64_t b0 = seg_data[k], b1 = seg_data[k + 1];
+                const int j = (int)(k % kSegSlots);
+                if (k >= (uint64_t)kSegSlots)
+                    HIP_TRY(hipStreamWaitEvent(cs, slot_free[j], 0));
+                uint8_t *slot = staging + (uint64_t)j * slot_bytes;
+                if (b1 > b0)
+                    HIP_TRY(hipMemcpyAsync(slot, (const uint8_t *)img->data.p + b0, b1 - b0, hipMemcpyHostToDevice, cs));
+                HIP_TRY(hipEventRecord(slot_full[j], cs));
+                HIP_TRY(hipStreamWaitEvent(s, slot_full[j], 0));
+                ChunkArgs sa = a;
+                sa.item_begin = k * seg_chunks;
+                sa.item_end = std::min<uint64_t>(N, (k + 1) * seg_chunks);
+                sa.staging = slot;
+                sa.soff_base = b0;
+                if (timing)
+                    HIP_TRY(hipEventRecord(tev[2 * k], s));
+                HIP_TRY(launch_chunks(s, kModeRestore, sa, ctx->grid_chunks, ctx->cfg.block_threads));
+                if (timing)
+                    HIP_TRY(hipEventRecord(tev[2 * k + 1], s));
+                HIP_TRY(hipEventRecord(slot_free[j], s));
+            }
+            if (timing)
+                HIP_TRY(hipEventRecord(ctx->ev[6], cs));
+        }
     } else if (img->ser_bytes) {
         return set_error(CKPT_E_INVAL, "image without chunks holds serialized bytes");
     }
@@ -1315,7 +1474,9 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
         CKPT_TRY(ctx->d_flags2.ensure(std::max<uint64_t>(N, 1)));
         CKPT_TRY(ctx->d_ids.ensure(nd * 8));
         CKPT_TRY(ctx->d_soff2.ensure(nd * 8));
-        uint8_t *staging2 = staging + img->ser_bytes;
+        if (timing)
+            HIP_TRY(hipEventRecord(ctx->ev[4], s));
+        uint8_t *staging2 = staging + base_stage;
         HIP_TRY(hipMemcpyAsync(ctx->d_crc2.p, delta->crc, N * 4, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(ctx->d_flags2.p, delta->flags, N, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(ctx->d_ids.p, delta->ids_buf.p, nd * 8, hipMemcpyHostToDevice, s));
@@ -1356,8 +1517,16 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
         HIP_TRY(hipMemcpy(ids, ctx->d_ids.p, n_ids * 8, hipMemcpyDeviceToHost));
     }
     if (timing) {
-        T.h2d_ms = ev_ms(ctx->ev[0], ctx->ev[1]);
-        T.scatter_ms = ev_ms(ctx->ev[1], ctx->ev[2]);
+        if (segmented) {
+            T.h2d_ms = ev_ms(ctx->ev[7], ctx->ev[6]);
+            for (uint64_t k = 0; k < n_seg; k++)
+                T.scatter_ms += ev_ms(ctx->seg_ev[2 * kSegSlots + 2 * k], ctx->seg_ev[2 * kSegSlots + 2 * k + 1]);
+            if (delta && delta->n_dirty)
+                T.scatter_ms += ev_ms(ctx->ev[4], ctx->ev[2]);
+        } else {
+            T.h2d_ms = ev_ms(ctx->ev[0], ctx->ev[1]);
+            T.scatter_ms = ev_ms(ctx->ev[1], ctx->ev[2]);
+        }
     }
     T.link_bytes = stage + 5 * N;
     T.total_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t_call).count();

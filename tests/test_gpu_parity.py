@@ -785,3 +785,94 @@ def test_autotuner_shapes_match_the_oracle(tmp_path):
     again = autotune.tune(alloc_sets, chunks=chunks, waves=(1, 2, 4), blocks=(256, 1024), reps=1,
                           cache_path=cache)
     assert again["cached"] and again["best"] == res["best"]
+
+
+# ------------------------------------------------------------- segments
+
+@pytest.mark.parametrize("C", [4096, 65536])
+def test_segmented_drain_and_restore_equal_one_pass(C):
+    """Drain and refill in 1 MiB segments (more segments than device slots, so
+    slots are reused; whole segments of ZERO chunks skipped; allocations and
+    outputs cut by segment bounds) give the oracle's image and memory, as one
+    pass does."""
+    MiB = 1 << 20
+    sizes = [3 * MiB + 5, 17, 5 * MiB, 2 * MiB + 4096 * 3 + 1, 700000, 6 * MiB]
+    tensors = random_allocs(sizes, seed=41, zero=(2,))
+    tensors[5][MiB:3 * MiB] = 0                    # ZERO chunks inside an allocation
+    hosts = [host(t) for t in tensors]
+    ref = O.checkpoint(hosts, C)
+    imgs = {}
+    for seg in (1, 0xFFFFFFFF):
+        ctx = K.Context(chunk_bytes=C, segment_mib=seg, flags=K.CKPT_TIMING)
+        register_all(ctx, tensors)
+        img = ctx.checkpoint()
+        check_full(img, ref, tensors, C)
+        t = ctx.timing()
+        log("segment_mib=%d: gather %.3f ms, d2h %.3f ms, total %.3f ms"
+            % (seg, t["gather_ms"], t["d2h_ms"], t["total_ms"]))
+        for seg_r in (1, 0xFFFFFFFF):
+            rctx = K.Context(chunk_bytes=C, segment_mib=seg_r)
+            dsts = [torch.full_like(x, 0x5A) for x in tensors]
+            rc, rep = rctx.restore(img, dsts)
+            assert rc == K.CKPT_OK, (seg, seg_r, rep)
+            check_restored(dsts, tensors)
+            # a corrupted chunk in a late segment is still reported exactly
+            g = int(ref["n_chunks"]) - 2
+            img.crc[g] ^= 0x4
+            rc, rep = rctx.restore(img, dsts)
+            img.crc[g] ^= 0x4
+            assert rc == K.CKPT_E_CORRUPT and rep["ids"] == [g], (seg, seg_r, rep)
+            rctx.close()
+        imgs[seg] = img
+    for key in ("crc", "flags", "data"):
+        assert np.array_equal(getattr(imgs[1], key), getattr(imgs[0xFFFFFFFF], key)), key
+
+
+def test_segmented_batch_drain_cuts_outputs():
+    """A batched drain in segments: a segment's bytes are cut at the
+    contexts' bounds, so each context's image equals the oracle's."""
+    C = 4096
+    rng = np.random.default_rng(43)
+    sets, hosts = [], []
+    for i in range(7):
+        sizes = [int(x) for x in rng.integers(1, 1500000, int(rng.integers(1, 5)))]
+        t = random_allocs(sizes, seed=430 + i, zero=(0,) if i == 3 else ())
+        sets.append(t)
+        hosts.append([host(a) for a in t])
+    members = []
+    for t in sets:
+        c = K.Context(chunk_bytes=C)
+        register_all(c, t)
+        members.append(c)
+    leader = K.Context(chunk_bytes=C, segment_mib=1)
+    imgs = K.checkpoint_batch([leader] + members)
+    for i, t in enumerate(sets):
+        check_full(imgs[i + 1], O.checkpoint(hosts[i], C), t, C)
+    for im in imgs:
+        im.close()
+    for c in members + [leader]:
+        c.close()
+
+
+def test_increment_drains_on_the_side_stream():
+    """An increment's delta is gathered on the caller's stream and copied to
+    the host on the context's side stream; the image is complete when the call
+    returns and equals the oracle's."""
+    C = 4096
+    tensors = random_allocs([3 << 20, 100000], seed=44)
+    ctx = K.Context(chunk_bytes=C, flags=K.CKPT_TIMING)
+    register_all(ctx, tensors)
+    s = torch.cuda.Stream()
+    base = ctx.checkpoint(stream=s)
+    ref = O.checkpoint([host(t) for t in tensors], C)
+    tensors[0][5 * C:7 * C] = 7
+    torch.cuda.synchronize()
+    d = ctx.checkpoint(stream=s, mode=K.CKPT_INCREMENTAL, base=base)
+    dref = O.delta([host(t) for t in tensors], C, ref["crc"])
+    assert list(d.dirty_ids) == [5, 6]
+    assert np.array_equal(d.data, dref["delta"]) and np.array_equal(d.crc, dref["crc"])
+    t = ctx.timing()
+    assert t["d2h_ms"] > 0 and t["gather_ms"] > 0
+    d.close()
+    base.close()
+    ctx.close()
