@@ -239,7 +239,8 @@ struct ckpt_ctx {
     std::atomic<bool> hooked{false};   // the allocation hook logs into this context
 
     // device buffers
-    ckpt::DevBuf d_tables, d_plan, d_addr, d_size, d_off, d_cb, d_map;
+    const uint32_t *tables = nullptr;   // shared CRC operator tables (shared_tables)
+    ckpt::DevBuf d_plan, d_addr, d_size, d_off, d_cb, d_map;
     ckpt::DevBuf d_crc, d_flags, d_base_crc, d_prev_crc, d_soff, d_ids, d_tile_b, d_tile_c;
     ckpt::DevBuf d_dense, d_compact, d_bad, d_pick, d_crc2, d_flags2, d_soff2, d_base_cb, d_snap_flags;
     ckpt::PinnedBuf h_up, h_plan, h_base_cb;
@@ -251,7 +252,7 @@ struct ckpt_ctx {
 
     std::vector<ckpt::DevBuf *> all_dev()
     {
-        return {&d_tables, &d_plan, &d_addr, &d_size, &d_off, &d_cb, &d_map, &d_crc, &d_flags, &d_base_crc,
+        return {&d_plan, &d_addr, &d_size, &d_off, &d_cb, &d_map, &d_crc, &d_flags, &d_base_crc,
                 &d_prev_crc, &d_soff, &d_ids, &d_tile_b, &d_tile_c, &d_dense, &d_compact, &d_bad, &d_pick,
                 &d_crc2, &d_flags2, &d_soff2, &d_base_cb, &d_snap_flags};
     }
@@ -281,6 +282,9 @@ struct ckpt_image {
 namespace ckpt {
 
 int ctx_setup(ckpt_ctx *ctx);
+// The device CRC operator tables for cfg (device, layout, pieces, rounds per
+// wave), made on first use and shared; NULL and *rc set on failure.
+const uint32_t *shared_tables(const ckpt_config &cfg, int *rc);
 // A private pinned block for an image's CRC (4N bytes) and flags (N bytes).
 int alloc_meta(ckpt_image *img, uint64_t N);
 void image_wait(const ckpt_image *img);

@@ -14,6 +14,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "ckpt.h"
@@ -349,6 +350,50 @@ extern "C" int ckpt_init(const ckpt_config *cfg_in, ckpt_ctx **out)
     return CKPT_OK;
 }
 
+// CRC operator tables on the device, shared by every context with the same
+// device, table layout, pieces per lane and rounds per wave, and kept until
+// the process ends: a batch of hundreds of contexts uploads one set, and a
+// context's later calls find its tables in place.
+const uint32_t *ckpt::shared_tables(const ckpt_config &cfg, int *rc)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, uint32_t, uint32_t, uint32_t>, void *> cache;
+    const uint32_t round_bytes = kRoundBytes * cfg.lane_pieces;
+    const uint32_t r_full = (cfg.chunk_bytes + round_bytes - 1) / round_bytes;
+    const uint32_t rw = (r_full + cfg.waves_per_chunk - 1) / cfg.waves_per_chunk;
+    const auto key = std::make_tuple(cfg.device, cfg.table_mode, cfg.lane_pieces, rw);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        *rc = CKPT_OK;
+        return (const uint32_t *)it->second;
+    }
+    // replicated: the set of the one-wave forms, then the quad form's
+    std::vector<uint32_t> tabs(cfg.table_mode == kTableReplicated ? 2 * kRepWords : kTabTotalWords);
+    if (cfg.table_mode == kTableReplicated) {
+        build_tables_replicated(tabs.data(), rw);
+        build_tables_replicated(tabs.data() + kRepWords, rw, kQuadSkipBytes);
+    } else {
+        build_tables(tabs.data(), cfg.lane_pieces, rw);
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, tabs.size() * 4);
+    if (e == hipSuccess) {
+        e = hipMemcpy(p, tabs.data(), tabs.size() * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(p);
+            p = nullptr;
+        }
+    }
+    if (e != hipSuccess) {
+        *rc = hip_fail(e, "tables", __LINE__);
+        return nullptr;
+    }
+    cache.emplace(key, p);
+    *rc = CKPT_OK;
+    return (const uint32_t *)p;
+}
+
 int ckpt::ctx_setup(ckpt_ctx *ctx)
 {
     const ckpt_config &cfg = ctx->cfg;
@@ -363,11 +408,13 @@ int ckpt::ctx_setup(ckpt_ctx *ctx)
                                       : std::max(1, std::min(lds_fit, 32 / (int)(cfg.block_threads / 64)));
     ctx->grid_chunks = ctx->cu_count * per_cu;
     ctx->grid_small = ctx->cu_count * 4;
-    return CKPT_OK;
+    int rc = CKPT_OK;
+    ctx->tables = shared_tables(cfg, &rc);
+    return rc;
 }
 
-// Streams, events and tables are made on first use, so that contexts that
-// only hold registrations (members of a batch) stay cheap.
+// Streams and events are made on first use, so that contexts that only hold
+// registrations (members of a batch) stay cheap.
 int ckpt::ctx_ready(ckpt_ctx *ctx)
 {
     if (ctx->ready)
@@ -379,19 +426,6 @@ int ckpt::ctx_ready(ckpt_ctx *ctx)
     for (auto &ev : ctx->ev)
         HIP_TRY(hipEventCreate(&ev));
     HIP_TRY(hipEventCreateWithFlags(&ctx->meta_ev, hipEventDisableTiming));
-    const uint32_t round_bytes = kRoundBytes * cfg.lane_pieces;
-    const uint32_t r_full = (cfg.chunk_bytes + round_bytes - 1) / round_bytes;
-    const uint32_t rw = (r_full + cfg.waves_per_chunk - 1) / cfg.waves_per_chunk;
-    // replicated: the set of the one-wave forms, then the quad form's
-    std::vector<uint32_t> tabs(cfg.table_mode == kTableReplicated ? 2 * kRepWords : kTabTotalWords);
-    if (cfg.table_mode == kTableReplicated) {
-        build_tables_replicated(tabs.data(), rw);
-        build_tables_replicated(tabs.data() + kRepWords, rw, kQuadSkipBytes);
-    } else {
-        build_tables(tabs.data(), cfg.lane_pieces, rw);
-    }
-    CKPT_TRY(ctx->d_tables.ensure(tabs.size() * 4));
-    HIP_TRY(hipMemcpy(ctx->d_tables.p, tabs.data(), tabs.size() * 4, hipMemcpyHostToDevice));
     CKPT_TRY(ctx->d_plan.ensure(sizeof(DevPlan)));
     CKPT_TRY(ctx->h_plan.ensure(sizeof(DevPlan)));
     ctx->ready = true;
@@ -624,7 +658,7 @@ ChunkArgs ckpt::chunk_args(ckpt_ctx *ctx)
     memset(&a, 0, sizeof(a));
     a.plan = (const DevPlan *)ctx->d_plan.p;
     a.plan_rw = (DevPlan *)ctx->d_plan.p;
-    a.tables = (const uint32_t *)ctx->d_tables.p;
+    a.tables = ctx->tables;
     if (ctx->cfg.table_mode == kTableReplicated)
         a.tables_quad = a.tables + kRepWords;
     a.C = ctx->cfg.chunk_bytes;
