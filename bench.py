@@ -44,9 +44,7 @@ def parse():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--wpc", type=int, default=0)
     ap.add_argument("--wgs-per-cu", type=int, default=0)
-    ap.add_argument("--lane-pieces", type=int, default=0)
     ap.add_argument("--load-hint", type=int, default=0)
-    ap.add_argument("--table-mode", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed pack steps")
     ap.add_argument("--drain-steps", type=int, default=5)
@@ -71,7 +69,7 @@ def parse():
 def tune_kw(args):
     """Launch-configuration overrides from the command line (0 = library default)."""
     return dict(block_threads=args.block, waves_per_chunk=args.wpc, wgs_per_cu=args.wgs_per_cu,
-                lane_pieces=args.lane_pieces, load_hint=args.load_hint, table_mode=args.table_mode)
+                load_hint=args.load_hint)
 
 
 def profiled_traffic(summary_glob="k_chunks_pack_*.md"):
@@ -736,13 +734,13 @@ def bench_serving(K, synth, torch, args):
                 tk = srv.submit(K.CKPT_REQ_CHECKPOINT, sh["ptrs"], sizes=sh["sizes"], kinds=sh["kinds"])
                 tickets.append((tk, si, None, warm_req))
                 if not warm_req:
-                    offered.append(2 * sh["bytes"])
+                    offered.append(sh["bytes"])
             else:
                 refs[id(img)][1] += 1
                 tk = srv.submit(K.CKPT_REQ_RESTORE, sh["dst"], image=img)
                 tickets.append((tk, si, img, warm_req))
                 if not warm_req:
-                    offered.append(sh["bytes"] + img.info()["serialized_bytes"])
+                    offered.append(sh["bytes"])
             inflight[si] += 1
             still = []
             for entry in tickets:
@@ -756,13 +754,14 @@ def bench_serving(K, synth, torch, args):
             done(entry, srv.wait(entry[0]))
         return srv.stats()
 
-    knee = None
+    knee = p50_first = None
     for lam in [float(x) for x in args.serving_rates.split(",")]:
         fail_status.clear()
         warm_failed.clear()
         offered.clear()
         st = run_rate(lam, args.serving_requests + args.serving_warmup, args.serving_warmup)
-        # offered load: the measured requests' algorithmic bytes at the arrival rate
+        # offered load: the measured requests' live bytes at the arrival rate, the
+        # unit of the server's aggregate GB/s (live bytes of completed requests / makespan)
         offered_gbps = statistics.mean(offered) * lam / 1e9 if offered else 0.0
         res = {"p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
                "mean_ms": round(st["mean_ms"], 2), "completed": st["completed"], "failed": st["failed"],
@@ -774,12 +773,15 @@ def bench_serving(K, synth, torch, args):
         if fail_status or warm_failed:
             res["failed_by_status"] = {K.STATUS_NAMES.get(k, str(k)): v
                                        for k, v in list(fail_status.items()) + list(warm_failed.items())}
-        if knee is None and offered_gbps and st["gbps"] < 0.9 * offered_gbps:
+        if p50_first is None:
+            p50_first = st["p50_ms"]
+        elif knee is None and st["p50_ms"] > 4 * p50_first:
             knee = lam
         out["rates"]["%g" % lam] = res
         log("serving rate %g/s: %s" % (lam, res))
     out["knee_rate"] = knee
-    out["knee_rule"] = "lowest rate whose aggregate GB/s falls below 0.9 x the offered GB/s"
+    out["knee_rule"] = ("lowest rate whose p50 latency exceeds 4 x the lowest rate's: past it requests queue "
+                        "for the host link")
     out["failed_total"] = sum(r["failed"] + r["warmup_failed"] for r in out["rates"].values())
     out["managed_prefetch_to_host"] = bool(prefetch_ok)
     srv.close()

@@ -115,20 +115,19 @@ typedef struct ckpt_config {
                                   (dense image + compact drain buffer); 0 = no cap    */
     uint32_t flags;            /* CKPT_* flags above                                  */
     uint32_t block_threads;    /* threads per workgroup for the chunk kernels:
-                                  64, 128, 256, 512 or 1024; 0: see table_mode        */
+                                  64, 128, 256, 512 or 1024; 0 selects 1024          */
     uint32_t waves_per_chunk;  /* waves that share one chunk (1, 2, 4, 8 or 16,
                                   at most block_threads / 64); 0 selects 1            */
-    uint32_t wgs_per_cu;       /* persistent workgroups per compute unit; 0 = auto    */
-    uint32_t lane_pieces;      /* 16-byte pieces each lane hashes back to back per
-                                  round (1, 2 or 4); 0 selects 1                      */
+    uint32_t wgs_per_cu;       /* persistent workgroups per compute unit; 0 selects 1
+                                  (the LDS tables fit one workgroup per CU)           */
+    uint32_t lane_pieces;      /* 16-byte pieces each lane hashes per round: 1 (0
+                                  selects 1; other values are CKPT_E_INVAL)           */
     uint32_t load_hint;        /* bulk loads/stores: 1 regular, 2 non-temporal;
                                   0 selects 2                                         */
-    uint32_t table_mode;       /* CRC operator tables in LDS: 1 compact (36 KiB, up
-                                  to 4 workgroups per CU), 2 replicated per lane
+    uint32_t table_mode;       /* CRC operator tables in LDS: 2, replicated per lane
                                   (124 KiB, bank-conflict-free lookups, one workgroup
-                                  per CU; lane_pieces 1 only); 0 selects 2 when
-                                  lane_pieces is 1, else 1.  block_threads 0 then
-                                  selects 1024 (replicated) or 256 (compact)          */
+                                  per CU); 0 selects 2, other values are
+                                  CKPT_E_INVAL.  block_threads 0 selects 1024         */
     uint32_t segment_mib;      /* a full checkpoint's drain (gather, then copy to the
                                   host) and a restore's refill (copy to the device,
                                   then scatter) go in segments of about this many MiB,
@@ -572,9 +571,8 @@ typedef struct ckpt_server_config {
                                   0 selects 256 MiB                                     */
     uint32_t max_active;       /* requests admitted at once; 0 selects 16               */
     uint32_t aux_threads;      /* workers that prepare and finish requests; 0 selects 2 */
-    uint32_t block_threads;    /* 0 selects 256                                         */
-    uint32_t lane_pieces;      /* as in ckpt_config; 0 selects 1 (then replicated
-                                  tables and 1024-thread workgroups)                    */
+    uint32_t block_threads;    /* 0 selects 1024                                        */
+    uint32_t lane_pieces;      /* as in ckpt_config: 1 (0 selects 1)                    */
     uint64_t host_budget;      /* pinned host bytes for images (see above); 0 selects
                                   64 GiB                                                */
 } ckpt_server_config;

@@ -37,16 +37,6 @@ static void build_operator(uint32_t *out, uint64_t m)
         }
 }
 
-void build_tables(uint32_t *out, uint32_t G, uint32_t rounds_per_wave)
-{
-    const uint64_t round = (uint64_t)kRoundBytes * G;
-    build_operator(out + kTabChain, 4);
-    build_operator(out + kTabGap, round);   // one round: the lane's next piece is a round later
-    for (int k = 0; k < kTreeLevels; k++)
-        build_operator(out + kTabTree + k * kTabWords, (16ull * G) << k);
-    build_operator(out + kTabSeg, (uint64_t)rounds_per_wave * round);
-}
-
 void build_tables_replicated(uint32_t *out, uint32_t rounds_per_wave, uint32_t gap_bytes)
 {
     std::vector<uint32_t> op(kTabWords);

@@ -11,39 +11,29 @@ namespace ckpt {
 // CRC-32C, reflected form of the Castagnoli polynomial.
 constexpr uint32_t kPolyReflected = 0x82F63B78u;
 
-// Shift-operator tables.  Every table is an operator "feed m zero bytes
-// through the CRC register" stored as 4 x 256 words: S[j][b] is the operator
-// applied to the register value b << 8j, so applying it to v is the XOR of the
-// four entries picked by v's bytes.  The chain step over one 4-byte word w from
-// register s is the 4-byte operator applied to (s ^ w).
-//
-// The chunk kernels read a chunk in rounds: in one round lane l of a wave
-// hashes G consecutive 16-byte pieces (G = lane_pieces), so a round covers
-// 1024 * G bytes.  The operators depend on G and on the rounds per wave:
-constexpr int kTabWords = 1024;                 // one operator, 4 x 256 words
-constexpr int kTabChain = 0;                    // m = 4 (slicing by 4)
-constexpr int kTabGap = 1 * kTabWords;          // m = 1024 G - 16 G: to the lane's next round
-constexpr int kTabTree = 2 * kTabWords;         // m = 16 G << k, k = 0..5: cross-lane tree
-constexpr int kTreeLevels = 6;
-constexpr int kTabSeg = kTabTree + kTreeLevels * kTabWords;  // m = rounds_per_wave * 1024 G:
-                                                              // cross-wave combine
-constexpr int kTabTotalWords = kTabSeg + kTabWords;          // 9 operators, 36 KiB
+// Shift-operator tables.  Every operator "feed m zero bytes through the CRC
+// register" is 4 x 256 words: S[j][b] is the operator applied to the register
+// value b << 8j, so applying it to v is the XOR of the four entries picked by
+// v's bytes.  The chunk kernels read a chunk in rounds of 1 KiB: in one round
+// lane l of a wave hashes the 16-byte piece l of the round.
+constexpr int kTabWords = 1024;     // one operator, 4 x 256 words
+constexpr int kTreeLevels = 6;      // cross-lane tree: m = 16 << k, k = 0..5
+constexpr int kRoundBytes = 1024;   // one wave64 x 16-byte load
 
-constexpr int kRoundBytes = 1024;   // one wave64 x 16-byte load; a round is G of these
-
-// Replicated table set (one 1024-thread workgroup per CU): random-index LDS
-// lookups are bank-conflict free when each lane reads its own copy of an
-// entry.  Byte offsets in LDS:
-//   gap operator, 8 copies:   (j << 13) | (b << 5) | ((lane & 7) << 2)     [0, 32 KiB)
+// The table set staged in LDS (one 1024-thread workgroup per CU):
+// random-index lookups are bank-conflict free when each lane reads its own
+// copy of an entry.  Byte offsets in LDS:
+//   round operator (m = 1024: a lane's register one round later, for the
+//   Horner combine of its per-round registers), 8 copies:
+//                             (j << 13) | (b << 5) | ((lane & 7) << 2)     [0, 32 KiB)
 //   2-byte chain step, 32 copies, both byte positions interleaved:
 //                             32768 + ((b << 8) | (t << 7) | ((lane & 31) << 2))  [32, 96 KiB)
-//   tree and cross-wave operators as in the compact set, from 96 KiB.
+//   from 96 KiB, single copies: the six tree operators, then the cross-wave
+//   operator (m = rounds per wave x 1 KiB).
 constexpr int kRepGapBytes = 32768;
 constexpr int kRepChainOff = 32768;
 constexpr int kRepTreeOff = 98304;                         // bytes
 constexpr int kRepWords = (kRepTreeOff / 4) + (kTreeLevels + 1) * kTabWords;   // 124 KiB
-constexpr int kTableCompact = 1;
-constexpr int kTableReplicated = 2;
 
 // The quad form of the hash-only pass (chunks of at most four rounds): each
 // row of kQuadLanes lanes hashes its own chunk, and lane l of a row reads the
@@ -75,14 +65,12 @@ constexpr uint64_t kNoBase = ~0ull;
 
 struct ChunkArgs {
     const DevPlan *plan;
-    const uint32_t *tables;   // table_words words
-    const uint32_t *tables_quad;   // nullable: the quad form's replicated set
+    const uint32_t *tables;   // kRepWords words
+    const uint32_t *tables_quad;   // nullable: the quad form's set
     uint32_t C;
     uint32_t waves_per_chunk;
-    uint32_t lane_pieces;     // G
     uint32_t nontemporal;     // 1: streaming loads/stores for the bulk data
-    uint32_t table_mode;      // kTableCompact or kTableReplicated
-    uint32_t table_words;     // words of the table set to stage in LDS
+    uint32_t pad1;
     // allocation table (n rows; off and cb have n + 1)
     const uint64_t *src;      // pack/hash: source address of each allocation
     const uint64_t *dst;      // restore: destination address of each allocation
@@ -136,9 +124,7 @@ struct StepRow {
 struct RowArgs {
     const uint32_t *tables;
     uint32_t C;
-    uint32_t lane_pieces;
     uint32_t nontemporal;
-    uint32_t table_mode;
     uint64_t n_items;
     const StepRow *rows;
     const uint32_t *map;   // item -> row
@@ -189,6 +175,8 @@ struct GatherArgs {
     // by segments: chunks [g_begin, g_end) when g_end != 0 (else all chunks
     // of the plan); out holds the serialized bytes from offset soff_base on
     uint64_t g_begin, g_end, soff_base;
+    uint32_t tile;            // chunks per wave step (1 .. 64, a power of two); set by launch_gather
+    uint32_t pad;
 };
 
 // Launch wrappers (kernels.hip).  All return the hipError_t of the launch.
@@ -205,13 +193,10 @@ hipError_t launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t n_words, uint64_
 hipError_t launch_pick_u64(hipStream_t s, const uint64_t *src, const uint64_t *idx, uint64_t *out,
                            uint32_t m);
 
-// Host-side table generation (crc_tables.cpp): fills kTabTotalWords words for
-// a launch with G pieces per lane per round and `rounds_per_wave` consecutive
-// rounds per wave.
-void build_tables(uint32_t *out, uint32_t G, uint32_t rounds_per_wave);
-// The replicated set (kRepWords words; G = 1 only); its gap operator moves
-// the register gap_bytes forward (kRoundBytes, or kQuadSkipBytes for the
-// quad form).
+// Host-side table generation (crc_tables.cpp): the set of kRepWords words
+// for `rounds_per_wave` consecutive rounds per wave; its round operator moves
+// the register gap_bytes forward (kRoundBytes, or kQuadSkipBytes for the quad
+// form).
 void build_tables_replicated(uint32_t *out, uint32_t rounds_per_wave, uint32_t gap_bytes = kRoundBytes);
 // Register after feeding nbytes zero bytes (host, for tests of the tables).
 uint32_t host_shift(uint32_t reg, uint64_t nbytes);

@@ -8,21 +8,20 @@
 // work: no MFMA.  The CRC-32C per chunk is the library's own check.
 //
 // CRC scheme (one wave64 per chunk, or `waves_per_chunk` waves):
-//   * The chunk's bytes are read in rounds of 1024 G bytes: in round r, lane l
-//     loads the G consecutive 16-byte pieces r*64G + l*G .. + G-1 (16-byte
-//     loads; across the wave each load instruction covers whole cache lines
-//     after G instructions).
+//   * The chunk's bytes are read in rounds of 1 KiB: in round r, lane l loads
+//     the 16-byte piece r*64 + l (each load instruction covers 1 KiB of whole
+//     cache lines).
 //   * A chunk of len bytes is placed at the END of a window of whole rounds
 //     (leading zero pieces, and zeros after len up to the next 16 bytes).
 //     Leading zeros leave a zero CRC register unchanged, so the window's raw
 //     CRC (zero init, no final XOR) equals that of the data followed by its
 //     s = roundup16(len) - len zero pad bytes; the pad is undone at the end by
 //     running the register backwards s bytes.
-//   * Each lane folds its pieces into one register with a slicing-by-4 chain
-//     over the words of its G contiguous pieces, moving the register forward
-//     1024 G - 16 G bytes (the gap to its pieces in the next round) first.
+//   * Each lane hashes each round's piece from a zero register (two 2-byte
+//     table steps per 4-byte word) and combines the rounds by Horner's rule
+//     with the one-round operator (1024 - 16 bytes to the lane's next piece).
 //   * A 6-level tree across lanes combines the registers: at level k the left
-//     partner is moved forward 16 G << k bytes and XORed with the right one;
+//     partner is moved forward 16 << k bytes and XORed with the right one;
 //     only the lanes whose result is still needed do the table lookups.
 //   * With several waves per chunk, each wave owns consecutive rounds and the
 //     per-wave results are combined by one more operator.
@@ -31,7 +30,8 @@
 //     the part of the initial value that is still in the register), and the
 //     final XOR is applied last.
 //   Every "move forward m bytes" is a GF(2)-linear operator stored in LDS as
-//   four 256-entry byte tables (crc_tables.cpp).
+//   byte-indexed tables (crc_tables.cpp), the chain and round operators
+//   replicated per lane so that the random lookups are bank-conflict free.
 #include "internal.h"
 
 namespace ckpt {
@@ -44,24 +44,20 @@ __device__ __forceinline__ uint32_t apply_op(const uint32_t *__restrict__ t, uin
            t[768 + (v >> 24)];
 }
 
-// The operator tables as staged in LDS, compact (one copy, 36 KiB) or
-// replicated (per-lane copies of the chain and gap operators, 124 KiB).
-template <bool REP>
+// The operator tables as staged in LDS (124 KiB): per-lane copies of the
+// chain and round operators, single copies of the tree and cross-wave ones.
 struct Tabs {
     const uint32_t *t;   // LDS base
-    uint32_t lb;         // replicated: (lane & 31) << 2, this lane's chain copy
-    uint32_t lb8;        // replicated: (lane & 7) << 2, this lane's gap copy
+    uint32_t lb;         // (lane & 31) << 2, this lane's chain copy
+    uint32_t lb8;        // (lane & 7) << 2, this lane's round-operator copy
 
     __device__ __forceinline__ uint32_t lds(uint32_t byte_off) const
     {
         return *(const uint32_t *)((const uint8_t *)t + byte_off);
     }
-    // register after the 4-byte word w: slicing by 4 (compact) or two 2-byte
-    // steps (replicated)
+    // register after the 4-byte word w: two 2-byte steps
     __device__ __forceinline__ uint32_t chain(uint32_t s, uint32_t w) const
     {
-        if (!REP)
-            return apply_op(t + kTabChain, s ^ w);
         uint32_t y = s ^ w;
 #pragma unroll
         for (int h = 0; h < 2; h++) {
@@ -71,28 +67,25 @@ struct Tabs {
         }
         return y;
     }
-    // the register moved one round (kRoundBytes * G bytes) forward
+    // the register moved one round (or, in the quad form's set, the skip) forward
     __device__ __forceinline__ uint32_t gap(uint32_t v) const
     {
-        if (!REP)
-            return apply_op(t + kTabGap, v);
         return lds(((v & 0xffu) << 5) | lb8) ^ lds(8192 + ((((v >> 8) & 0xffu) << 5) | lb8)) ^
                lds(16384 + ((((v >> 16) & 0xffu) << 5) | lb8)) ^ lds(24576 + (((v >> 24) << 5) | lb8));
     }
     __device__ __forceinline__ uint32_t tree(int k, uint32_t v) const
     {
-        return apply_op(t + (REP ? kRepTreeOff / 4 : kTabTree) + k * kTabWords, v);
+        return apply_op(t + kRepTreeOff / 4 + k * kTabWords, v);
     }
     __device__ __forceinline__ uint32_t seg(uint32_t v) const
     {
-        return apply_op(t + (REP ? kRepTreeOff / 4 + kTreeLevels * kTabWords : kTabSeg), v);
+        return apply_op(t + kRepTreeOff / 4 + kTreeLevels * kTabWords, v);
     }
 };
 
-template <bool REP>
-__device__ __forceinline__ Tabs<REP> make_tabs(const uint32_t *lds_tabs, int lane)
+__device__ __forceinline__ Tabs make_tabs(const uint32_t *lds_tabs, int lane)
 {
-    Tabs<REP> T;
+    Tabs T;
     T.t = lds_tabs;
     T.lb = (uint32_t)(lane & 31) << 2;
     T.lb8 = (uint32_t)(lane & 7) << 2;
@@ -318,8 +311,7 @@ __device__ __forceinline__ uint32_t dpp_down(uint32_t v)
 // be active.
 static_assert(kTreeLevels == 6, "the combine is written out for 64 lanes");
 
-template <bool REP>
-__device__ __forceinline__ uint32_t wave_combine(const Tabs<REP> &T, uint32_t acc, int lane)
+__device__ __forceinline__ uint32_t wave_combine(const Tabs &T, uint32_t acc, int lane)
 {
     uint32_t right = dpp_down<1>(acc);
     if ((lane & 1) == 0)
@@ -342,52 +334,49 @@ __device__ __forceinline__ uint32_t wave_combine(const Tabs<REP> &T, uint32_t ac
     return acc;
 }
 
+// The lane's register after one 16-byte piece, chained from register c.
+__device__ __forceinline__ uint32_t chain_piece(const Tabs &T, uint32_t c, const uint4 &v)
+{
+    c = T.chain(c, v.x);
+    c = T.chain(c, v.y);
+    c = T.chain(c, v.z);
+    return T.chain(c, v.w);
+}
 
+constexpr int kPerRound = 64;   // 16-byte pieces per round (one per lane)
 
 // One wave's share of a chunk: rounds [r_begin, r_end) of a window of r_win
-// rounds of 1024 G bytes.  Returns the raw register of those rounds in lane 0
-// (as a message ending with the wave's last round) and ORs the data words
-// into *orv.
-template <int MODE, int G, bool NT, bool REP>
-__device__ __forceinline__ uint32_t wave_rounds(const Tabs<REP> &T, const Desc &d, int lane,
-                                                uint32_t r_begin, uint32_t r_end, uint32_t r_win,
-                                                uint32_t *orv)
+// rounds of 1 KiB.  Returns the raw register of those rounds in lane 0 (as a
+// message ending with the wave's last round) and ORs the data words into
+// *orv.
+template <int MODE, bool NT>
+__device__ __forceinline__ uint32_t wave_rounds(const Tabs &T, const Desc &d, int lane, uint32_t r_begin,
+                                                uint32_t r_end, uint32_t r_win, uint32_t *orv)
 {
-    constexpr int B = kLoadsInFlight / G > 0 ? kLoadsInFlight / G : 1;   // rounds per batch
-    constexpr uint32_t per_round = 64 * G;                                // pieces per round
+    constexpr int B = kLoadsInFlight;                                     // rounds per batch
     const uint32_t np = (d.len + 15) >> 4;                                // data pieces
-    const uint32_t z = r_win * per_round - np;                            // leading zero pieces
-    if (d.len == r_win * per_round * 16 && (MODE != kModeRestore || !d.zero)) {
+    const uint32_t z = r_win * kPerRound - np;                            // leading zero pieces
+    if (d.len == r_win * kPerRound * 16 && (MODE != kModeRestore || !d.zero)) {
         // The chunk fills the window exactly (uniform over the wave): every
-        // piece is 16 bytes of data at offset (r * per_round + lane * G + j) * 16
-        // and only piece 0 carries the complemented init.
+        // piece is 16 bytes of data at offset (r * 64 + lane) * 16 and only
+        // piece 0 carries the complemented init.
         uint32_t acc = 0, o = 0;
         for (uint32_t rb = r_begin; rb < r_end; rb += B) {
-            uint4 v[B][G];
+            uint4 v[B];
 #pragma unroll
             for (int b = 0; b < B; b++)
-#pragma unroll
-                for (int j = 0; j < G; j++)
-                    v[b][j] = rb + b < r_end
-                                  ? ld16<NT>((const uint8_t *)d.src + ((rb + b) * per_round + lane * G + j) * 16)
-                                  : make_uint4(0u, 0u, 0u, 0u);
+                v[b] = rb + b < r_end ? ld16<NT>((const uint8_t *)d.src + ((rb + b) * kPerRound + lane) * 16)
+                                      : make_uint4(0u, 0u, 0u, 0u);
             uint32_t c[B];
 #pragma unroll
             for (int b = 0; b < B; b++) {
                 const uint32_t r = rb + b;
-                c[b] = 0;
-#pragma unroll
-                for (int j = 0; j < G; j++) {
-                    if (MODE != kModeHash && r < r_end)
-                        st16<NT>((uint8_t *)d.dst + (r * per_round + lane * G + j) * 16, v[b][j]);
-                    o |= v[b][j].x | v[b][j].y | v[b][j].z | v[b][j].w;
-                    if (r == 0 && j == 0 && lane == 0)
-                        v[b][j].x = ~v[b][j].x;
-                    c[b] = T.chain(c[b], v[b][j].x);
-                    c[b] = T.chain(c[b], v[b][j].y);
-                    c[b] = T.chain(c[b], v[b][j].z);
-                    c[b] = T.chain(c[b], v[b][j].w);
-                }
+                if (MODE != kModeHash && r < r_end)
+                    st16<NT>((uint8_t *)d.dst + (r * kPerRound + lane) * 16, v[b]);
+                o |= v[b].x | v[b].y | v[b].z | v[b].w;
+                if (r == 0 && lane == 0)
+                    v[b].x = ~v[b].x;
+                c[b] = chain_piece(T, 0u, v[b]);
             }
 #pragma unroll
             for (int b = 0; b < B; b++) {
@@ -396,23 +385,21 @@ __device__ __forceinline__ uint32_t wave_rounds(const Tabs<REP> &T, const Desc &
                     acc = (r > r_begin ? T.gap(acc) : 0u) ^ c[b];
             }
         }
-        acc = wave_combine<REP>(T, acc, lane);
+        acc = wave_combine(T, acc, lane);
         *orv = o;
         return acc;
     }
-    const uint32_t r0 = max(r_begin, z / per_round);                      // earlier rounds: all zero
+    const uint32_t r0 = max(r_begin, z / kPerRound);                      // earlier rounds: all zero
     uint32_t acc = 0, o = 0;
     for (uint32_t rb = r0; rb < r_end; rb += B) {
-        uint4 v[B][G];
+        uint4 v[B];
 #pragma unroll
-        for (int b = 0; b < B; b++)
-#pragma unroll
-            for (int j = 0; j < G; j++) {
-                const int p = (int)((rb + b) * per_round + lane * G + j) - (int)z;
-                v[b][j] = make_uint4(0u, 0u, 0u, 0u);
-                if (rb + b < r_end && p >= 0)
-                    v[b][j] = load_piece<MODE, NT>(d, (uint32_t)p * 16);
-            }
+        for (int b = 0; b < B; b++) {
+            const int p = (int)((rb + b) * kPerRound + lane) - (int)z;
+            v[b] = make_uint4(0u, 0u, 0u, 0u);
+            if (rb + b < r_end && p >= 0)
+                v[b] = load_piece<MODE, NT>(d, (uint32_t)p * 16);
+        }
         // Each round's contribution is chained from a zero register, so the
         // rounds' lookups are independent; they are combined by Horner's rule
         // with the one-round shift.  Pieces past r_end are zero and add nothing.
@@ -420,20 +407,13 @@ __device__ __forceinline__ uint32_t wave_rounds(const Tabs<REP> &T, const Desc &
 #pragma unroll
         for (int b = 0; b < B; b++) {
             const uint32_t r = rb + b;
-            c[b] = 0;
-#pragma unroll
-            for (int j = 0; j < G; j++) {
-                const int p = (int)(r * per_round + lane * G + j) - (int)z;
-                if (r < r_end && p >= 0)
-                    store_piece<MODE, NT>(d, (uint32_t)p * 16, v[b][j]);
-                o |= v[b][j].x | v[b][j].y | v[b][j].z | v[b][j].w;
-                if (p == 0)
-                    v[b][j].x ^= init_mask(d.len);
-                c[b] = T.chain(c[b], v[b][j].x);
-                c[b] = T.chain(c[b], v[b][j].y);
-                c[b] = T.chain(c[b], v[b][j].z);
-                c[b] = T.chain(c[b], v[b][j].w);
-            }
+            const int p = (int)(r * kPerRound + lane) - (int)z;
+            if (r < r_end && p >= 0)
+                store_piece<MODE, NT>(d, (uint32_t)p * 16, v[b]);
+            o |= v[b].x | v[b].y | v[b].z | v[b].w;
+            if (p == 0)
+                v[b].x ^= init_mask(d.len);
+            c[b] = chain_piece(T, 0u, v[b]);
         }
 #pragma unroll
         for (int b = 0; b < B; b++) {
@@ -442,114 +422,88 @@ __device__ __forceinline__ uint32_t wave_rounds(const Tabs<REP> &T, const Desc &
                 acc = (r > r0 ? T.gap(acc) : 0u) ^ c[b];
         }
     }
-    acc = wave_combine<REP>(T, acc, lane);
+    acc = wave_combine(T, acc, lane);
     *orv = o;
     return acc;
 }
 
-// Chunks of at most one batch of rounds (r_win <= kLoadsInFlight / G, one
-// wave per chunk): the same steps as wave_rounds, split into the loads and the
+// Chunks of at most one batch of rounds (r_win <= kLoadsInFlight, one wave
+// per chunk): the same steps as wave_rounds, split into the loads and the
 // rest, so that a wave can have the next chunk's loads in flight while it
 // hashes, combines and finishes the current one.
-template <int MODE, int G, bool NT>
-__device__ __forceinline__ void small_loads(const Desc &d, int lane, uint32_t r_win, uint4 (&v)[kLoadsInFlight / G][G])
+template <int MODE, bool NT>
+__device__ __forceinline__ void small_loads(const Desc &d, int lane, uint32_t r_win, uint4 (&v)[kLoadsInFlight])
 {
-    constexpr int B = kLoadsInFlight / G;
-    constexpr uint32_t per_round = 64 * G;
     const uint32_t np = (d.len + 15) >> 4;
-    const uint32_t z = r_win * per_round - np;
-    if (d.len == r_win * per_round * 16 && (MODE != kModeRestore || !d.zero)) {
+    const uint32_t z = r_win * kPerRound - np;
+    if (d.len == r_win * kPerRound * 16 && (MODE != kModeRestore || !d.zero)) {
         // the chunk fills the window exactly (uniform over the wave): every
         // piece is 16 bytes of data
 #pragma unroll
-        for (int b = 0; b < B; b++)
-#pragma unroll
-            for (int j = 0; j < G; j++)
-                v[b][j] = (uint32_t)b < r_win
-                              ? ld16<NT>((const uint8_t *)d.src + ((uint32_t)b * per_round + lane * G + j) * 16)
-                              : make_uint4(0u, 0u, 0u, 0u);
+        for (int b = 0; b < kLoadsInFlight; b++)
+            v[b] = (uint32_t)b < r_win ? ld16<NT>((const uint8_t *)d.src + ((uint32_t)b * kPerRound + lane) * 16)
+                                       : make_uint4(0u, 0u, 0u, 0u);
         return;
     }
-    const uint32_t r0 = z / per_round;
+    const uint32_t r0 = z / kPerRound;
 #pragma unroll
-    for (int b = 0; b < B; b++)
-#pragma unroll
-        for (int j = 0; j < G; j++) {
-            const int p = (int)((r0 + b) * per_round + lane * G + j) - (int)z;
-            v[b][j] = make_uint4(0u, 0u, 0u, 0u);
-            if (r0 + b < r_win && p >= 0)
-                v[b][j] = load_piece<MODE, NT>(d, (uint32_t)p * 16);
-        }
+    for (int b = 0; b < kLoadsInFlight; b++) {
+        const int p = (int)((r0 + b) * kPerRound + lane) - (int)z;
+        v[b] = make_uint4(0u, 0u, 0u, 0u);
+        if (r0 + b < r_win && p >= 0)
+            v[b] = load_piece<MODE, NT>(d, (uint32_t)p * 16);
+    }
 }
 
-template <int MODE, int G, bool NT, bool REP>
-__device__ __forceinline__ uint32_t small_rest(const Tabs<REP> &T, const Desc &d, int lane, uint32_t r_win,
-                                               uint4 (&v)[kLoadsInFlight / G][G], uint32_t *orv)
+template <int MODE, bool NT>
+__device__ __forceinline__ uint32_t small_rest(const Tabs &T, const Desc &d, int lane, uint32_t r_win,
+                                               uint4 (&v)[kLoadsInFlight], uint32_t *orv)
 {
-    constexpr int B = kLoadsInFlight / G;
-    constexpr uint32_t per_round = 64 * G;
+    constexpr int B = kLoadsInFlight;
     const uint32_t np = (d.len + 15) >> 4;
-    const uint32_t z = r_win * per_round - np;
-    if (d.len == r_win * per_round * 16) {
+    const uint32_t z = r_win * kPerRound - np;
+    if (d.len == r_win * kPerRound * 16) {
         // The chunk fills the window exactly (uniform over the wave): every
         // piece is 16 bytes of data, and only lane 0's first piece carries the
         // complemented init (the chunk is at least 16 bytes long).
         uint32_t acc = 0, o = 0, c[B];
 #pragma unroll
         for (int b = 0; b < B; b++) {
-            c[b] = 0;
-#pragma unroll
-            for (int j = 0; j < G; j++) {
-                const uint32_t off = ((uint32_t)b * per_round + lane * G + j) * 16;
-                if ((uint32_t)b < r_win) {
-                    if (MODE == kModePack)
-                        st16<NT>((uint8_t *)d.dst + off, v[b][j]);
-                    else if (MODE == kModeRestore)
-                        st16<NT>((uint8_t *)d.dst + off, v[b][j]);
-                }
-                o |= v[b][j].x | v[b][j].y | v[b][j].z | v[b][j].w;
-                if (b == 0 && j == 0 && lane == 0)
-                    v[b][j].x = ~v[b][j].x;
-                c[b] = T.chain(c[b], v[b][j].x);
-                c[b] = T.chain(c[b], v[b][j].y);
-                c[b] = T.chain(c[b], v[b][j].z);
-                c[b] = T.chain(c[b], v[b][j].w);
-            }
+            const uint32_t off = ((uint32_t)b * kPerRound + lane) * 16;
+            if (MODE != kModeHash && (uint32_t)b < r_win)
+                st16<NT>((uint8_t *)d.dst + off, v[b]);
+            o |= v[b].x | v[b].y | v[b].z | v[b].w;
+            if (b == 0 && lane == 0)
+                v[b].x = ~v[b].x;
+            c[b] = chain_piece(T, 0u, v[b]);
         }
 #pragma unroll
         for (int b = 0; b < B; b++)
             if ((uint32_t)b < r_win)
                 acc = (b > 0 ? T.gap(acc) : 0u) ^ c[b];
-        acc = wave_combine<REP>(T, acc, lane);
+        acc = wave_combine(T, acc, lane);
         *orv = o;
         return acc;
     }
-    const uint32_t r0 = z / per_round;
+    const uint32_t r0 = z / kPerRound;
     uint32_t acc = 0, o = 0, c[B];
     // independent per-round chains, then Horner's rule (as in wave_rounds)
 #pragma unroll
     for (int b = 0; b < B; b++) {
         const uint32_t r = r0 + b;
-        c[b] = 0;
-#pragma unroll
-        for (int j = 0; j < G; j++) {
-            const int p = (int)(r * per_round + lane * G + j) - (int)z;
-            if (r < r_win && p >= 0)
-                store_piece<MODE, NT>(d, (uint32_t)p * 16, v[b][j]);
-            o |= v[b][j].x | v[b][j].y | v[b][j].z | v[b][j].w;
-            if (p == 0)
-                v[b][j].x ^= init_mask(d.len);
-            c[b] = T.chain(c[b], v[b][j].x);
-            c[b] = T.chain(c[b], v[b][j].y);
-            c[b] = T.chain(c[b], v[b][j].z);
-            c[b] = T.chain(c[b], v[b][j].w);
-        }
+        const int p = (int)(r * kPerRound + lane) - (int)z;
+        if (r < r_win && p >= 0)
+            store_piece<MODE, NT>(d, (uint32_t)p * 16, v[b]);
+        o |= v[b].x | v[b].y | v[b].z | v[b].w;
+        if (p == 0)
+            v[b].x ^= init_mask(d.len);
+        c[b] = chain_piece(T, 0u, v[b]);
     }
 #pragma unroll
     for (int b = 0; b < B; b++)
         if (r0 + b < r_win)
             acc = (b > 0 ? T.gap(acc) : 0u) ^ c[b];
-    acc = wave_combine<REP>(T, acc, lane);
+    acc = wave_combine(T, acc, lane);
     *orv = o;
     return acc;
 }
@@ -706,7 +660,7 @@ __device__ __forceinline__ void quad_loads(const Desc &d, bool valid, bool exact
 
 // Chains round b's pieces into the lane's register (T is the quad table set:
 // its gap operator is the skip) and ORs their data words into *o.
-__device__ __forceinline__ void quad_hash(const Tabs<true> &T, const Desc &d, bool valid, bool exact, int lr,
+__device__ __forceinline__ void quad_hash(const Tabs &T, const Desc &d, bool valid, bool exact, int lr,
                                           uint32_t r_win, uint32_t b, uint4 (&v)[kQuadPieces], uint32_t *acc,
                                           uint32_t *o)
 {
@@ -739,7 +693,7 @@ __device__ __forceinline__ void quad_hash(const Tabs<true> &T, const Desc &d, bo
 // The row's 16 registers combined into the row's lane 0 (DPP row shifts):
 // at level k, lane i moves its register past the 16 << k bytes of lane
 // i + 2^k's pieces and adds that lane's register.
-__device__ __forceinline__ uint32_t quad_combine(const Tabs<true> &T, uint32_t acc, int lane)
+__device__ __forceinline__ uint32_t quad_combine(const Tabs &T, uint32_t acc, int lane)
 {
     uint32_t right = dpp_down<1>(acc);
     if ((lane & 1) == 0)
@@ -764,10 +718,10 @@ constexpr int kFormWave = 0;
 constexpr int kFormSmall = 1;
 constexpr int kFormQuad = 2;
 
-template <int MODE, int G, bool NT, bool REP, int FORM = kFormWave>
+template <int MODE, bool NT, int FORM = kFormWave>
 __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
 {
-    __shared__ uint32_t tabs[REP ? kRepWords : kTabTotalWords];
+    __shared__ uint32_t tabs[kRepWords];
     // two descriptor tiles: the first wave loads the next tile's descriptors
     // while the workgroup works on the current one
     constexpr int kDescTile = FORM == kFormQuad ? kQuadTile : kTile;
@@ -775,18 +729,16 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
     __shared__ uint32_t s_part[16];
     __shared__ uint32_t s_nz[16];
 
-    constexpr int kWords = REP ? kRepWords : kTabTotalWords;
-    for (int i = threadIdx.x; i < kWords; i += blockDim.x)
+    for (int i = threadIdx.x; i < kRepWords; i += blockDim.x)
         tabs[i] = a.tables[i];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const Tabs<REP> T = make_tabs<REP>(tabs, lane);
+    const Tabs T = make_tabs(tabs, lane);
     const int nwaves = blockDim.x >> 6;
     const int W = a.waves_per_chunk;
     const int groups = nwaves / W, group = wave / W, wig = wave % W;
     const uint32_t C = a.C;
-    const uint32_t round_bytes = kRoundBytes * G;
-    const uint32_t r_full = (C + round_bytes - 1) / round_bytes;
+    const uint32_t r_full = (C + kRoundBytes - 1) / kRoundBytes;
     const uint32_t rw = (r_full + W - 1) / W;            // rounds per wave
     const uint32_t r_win = rw * W;
     const uint64_t M = (MODE != kModeRestore) ? a.plan->n_chunks
@@ -816,7 +768,7 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
             nd = make_desc<MODE>(a, n0 + threadIdx.x, C);   // loads in flight during the tile
         const int cnt = (int)(hi - g0);   // uniform over the workgroup, at most tile
         if constexpr (FORM == kFormQuad) {
-            static_assert(MODE == kModeHash && REP && G == 1, "the quad form hashes with the replicated tables");
+            static_assert(MODE == kModeHash, "the quad form only hashes");
             // This wave's quads of the tile, round by round: the next round's
             // loads (of this quad, or the first of the next) are in flight
             // while the current round is hashed.
@@ -861,29 +813,27 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
         } else if constexpr (FORM == kFormSmall) {
             // one batch per chunk: the next chunk's loads go out before this
             // chunk is hashed, combined and finished
-            uint4 cur[kLoadsInFlight / G][G], nxt[kLoadsInFlight / G][G];
+            uint4 cur[kLoadsInFlight], nxt[kLoadsInFlight];
             Desc dn;
             if (group < cnt) {
                 dn = desc[buf][group];
-                small_loads<MODE, G, NT>(dn, lane, r_win, nxt);
+                small_loads<MODE, NT>(dn, lane, r_win, nxt);
             }
             for (int t = group; t < cnt; t += groups) {
                 const Desc d = dn;
 #pragma unroll
-                for (int b = 0; b < kLoadsInFlight / G; b++)
-#pragma unroll
-                    for (int j = 0; j < G; j++)
-                        cur[b][j] = nxt[b][j];
+                for (int b = 0; b < kLoadsInFlight; b++)
+                    cur[b] = nxt[b];
                 if (t + groups < cnt) {
                     dn = desc[buf][t + groups];
-                    small_loads<MODE, G, NT>(dn, lane, r_win, nxt);
+                    small_loads<MODE, NT>(dn, lane, r_win, nxt);
                 }
                 if (MODE == kModeRestore && d.zero && d.len == C) {   // uniform over the wave
                     restore_zero_chunk<NT>(a, d, lane);
                     continue;
                 }
                 uint32_t orv = 0;
-                const uint32_t raw = small_rest<MODE, G, NT, REP>(T, d, lane, r_win, cur, &orv);
+                const uint32_t raw = small_rest<MODE, NT>(T, d, lane, r_win, cur, &orv);
                 const bool nonzero = __ballot(orv != 0) != 0;
                 if (lane == 0)
                     finish_chunk<MODE>(a, d, raw, nonzero);
@@ -900,7 +850,7 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
                     restore_zero_chunk<NT>(a, d, lane);
                     continue;
                 }
-                raw = wave_rounds<MODE, G, NT, REP>(T, d, lane, wig * rw, (wig + 1) * rw, r_win, &orv);
+                raw = wave_rounds<MODE, NT>(T, d, lane, wig * rw, (wig + 1) * rw, r_win, &orv);
             }
             const bool nonzero = __ballot(orv != 0) != 0;
             if (W == 1) {
@@ -973,21 +923,19 @@ __device__ __forceinline__ RowDesc make_row_desc(const RowArgs &a, uint64_t i, u
     return r;
 }
 
-template <int G, bool NT, bool REP>
+template <bool NT>
 __global__ __launch_bounds__(1024) void k_rows(RowArgs a)
 {
-    __shared__ uint32_t tabs[REP ? kRepWords : kTabTotalWords];
+    __shared__ uint32_t tabs[kRepWords];
     __shared__ RowDesc desc[2][kTile];
 
-    constexpr int kWords = REP ? kRepWords : kTabTotalWords;
-    for (int i = threadIdx.x; i < kWords; i += blockDim.x)
+    for (int i = threadIdx.x; i < kRepWords; i += blockDim.x)
         tabs[i] = a.tables[i];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const Tabs<REP> T = make_tabs<REP>(tabs, lane);
+    const Tabs T = make_tabs(tabs, lane);
     const int nwaves = blockDim.x >> 6;
     const uint32_t C = a.C;
-    const uint32_t round_bytes = kRoundBytes * G;
-    const uint32_t r_win = (C + round_bytes - 1) / round_bytes;
+    const uint32_t r_win = (C + kRoundBytes - 1) / kRoundBytes;
     const uint64_t M = a.n_items;
 
     // Balanced interleaved rounds and double-buffered descriptors, as in k_chunks.
@@ -1014,9 +962,9 @@ __global__ __launch_bounds__(1024) void k_rows(RowArgs a)
             const RowDesc rd = desc[buf][t];
             uint32_t raw, orv;
             if (rd.mode == kModeRestore)
-                raw = wave_rounds<kModeRestore, G, NT, REP>(T, rd.d, lane, 0, r_win, r_win, &orv);
+                raw = wave_rounds<kModeRestore, NT>(T, rd.d, lane, 0, r_win, r_win, &orv);
             else
-                raw = wave_rounds<kModePack, G, NT, REP>(T, rd.d, lane, 0, r_win, r_win, &orv);
+                raw = wave_rounds<kModePack, NT>(T, rd.d, lane, 0, r_win, r_win, &orv);
             const bool nonzero = __ballot(orv != 0) != 0;
             if (lane == 0) {
                 const uint32_t crc = finish_crc(raw, rd.d.len);
@@ -1197,10 +1145,11 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_down(SelArgs a)
 //
 // Copies each selected chunk (roundup16(len) bytes) to out + soff[g], from the
 // dense image or straight from the allocation (zero pad written, never read).
-// Each wave takes 64 consecutive chunks: lane l fetches the descriptor of
-// chunk t0 + l, so the descriptor loads of all 64 are in flight together.
-// The wave then copies its selected chunks one after the other (their
-// addresses read from the owning lane), each lane issuing up to
+// Each wave takes `tile` consecutive chunks (up to 64, fewer when a launch
+// covers few chunks, so that every wave of the grid has work): lane l fetches
+// the descriptor of chunk t0 + l, so the descriptor loads are in flight
+// together.  The wave then copies its selected chunks one after the other
+// (their addresses read from the owning lane), each lane issuing up to
 // kGatherLoads 16-byte loads before its first store.
 
 constexpr int kGatherLoads = 8;
@@ -1244,12 +1193,13 @@ __global__ __launch_bounds__(1024) void k_gather(GatherArgs a)
     const int lane = threadIdx.x & 63;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    for (uint64_t t0 = a.g_begin + wave * 64; t0 < N; t0 += waves * 64) {
+    const uint32_t tile = a.tile;
+    for (uint64_t t0 = a.g_begin + wave * tile; t0 < N; t0 += waves * tile) {
         const uint64_t g = t0 + lane;
         bool take = false;
         uint64_t src = 0, dst = 0;
         uint32_t len = 0;
-        if (g < N) {
+        if ((uint32_t)lane < tile && g < N) {
             const uint8_t f = a.flags[g];
             const uint32_t k = a.map[g];
             const uint64_t so = a.soff[g];
@@ -1302,59 +1252,36 @@ hipError_t launch_chunk_map(hipStream_t s, const DevPlan *plan, const uint64_t *
     return hipGetLastError();
 }
 
-template <int MODE, int G>
-static void launch_chunks_g(hipStream_t s, const ChunkArgs &a, int grid, int block)
-{
-    if (a.nontemporal)
-        hipLaunchKernelGGL((k_chunks<MODE, G, true, false>), dim3(grid), dim3(block), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_chunks<MODE, G, false, false>), dim3(grid), dim3(block), 0, s, a);
-}
-
 template <int MODE>
 static void launch_chunks_m(hipStream_t s, const ChunkArgs &a, int grid, int block)
 {
-    if (a.table_mode == kTableReplicated) {     // G = 1 only
-        const uint32_t rounds = (a.C + kRoundBytes - 1) / kRoundBytes;
-        // hash-only chunks of at most 4 KiB: four chunks per wave
-        if (MODE == kModeHash && a.tables_quad && a.waves_per_chunk == 1 && rounds <= kQuadMaxRounds) {
-            ChunkArgs q = a;
-            q.tables = a.tables_quad;
-            if (a.nontemporal)
-                hipLaunchKernelGGL((k_chunks<kModeHash, 1, true, true, kFormQuad>), dim3(grid), dim3(block), 0, s, q);
-            else
-                hipLaunchKernelGGL((k_chunks<kModeHash, 1, false, true, kFormQuad>), dim3(grid), dim3(block), 0, s,
-                                   q);
-            return;
-        }
-        // one wave per chunk and one batch of rounds per chunk: the pipelined form
-        const bool small = a.waves_per_chunk == 1 && rounds <= kLoadsInFlight;
-        if (small) {
-            if (a.nontemporal)
-                hipLaunchKernelGGL((k_chunks<MODE, 1, true, true, kFormSmall>), dim3(grid), dim3(block), 0, s, a);
-            else
-                hipLaunchKernelGGL((k_chunks<MODE, 1, false, true, kFormSmall>), dim3(grid), dim3(block), 0, s, a);
-        } else if (a.nontemporal) {
-            hipLaunchKernelGGL((k_chunks<MODE, 1, true, true>), dim3(grid), dim3(block), 0, s, a);
-        } else {
-            hipLaunchKernelGGL((k_chunks<MODE, 1, false, true>), dim3(grid), dim3(block), 0, s, a);
-        }
+    const uint32_t rounds = (a.C + kRoundBytes - 1) / kRoundBytes;
+    // hash-only chunks of at most 4 KiB: four chunks per wave
+    if (MODE == kModeHash && a.tables_quad && a.waves_per_chunk == 1 && rounds <= kQuadMaxRounds) {
+        ChunkArgs q = a;
+        q.tables = a.tables_quad;
+        if (a.nontemporal)
+            hipLaunchKernelGGL((k_chunks<kModeHash, true, kFormQuad>), dim3(grid), dim3(block), 0, s, q);
+        else
+            hipLaunchKernelGGL((k_chunks<kModeHash, false, kFormQuad>), dim3(grid), dim3(block), 0, s, q);
         return;
     }
-    switch (a.lane_pieces) {
-    case 1: launch_chunks_g<MODE, 1>(s, a, grid, block); break;
-    case 2: launch_chunks_g<MODE, 2>(s, a, grid, block); break;
-    default: launch_chunks_g<MODE, 4>(s, a, grid, block); break;
+    // one wave per chunk and one batch of rounds per chunk: the pipelined form
+    const bool small = a.waves_per_chunk == 1 && rounds <= kLoadsInFlight;
+    if (small) {
+        if (a.nontemporal)
+            hipLaunchKernelGGL((k_chunks<MODE, true, kFormSmall>), dim3(grid), dim3(block), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_chunks<MODE, false, kFormSmall>), dim3(grid), dim3(block), 0, s, a);
+    } else if (a.nontemporal) {
+        hipLaunchKernelGGL((k_chunks<MODE, true>), dim3(grid), dim3(block), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_chunks<MODE, false>), dim3(grid), dim3(block), 0, s, a);
     }
 }
 
 hipError_t launch_chunks(hipStream_t s, int mode, const ChunkArgs &a, int grid, int block)
 {
-    if (a.lane_pieces != 1 && a.lane_pieces != 2 && a.lane_pieces != 4)
-        return hipErrorInvalidValue;
-    if (a.table_mode == kTableReplicated ? (a.lane_pieces != 1 || a.table_words != kRepWords)
-                                         : a.table_words != kTabTotalWords)
-        return hipErrorInvalidValue;
     switch (mode) {
     case kModePack: launch_chunks_m<kModePack>(s, a, grid, block); break;
     case kModeHash: launch_chunks_m<kModeHash>(s, a, grid, block); break;
@@ -1365,30 +1292,10 @@ hipError_t launch_chunks(hipStream_t s, int mode, const ChunkArgs &a, int grid, 
 
 hipError_t launch_rows(hipStream_t s, const RowArgs &a, int grid, int block)
 {
-    const bool nt = a.nontemporal;
-    if (a.table_mode == kTableReplicated) {
-        if (a.lane_pieces != 1)
-            return hipErrorInvalidValue;
-        if (nt) hipLaunchKernelGGL((k_rows<1, true, true>), dim3(grid), dim3(block), 0, s, a);
-        else hipLaunchKernelGGL((k_rows<1, false, true>), dim3(grid), dim3(block), 0, s, a);
-        return hipGetLastError();
-    }
-    switch (a.lane_pieces) {
-    case 1:
-        if (nt) hipLaunchKernelGGL((k_rows<1, true, false>), dim3(grid), dim3(block), 0, s, a);
-        else hipLaunchKernelGGL((k_rows<1, false, false>), dim3(grid), dim3(block), 0, s, a);
-        break;
-    case 2:
-        if (nt) hipLaunchKernelGGL((k_rows<2, true, false>), dim3(grid), dim3(block), 0, s, a);
-        else hipLaunchKernelGGL((k_rows<2, false, false>), dim3(grid), dim3(block), 0, s, a);
-        break;
-    case 4:
-        if (nt) hipLaunchKernelGGL((k_rows<4, true, false>), dim3(grid), dim3(block), 0, s, a);
-        else hipLaunchKernelGGL((k_rows<4, false, false>), dim3(grid), dim3(block), 0, s, a);
-        break;
-    default:
-        return hipErrorInvalidValue;
-    }
+    if (a.nontemporal)
+        hipLaunchKernelGGL((k_rows<true>), dim3(grid), dim3(block), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_rows<false>), dim3(grid), dim3(block), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1408,8 +1315,17 @@ hipError_t launch_select(hipStream_t s, const SelArgs &a, uint64_t max_items)
     return hipGetLastError();
 }
 
-hipError_t launch_gather(hipStream_t s, const GatherArgs &a, int grid)
+hipError_t launch_gather(hipStream_t s, const GatherArgs &a_in, int grid)
 {
+    GatherArgs a = a_in;
+    // a launch over a chunk range gives every wave of the grid at least one
+    // tile; without a range (all chunks of the plan) the tile is 64
+    a.tile = 64;
+    if (a.g_end) {
+        const uint64_t per_wave = (a.g_end - a.g_begin) / ((uint64_t)grid * 16);
+        while (a.tile > 1 && a.tile > per_wave)
+            a.tile >>= 1;
+    }
     // stores into pinned host memory (the direct drain) keep the default policy
     if (a.out_host)
         hipLaunchKernelGGL(k_gather<false>, dim3(grid), dim3(1024), 0, s, a);

@@ -14,7 +14,6 @@
 #include <mutex>
 #include <string>
 #include <thread>
-#include <tuple>
 #include <vector>
 
 #include "ckpt.h"
@@ -307,16 +306,20 @@ extern "C" int ckpt_init(const ckpt_config *cfg_in, ckpt_ctx **out)
         cfg.chunk_bytes = 4096;
     if (cfg.chunk_bytes % 16 != 0 || cfg.chunk_bytes > (1u << 30))
         return set_error(CKPT_E_INVAL, "chunk_bytes %u: not a multiple of 16 in [16, 2^30]", cfg.chunk_bytes);
+    // one 16-byte piece per lane per round and per-lane replicated tables are
+    // the only forms (the others measured slower and were removed); the
+    // fields stay for the structure's layout
     if (cfg.lane_pieces == 0)
-        cfg.lane_pieces = 1;    // fully coalesced 16-byte loads measured fastest
+        cfg.lane_pieces = 1;
+    if (cfg.lane_pieces != 1)
+        return set_error(CKPT_E_INVAL, "lane_pieces %u: only 1 (one 16-byte piece per lane per round)",
+                         cfg.lane_pieces);
     if (cfg.table_mode == 0)
-        cfg.table_mode = cfg.lane_pieces == 1 ? kTableReplicated : kTableCompact;
-    if (cfg.table_mode != kTableCompact && cfg.table_mode != kTableReplicated)
-        return set_error(CKPT_E_INVAL, "table_mode %u", cfg.table_mode);
-    if (cfg.table_mode == kTableReplicated && cfg.lane_pieces != 1)
-        return set_error(CKPT_E_INVAL, "replicated tables need lane_pieces 1");
+        cfg.table_mode = 2;
+    if (cfg.table_mode != 2)
+        return set_error(CKPT_E_INVAL, "table_mode %u: only 2 (replicated)", cfg.table_mode);
     if (cfg.block_threads == 0)
-        cfg.block_threads = cfg.table_mode == kTableReplicated ? 1024 : 256;
+        cfg.block_threads = 1024;
     if (cfg.block_threads != 64 && cfg.block_threads != 128 && cfg.block_threads != 256 &&
         cfg.block_threads != 512 && cfg.block_threads != 1024)
         return set_error(CKPT_E_INVAL, "block_threads %u", cfg.block_threads);
@@ -327,8 +330,6 @@ extern "C" int ckpt_init(const ckpt_config *cfg_in, ckpt_ctx **out)
         return set_error(CKPT_E_INVAL, "waves_per_chunk %u with block_threads %u", w, cfg.block_threads);
     if (cfg.load_hint == 0)
         cfg.load_hint = 2;      // streaming: every byte is touched once
-    if (cfg.lane_pieces != 1 && cfg.lane_pieces != 2 && cfg.lane_pieces != 4)
-        return set_error(CKPT_E_INVAL, "lane_pieces %u: 1, 2 or 4", cfg.lane_pieces);
     if (cfg.load_hint > 2)
         return set_error(CKPT_E_INVAL, "load_hint %u", cfg.load_hint);
     int ndev = 0;
@@ -351,31 +352,26 @@ extern "C" int ckpt_init(const ckpt_config *cfg_in, ckpt_ctx **out)
 }
 
 // CRC operator tables on the device, shared by every context with the same
-// device, table layout, pieces per lane and rounds per wave, and kept until
+// device and rounds per wave, and kept until
 // the process ends: a batch of hundreds of contexts uploads one set, and a
 // context's later calls find its tables in place.
 const uint32_t *ckpt::shared_tables(const ckpt_config &cfg, int *rc)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, uint32_t, uint32_t, uint32_t>, void *> cache;
-    const uint32_t round_bytes = kRoundBytes * cfg.lane_pieces;
-    const uint32_t r_full = (cfg.chunk_bytes + round_bytes - 1) / round_bytes;
+    static std::map<std::pair<int, uint32_t>, void *> cache;
+    const uint32_t r_full = (cfg.chunk_bytes + kRoundBytes - 1) / kRoundBytes;
     const uint32_t rw = (r_full + cfg.waves_per_chunk - 1) / cfg.waves_per_chunk;
-    const auto key = std::make_tuple(cfg.device, cfg.table_mode, cfg.lane_pieces, rw);
+    const auto key = std::make_pair(cfg.device, rw);
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) {
         *rc = CKPT_OK;
         return (const uint32_t *)it->second;
     }
-    // replicated: the set of the one-wave forms, then the quad form's
-    std::vector<uint32_t> tabs(cfg.table_mode == kTableReplicated ? 2 * kRepWords : kTabTotalWords);
-    if (cfg.table_mode == kTableReplicated) {
-        build_tables_replicated(tabs.data(), rw);
-        build_tables_replicated(tabs.data() + kRepWords, rw, kQuadSkipBytes);
-    } else {
-        build_tables(tabs.data(), cfg.lane_pieces, rw);
-    }
+    // the set of the one-wave forms, then the quad form's
+    std::vector<uint32_t> tabs(2 * kRepWords);
+    build_tables_replicated(tabs.data(), rw);
+    build_tables_replicated(tabs.data() + kRepWords, rw, kQuadSkipBytes);
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, tabs.size() * 4);
     if (e == hipSuccess) {
@@ -401,11 +397,8 @@ int ckpt::ctx_setup(ckpt_ctx *ctx)
     int managed = 0;
     if (hipDeviceGetAttribute(&managed, hipDeviceAttributeConcurrentManagedAccess, cfg.device) == hipSuccess)
         ctx->managed_prefetch = managed != 0;
-    // LDS decides how many workgroups fit a CU: 36 KiB (compact tables) or
-    // 124 KiB (replicated) of the 160 KiB
-    const int lds_fit = cfg.table_mode == kTableReplicated ? 1 : 4;
-    const int per_cu = cfg.wgs_per_cu ? (int)cfg.wgs_per_cu
-                                      : std::max(1, std::min(lds_fit, 32 / (int)(cfg.block_threads / 64)));
+    // the 124 KiB of tables in LDS fit one workgroup per CU (of 160 KiB)
+    const int per_cu = cfg.wgs_per_cu ? (int)cfg.wgs_per_cu : 1;
     ctx->grid_chunks = ctx->cu_count * per_cu;
     ctx->grid_small = ctx->cu_count * 4;
     int rc = CKPT_OK;
@@ -659,14 +652,10 @@ ChunkArgs ckpt::chunk_args(ckpt_ctx *ctx)
     a.plan = (const DevPlan *)ctx->d_plan.p;
     a.plan_rw = (DevPlan *)ctx->d_plan.p;
     a.tables = ctx->tables;
-    if (ctx->cfg.table_mode == kTableReplicated)
-        a.tables_quad = a.tables + kRepWords;
+    a.tables_quad = a.tables + kRepWords;
     a.C = ctx->cfg.chunk_bytes;
     a.waves_per_chunk = ctx->cfg.waves_per_chunk;
-    a.lane_pieces = ctx->cfg.lane_pieces;
     a.nontemporal = ctx->cfg.load_hint == 2;
-    a.table_mode = ctx->cfg.table_mode;
-    a.table_words = ctx->cfg.table_mode == kTableReplicated ? kRepWords : kTabTotalWords;
     a.size = (const uint64_t *)ctx->d_size.p;
     a.off = (const uint64_t *)ctx->d_off.p;
     a.cb = (const uint64_t *)ctx->d_cb.p;

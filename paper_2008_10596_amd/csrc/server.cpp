@@ -596,13 +596,11 @@ int run_step(ckpt_server *sv, const std::vector<Req *> &reqs, std::vector<uint64
     memset(&a, 0, sizeof(a));
     a.tables = (const uint32_t *)sv->d_tables.p;
     a.C = C;
-    a.lane_pieces = sv->cfg.lane_pieces;
     a.nontemporal = 1;
-    a.table_mode = sv->cfg.lane_pieces == 1 ? kTableReplicated : kTableCompact;
     a.n_items = items;
     a.rows = (const StepRow *)(d + sizeof(DevPlan));
     a.map = (const uint32_t *)sv->d_map.p;
-    HIP_TRY(launch_rows(s, a, sv->cu_count * (a.table_mode == kTableReplicated ? 1 : 4), sv->cfg.block_threads));
+    HIP_TRY(launch_rows(s, a, sv->cu_count, sv->cfg.block_threads));
     HIP_TRY(hipStreamSynchronize(s));
     return CKPT_OK;
 }
@@ -681,13 +679,13 @@ extern "C" int ckpt_server_create(const ckpt_server_config *cfg_in, ckpt_server 
         cfg.host_budget = uint64_t(64) << 30;
     if (cfg.lane_pieces == 0)
         cfg.lane_pieces = 1;
+    if (cfg.lane_pieces != 1)
+        return set_error(CKPT_E_INVAL, "lane_pieces %u: only 1", cfg.lane_pieces);
     if (cfg.block_threads == 0)
-        cfg.block_threads = cfg.lane_pieces == 1 ? 1024 : 256;
+        cfg.block_threads = 1024;
     if (cfg.block_threads != 64 && cfg.block_threads != 128 && cfg.block_threads != 256 &&
         cfg.block_threads != 512 && cfg.block_threads != 1024)
         return set_error(CKPT_E_INVAL, "block_threads %u", cfg.block_threads);
-    if (cfg.lane_pieces != 1 && cfg.lane_pieces != 2 && cfg.lane_pieces != 4)
-        return set_error(CKPT_E_INVAL, "lane_pieces %u", cfg.lane_pieces);
     if (cfg.aux_threads == 0)
         cfg.aux_threads = 2;
     if (cfg.aux_threads > 16)
@@ -718,16 +716,10 @@ extern "C" int ckpt_server_create(const ckpt_server_config *cfg_in, ckpt_server 
     int rc = sv->arena.init(cfg.staging_budget);
     if (rc != CKPT_OK)
         return fail(rc);
-    // replicated tables (one 1024-thread workgroup per CU) with one 16-byte
-    // piece per lane per round; compact tables otherwise
-    const bool rep = cfg.lane_pieces == 1;
-    std::vector<uint32_t> tabs(rep ? kRepWords : kTabTotalWords);
-    const uint32_t round_bytes = kRoundBytes * cfg.lane_pieces;
-    const uint32_t rounds = (cfg.chunk_bytes + round_bytes - 1) / round_bytes;
-    if (rep)
-        build_tables_replicated(tabs.data(), rounds);
-    else
-        build_tables(tabs.data(), cfg.lane_pieces, rounds);
+    // the replicated tables (one 1024-thread workgroup per CU)
+    std::vector<uint32_t> tabs(kRepWords);
+    const uint32_t rounds = (cfg.chunk_bytes + kRoundBytes - 1) / kRoundBytes;
+    build_tables_replicated(tabs.data(), rounds);
     if ((rc = sv->d_tables.ensure(tabs.size() * 4)) != CKPT_OK)
         return fail(rc);
     if ((e = hipMemcpy(sv->d_tables.p, tabs.data(), tabs.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)

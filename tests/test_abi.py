@@ -67,8 +67,9 @@ def test_init_rejects_bad_configs_before_touching_a_device(ck):
     h = ctypes.c_void_p()
     assert lib.ckpt_init(None, None) == ck.CKPT_E_INVAL
     for field, value in (("chunk_bytes", 8), ("chunk_bytes", 4100), ("block_threads", 100),
-                         ("waves_per_chunk", 3), ("waves_per_chunk", 8), ("lane_pieces", 3),
-                         ("lane_pieces", 8), ("load_hint", 3), ("table_mode", 3)):
+                         ("waves_per_chunk", 3), ("waves_per_chunk", 8), ("lane_pieces", 2),
+                         ("lane_pieces", 4), ("lane_pieces", 8), ("load_hint", 3), ("table_mode", 1),
+                         ("table_mode", 3)):
         cfg = ck.ckpt_config()
         setattr(cfg, field, value)
         if field == "waves_per_chunk" and value == 8:

@@ -110,14 +110,13 @@ def test_launch_shapes(block, wpc, C):
     full_roundtrip(tensors, C, block_threads=block, waves_per_chunk=wpc)
 
 
-@pytest.mark.parametrize("G,table", [(1, 1), (1, 2), (2, 1), (4, 1)])
 @pytest.mark.parametrize("hint", [1, 2])
 @pytest.mark.parametrize("C,wpc", [(4096, 1), (65536, 1), (65536, 4), (1040, 1), (262144, 2)])
-def test_lane_pieces_tables_and_load_hints(G, table, hint, C, wpc):
-    log("lane_pieces=%d table_mode=%d load_hint=%d C=%d waves/chunk=%d" % (G, table, hint, C, wpc))
+def test_load_hints(hint, C, wpc):
+    log("load_hint=%d C=%d waves/chunk=%d" % (hint, C, wpc))
     sizes = [C * 3 + 5, C, C - 16, 17, 1, 4, 3 * 1024 + 7, 1 << 20]
-    tensors = random_allocs(sizes, seed=G * 100 + hint * 10 + wpc, zero=(1,))
-    full_roundtrip(tensors, C, lane_pieces=G, table_mode=table, load_hint=hint, waves_per_chunk=wpc)
+    tensors = random_allocs(sizes, seed=100 + hint * 10 + wpc, zero=(1,))
+    full_roundtrip(tensors, C, load_hint=hint, waves_per_chunk=wpc)
 
 
 def test_zero_chunks_inside_random_allocations():
@@ -186,13 +185,12 @@ def test_registration_errors():
 
 # ------------------------------------------------------------ incremental
 
-@pytest.mark.parametrize("C,G,table", [(4096, 4, 1), (65536, 4, 1), (4096, 1, 2), (65536, 1, 2), (4096, 1, 1),
-                                       (65536, 2, 1)])
-def test_incremental_matches_oracle_and_restores(C, G, table):
-    log("incremental C=%d G=%d table_mode=%d" % (C, G, table))
+@pytest.mark.parametrize("C,wpc", [(4096, 1), (65536, 1), (65536, 4), (1040, 1)])
+def test_incremental_matches_oracle_and_restores(C, wpc):
+    log("incremental C=%d waves/chunk=%d" % (C, wpc))
     sizes = [C * 7 + 123, C * 2, 5000, C * 30, 16]
     tensors = random_allocs(sizes, seed=C + 1)
-    ctx = K.Context(chunk_bytes=C, lane_pieces=G, table_mode=table)
+    ctx = K.Context(chunk_bytes=C, waves_per_chunk=wpc)
     register_all(ctx, tensors)
     base = ctx.checkpoint()
     base_ref = O.checkpoint([host(t) for t in tensors], C)

@@ -35,8 +35,7 @@ def run_server(srv, items):
     return [srv.wait(t) for t in tickets]
 
 
-@pytest.mark.parametrize("lane_pieces", [1, 2])
-def test_server_alone_equals_mix_and_plain(lane_pieces):
+def test_server_alone_equals_mix_and_plain():
     reqs = make_requests(21)
     # images to restore from, taken with the plain path
     plain_imgs = []
@@ -50,7 +49,7 @@ def test_server_alone_equals_mix_and_plain(lane_pieces):
     items += [(K.CKPT_REQ_RESTORE, d, img) for d, img in zip(restore_dsts, plain_imgs)]
 
     # alone: one request at a time
-    srv = K.Server(chunk_bytes=C, staging_budget=1 << 30, step_bytes=1 << 20, lane_pieces=lane_pieces)
+    srv = K.Server(chunk_bytes=C, staging_budget=1 << 30, step_bytes=1 << 20)
     alone = []
     for it in items:
         r = run_server(srv, [it])[0]
@@ -63,8 +62,7 @@ def test_server_alone_equals_mix_and_plain(lane_pieces):
             x.fill_(0x33)
 
     # mix: everything at once, small steps and a budget that forces queueing
-    srv = K.Server(chunk_bytes=C, staging_budget=64 << 20, step_bytes=256 << 10, max_active=6,
-                   lane_pieces=lane_pieces)
+    srv = K.Server(chunk_bytes=C, staging_budget=64 << 20, step_bytes=256 << 10, max_active=6)
     mixed = run_server(srv, items)
     st = srv.stats()
     log("server mix stats: %s" % st)
