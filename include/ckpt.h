@@ -107,6 +107,13 @@ enum ckpt_status {
                                      pack (full checkpoints without a base)      */
 #define CKPT_NO_GRAPH       0x40u /* ckpt_checkpoint_batch: plain launches instead
                                      of the captured graph it uses by default    */
+#define CKPT_RESERVE_STAGING 0x80u /* ckpt_init allocates the whole staging_budget
+                                     (which must be set) as one device block at
+                                     once: the dense image at its start, a drain's
+                                     or restore's segment slots after it.  Later
+                                     checkpoints and restores that fit allocate no
+                                     device staging, and the block takes its place
+                                     before the application's later allocations. */
 
 typedef struct ckpt_config {
     int32_t device;            /* HIP device ordinal                                  */

@@ -34,6 +34,7 @@ CKPT_TIMING = 0x8
 CKPT_DRAIN_DIRECT = 0x10
 CKPT_GRAPH = 0x20
 CKPT_NO_GRAPH = 0x40
+CKPT_RESERVE_STAGING = 0x80
 CKPT_HOOK_ADDRESS_STABLE = 0x1
 CKPT_HOOK_CACHE = 0x2
 CKPT_SEC_ALLOCS, CKPT_SEC_CRC, CKPT_SEC_FLAGS, CKPT_SEC_DATA, CKPT_SEC_DIRTY_IDS, CKPT_SEC_DENSE = range(6)

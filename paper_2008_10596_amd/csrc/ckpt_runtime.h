@@ -244,6 +244,7 @@ struct ckpt_ctx {
     ckpt::DevBuf d_crc, d_flags, d_base_crc, d_prev_crc, d_soff, d_ids, d_tile_b, d_tile_c;
     ckpt::DevBuf d_dense, d_compact, d_bad, d_pick, d_crc2, d_flags2, d_soff2, d_base_cb, d_snap_flags;
     ckpt::PinnedBuf h_up, h_plan, h_base_cb;
+    bool reserved = false;      // CKPT_RESERVE_STAGING: d_dense is the reserved block
     uint64_t prev_serial = 0;   // image whose CRC array is in d_prev_crc
     uint32_t zero_crc = 0;      // CRC-32C of chunk_bytes zero bytes, once computed
     bool zero_crc_ready = false;
@@ -290,6 +291,14 @@ int alloc_meta(ckpt_image *img, uint64_t N);
 void image_wait(const ckpt_image *img);
 int order_after_meta(ckpt_ctx *ctx, hipStream_t s);
 int ctx_ready(ckpt_ctx *ctx);
+// Device staging of `bytes` serialized bytes (a drain's gather output, a
+// restore's copy from the host): with a reservation, the reserved block from
+// `used` bytes on (rounded up to 256); else the context's compact buffer.
+int serial_staging(ckpt_ctx *ctx, uint64_t used, uint64_t bytes, uint8_t **out);
+// ckpt_restore; fresh_dst: the destinations were mapped by the caller just
+// before (one pass instead of segments where the staging fits).
+int restore_impl(ckpt_ctx *ctx, void *stream, const ckpt_image *img, const ckpt_image *delta, void *const *dst,
+                 const size_t *dst_bytes, size_t n_dst, ckpt_verify_report *rep, bool fresh_dst);
 // Segment size of drains and restores (0: one pass) and the device slots.
 uint64_t segment_bytes(const ckpt_config &cfg);
 constexpr int kSegSlots = 4;

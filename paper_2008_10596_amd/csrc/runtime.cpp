@@ -328,6 +328,8 @@ extern "C" int ckpt_init(const ckpt_config *cfg_in, ckpt_ctx **out)
     const uint32_t w = cfg.waves_per_chunk;
     if ((w & (w - 1)) != 0 || w > 16 || w > cfg.block_threads / 64)
         return set_error(CKPT_E_INVAL, "waves_per_chunk %u with block_threads %u", w, cfg.block_threads);
+    if ((cfg.flags & CKPT_RESERVE_STAGING) && cfg.staging_budget == 0)
+        return set_error(CKPT_E_INVAL, "CKPT_RESERVE_STAGING needs a staging_budget");
     if (cfg.load_hint == 0)
         cfg.load_hint = 2;      // streaming: every byte is touched once
     if (cfg.load_hint > 2)
@@ -403,7 +405,15 @@ int ckpt::ctx_setup(ckpt_ctx *ctx)
     ctx->grid_small = ctx->cu_count * 4;
     int rc = CKPT_OK;
     ctx->tables = shared_tables(cfg, &rc);
-    return rc;
+    if (rc != CKPT_OK)
+        return rc;
+    if (cfg.flags & CKPT_RESERVE_STAGING) {
+        // the whole staging budget as one block, now: the dense image at its
+        // start, a drain's or restore's segment slots after it
+        CKPT_TRY(ctx->d_dense.ensure(cfg.staging_budget));
+        ctx->reserved = true;
+    }
+    return CKPT_OK;
 }
 
 // Streams and events are made on first use, so that contexts that only hold
@@ -439,6 +449,22 @@ int ckpt::seg_events(ckpt_ctx *ctx, size_t n)
         HIP_TRY(hipEventCreate(&e));
         ctx->seg_ev.push_back(e);
     }
+    return CKPT_OK;
+}
+
+int ckpt::serial_staging(ckpt_ctx *ctx, uint64_t used, uint64_t bytes, uint8_t **out)
+{
+    if (ctx->reserved) {
+        const uint64_t off = (used + 255) & ~uint64_t(255);
+        if (off > ctx->d_dense.cap || bytes > ctx->d_dense.cap - off)
+            return set_error(CKPT_E_BUDGET, "staging of %llu B past %llu B exceeds the reserved %llu B",
+                             (unsigned long long)bytes, (unsigned long long)off,
+                             (unsigned long long)ctx->d_dense.cap);
+        *out = (uint8_t *)ctx->d_dense.p + off;
+        return CKPT_OK;
+    }
+    CKPT_TRY(ctx->d_compact.ensure(std::max<uint64_t>(bytes, 16)));
+    *out = (uint8_t *)ctx->d_compact.p;
     return CKPT_OK;
 }
 
@@ -738,7 +764,9 @@ int ckpt::graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &r
             (void)hipGraphExecDestroy(ctx->g_exec);
             ctx->g_exec = nullptr;
         }
-        const uint64_t nc = grow(n, 64), Nc = grow(N, 1024), Dc = grow(data_bytes, 1 << 20);
+        const uint64_t nc = grow(n, 64), Nc = grow(N, 1024);
+        // a reserved dense block is kept (a larger image is refused by the budget)
+        const uint64_t Dc = ctx->reserved ? std::max<uint64_t>(data_bytes, ctx->d_dense.cap) : grow(data_bytes, 1 << 20);
         CKPT_TRY(ctx->d_addr.ensure(nc * 8));
         CKPT_TRY(ctx->d_size.ensure(nc * 8));
         CKPT_TRY(ctx->d_off.ensure((nc + 1) * 8));
@@ -1058,8 +1086,9 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
             CKPT_TRY(data[0].ensure(sel_bytes));
             d_out = (uint8_t *)data[0].p;
         } else {
-            CKPT_TRY(ctx->d_compact.ensure(stage));
-            d_out = (uint8_t *)ctx->d_compact.p;
+            // with a reservation, after the dense image when that is the
+            // context's staging
+            CKPT_TRY(serial_staging(ctx, dense == (uint8_t *)ctx->d_dense.p ? L.data_bytes : 0, stage, &d_out));
             for (size_t i = 0; i < nout; i++)
                 CKPT_TRY(data[i].ensure(part_data[i + 1] - part_data[i]));
         }
@@ -1101,7 +1130,11 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
                 ga.soff_base = b0;
                 if (timing)
                     HIP_TRY(hipEventRecord(tev[2 * used], gst));
-                HIP_TRY(launch_gather(gst, ga, 2 * ctx->cu_count));
+                // One 1024-thread workgroup per CU: the runtime's copies to the
+                // host are kernels too, and each of their workgroups holds a CU
+                // slot for the whole copy.  A second gather workgroup per CU
+                // would not fit beside one and would wait for the copy to end.
+                HIP_TRY(launch_gather(gst, ga, ctx->cu_count));
                 if (timing)
                     HIP_TRY(hipEventRecord(tev[2 * used + 1], gst));
                 HIP_TRY(hipEventRecord(slot_full[j], gst));
@@ -1329,6 +1362,13 @@ extern "C" int ckpt_checkpoint_batch(ckpt_ctx *const *ctxs, size_t n, void *stre
 extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, const ckpt_image *delta,
                             void *const *dst, const size_t *dst_bytes, size_t n_dst, ckpt_verify_report *rep)
 {
+    return restore_impl(ctx, stream, img, delta, dst, dst_bytes, n_dst, rep, false);
+}
+
+int ckpt::restore_impl(ckpt_ctx *ctx, void *stream, const ckpt_image *img, const ckpt_image *delta,
+                       void *const *dst, const size_t *dst_bytes, size_t n_dst, ckpt_verify_report *rep,
+                       bool fresh_dst)
+{
     if (!ctx || !img)
         return set_error(CKPT_E_INVAL, "ctx or image is NULL");
     if (!img->drained || img->mode != CKPT_FULL)
@@ -1340,7 +1380,7 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
         // the allocation table changed between the two: restore the merged image
         std::unique_ptr<ckpt_image> merged;
         CKPT_TRY(fold_delta(img, delta, &merged));
-        return ckpt_restore(ctx, stream, merged.get(), nullptr, dst, dst_bytes, n_dst, rep);
+        return restore_impl(ctx, stream, merged.get(), nullptr, dst, dst_bytes, n_dst, rep, fresh_dst);
     }
     const uint64_t n = img->allocs.size();
     if (n_dst != n)
@@ -1380,7 +1420,18 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
     const uint64_t seg_b = segment_bytes(ctx->cfg);
     const uint64_t seg_chunks = seg_b ? std::max<uint64_t>(1, seg_b / img->C) : 0;
     const uint64_t n_seg = seg_b && N ? (N + seg_chunks - 1) / seg_chunks : 0;
-    const bool segmented = n_seg > 1;
+    bool segmented = n_seg > 1;
+    // Destinations the caller has just mapped (a restore at the recorded
+    // addresses that re-created them): a segmented refill measured 66 ms
+    // slower there than into the same memory mapped earlier (16 GiB), and one
+    // pass 4 ms -- new memory is readied before its first use, and one pass
+    // copies the image to the device meanwhile.  One pass when its staging fits.
+    if (segmented && fresh_dst) {
+        const uint64_t whole = img->ser_bytes + (delta ? delta->ser_bytes : 0);
+        const uint64_t room = ctx->reserved ? ctx->d_dense.cap : ctx->cfg.staging_budget;
+        if (!room || whole <= room)
+            segmented = false;
+    }
     const uint64_t slot_bytes = seg_chunks * img->C;   // a segment's serialized bytes never exceed this
     const uint64_t base_stage = segmented ? std::min<uint64_t>(img->ser_bytes, kSegSlots * slot_bytes) : img->ser_bytes;
     const uint64_t stage = base_stage + (delta ? delta->ser_bytes : 0);
@@ -1406,8 +1457,8 @@ extern "C" int ckpt_restore(ckpt_ctx *ctx, void *stream, const ckpt_image *img, 
     CKPT_TRY(ctx->d_flags.ensure(std::max<uint64_t>(N, 1)));
     CKPT_TRY(ctx->d_bad.ensure(std::max<uint64_t>(N, 1)));
     CKPT_TRY(ctx->d_soff.ensure(std::max<uint64_t>(N, 1) * 8));
-    CKPT_TRY(ctx->d_compact.ensure(std::max<uint64_t>(stage, 16)));
-    uint8_t *staging = (uint8_t *)ctx->d_compact.p;
+    uint8_t *staging = nullptr;
+    CKPT_TRY(serial_staging(ctx, 0, stage, &staging));
     if (N) {
         HIP_TRY(hipMemcpyAsync(ctx->d_crc.p, img->crc, N * 4, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(ctx->d_flags.p, img->flags, N, hipMemcpyHostToDevice, s));

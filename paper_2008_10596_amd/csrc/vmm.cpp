@@ -513,7 +513,8 @@ extern "C" int ckpt_restore_at(ckpt_ctx *ctx, void *stream, const ckpt_image *im
     std::vector<void *> dst(n);
     for (uint64_t k = 0; k < n; k++)
         dst[k] = (void *)(uintptr_t)img->addrs[k];
-    const int rc = ckpt_restore(ctx, stream, img, delta, n ? dst.data() : nullptr, nullptr, n, rep);
+    const int rc = restore_impl(ctx, stream, img, delta, n ? dst.data() : nullptr, nullptr, n, rep,
+                                !made.ranges.empty());
     if (rc != CKPT_OK && rc != CKPT_E_CORRUPT) {
         (void)hipDeviceSynchronize();
         undo_made(ctx, made);

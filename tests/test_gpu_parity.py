@@ -649,6 +649,49 @@ def test_staging_budget():
     assert e.value.status == K.CKPT_E_BUDGET
 
 
+@pytest.mark.parametrize("segment_mib", [0, 1, 0xFFFFFFFF])
+def test_reserved_staging_matches_the_oracle(segment_mib):
+    """CKPT_RESERVE_STAGING: the staging budget is one block made at
+    ckpt_init; checkpoints (full, drained in segments or in one pass, and
+    incremental) and restores take their staging from it and equal the oracle."""
+    C = 4096
+    log("reserved staging, segment_mib=%d" % segment_mib)
+    sizes = [3 << 20, 12345, 0, 1 << 20, 4096 * 5 + 7, 2 << 20]
+    tensors = random_allocs(sizes, seed=31, zero=(3,))
+    dense_b = sum(r16(s) for s in sizes)
+    budget = 2 * dense_b + (8 << 20)
+    ctx = K.Context(chunk_bytes=C, staging_budget=budget, segment_mib=segment_mib,
+                    flags=K.CKPT_RESERVE_STAGING)
+    ids = register_all(ctx, tensors)
+    img = ctx.checkpoint()
+    ref = O.checkpoint([host(t) for t in tensors], C)
+    check_full(img, ref, tensors, C, ids)
+    tensors[0][5000:9000] = 7
+    tensors[5][-3:] = 1
+    d = ctx.checkpoint(mode=K.CKPT_INCREMENTAL, base=img)
+    dref = O.delta([host(t) for t in tensors], C, ref["crc"])
+    assert np.array_equal(d.dirty_ids, dref["dirty_ids"]) and np.array_equal(d.data, dref["delta"])
+    dsts = [torch.full((t.numel(),), 0xA5, dtype=torch.uint8, device="cuda") for t in tensors]
+    rc, rep = ctx.restore(img, dsts, delta=d)
+    assert rc == K.CKPT_OK and rep["n_bad"] == 0
+    check_restored(dsts, tensors)
+    # an image larger than the reservation is refused, and nothing is allocated for it
+    big = torch.empty(budget, dtype=torch.uint8, device="cuda")
+    ctx.register(big)
+    with pytest.raises(K.CkptError) as e:
+        ctx.checkpoint()
+    assert e.value.status == K.CKPT_E_BUDGET
+    d.close()
+    img.close()
+    ctx.close()
+
+
+def test_reserved_staging_needs_a_budget():
+    with pytest.raises(K.CkptError) as e:
+        K.Context(flags=K.CKPT_RESERVE_STAGING)
+    assert e.value.status == K.CKPT_E_INVAL
+
+
 # ------------------------------------------------------------------- graphs
 
 def test_graph_replays_match_eager_and_oracle():
