@@ -273,6 +273,47 @@ int ckpt_checkpoint(ckpt_ctx *ctx, void *stream, int mode, const ckpt_image *bas
                     ckpt_image **out);
 
 /*
+ * For callers that cannot allocate memory during the call (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * device pass of ckpt_checkpoint -- size scan, chunk map and the fused pack +
+ * CRC-32C + flags kernel (CKPT_FULL) or the hash-only kernel
+ * (CKPT_INCREMENTAL) -- over the context's live registrations, written into
+ * buffers the caller passes.  It calls no hipMalloc, hipFree or other
+ * allocating routine: its descriptor tables live in one device array that the
+ * library holds per device until the process ends (36 MiB: at most
+ * 65536 allocations and 2^23 chunks; more is CKPT_E_BUDGET).  The results are
+ * those of ckpt_checkpoint with CKPT_NO_DRAIN | CKPT_KEEP_DENSE: the dense
+ * image (CKPT_SEC_DENSE's layout, pad bytes zero) and the CRC and flag
+ * arrays, here in device memory.  There is no serialized DATA, no dirty-id
+ * list and no image object.
+ *
+ * base_crc: NULL (every chunk DIRTY; CKPT_FULL only), or a device array of N
+ *   CRCs of a checkpoint of the same allocation table (the same sizes in the
+ *   same order, e.g. the crc output of an earlier call); chunk g is DIRTY
+ *   when its CRC differs from base_crc[g].  The library cannot check that the
+ *   table is the same; a base of another table gives meaningless DIRTY flags.
+ * dense: device, 16-byte aligned, dense_bytes >= data_bytes (CKPT_FULL; may
+ *   be NULL for CKPT_INCREMENTAL, which writes no image).
+ * crc, flags: device arrays of chunk_cap >= N entries (uint32 and uint8);
+ *   crc 4-byte aligned.
+ * n_chunks, data_bytes (host, may be NULL): receive N = sum of ceil(size / C)
+ *   and sum of roundup16(size) on success and also on CKPT_E_MISMATCH, so a
+ *   call with zero capacities asks for the sizes.
+ * Ordering follows ckpt_checkpoint (device-wide drain first, or the stream's
+ *   order with CKPT_STREAM_ORDERED).  The call returns once the work is
+ *   enqueued on `stream`; the outputs are complete when the stream reaches
+ *   that point.
+ * Every call on one device uses that device's one array: calls whose work
+ *   overlaps on one device race (the caller orders them, e.g. on one stream).
+ * CKPT_E_INVAL: bad mode, CKPT_INCREMENTAL without base_crc, NULL or
+ *   misaligned outputs.  CKPT_E_MISMATCH: outputs smaller than the pass
+ *   needs.  CKPT_E_BUDGET: more allocations or chunks than the array holds.
+ */
+int ckpt_checkpoint_noalloc(ckpt_ctx *ctx, void *stream, int mode, const uint32_t *base_crc,
+                            void *dense, uint64_t dense_bytes, uint32_t *crc, uint8_t *flags,
+                            uint64_t chunk_cap, uint64_t *n_chunks, uint64_t *data_bytes);
+
+/*
  * Refill n_dst destination buffers from an image, and optionally overlay an
  * incremental image (delta) on top.  dst[k] receives allocation k (id order)
  * and must be 16-byte aligned device memory of exactly the allocation's size.

@@ -17,7 +17,7 @@ PROBE_LIB = os.path.join(HERE, "libckpt_probe.so")
 PROBE_SOURCE = "probe.hip"
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "crc_tables.cpp", "runtime.cpp", "server.cpp", "vmm.cpp", "hook.cpp", "sink.cpp"]
+SOURCES = ["kernels.hip", "crc_tables.cpp", "runtime.cpp", "server.cpp", "vmm.cpp", "hook.cpp", "sink.cpp", "noalloc.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -128,6 +128,9 @@ SIGNATURES = [
     ("ckpt_unregister", ctypes.c_int, [_vp, _vp]),
     ("ckpt_live_count", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     ("ckpt_checkpoint", ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
+    ("ckpt_checkpoint_noalloc", ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, ctypes.c_uint64, _vp, _vp,
+                                                ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
+                                                ctypes.POINTER(ctypes.c_uint64)]),
     ("ckpt_restore", ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t),
                                     ctypes.c_size_t, ctypes.POINTER(ckpt_verify_report)]),
     ("ckpt_image_info", ctypes.c_int, [_vp, ctypes.POINTER(ckpt_image_meta)]),
@@ -373,6 +376,35 @@ class Context:
         _check(lib().ckpt_checkpoint(self.handle, _stream_handle(stream), mode,
                                      base.handle if base else None, ctypes.byref(out)), "ckpt_checkpoint")
         return Image(out.value)
+
+    def noalloc_sizes(self):
+        """(N, data_bytes) of the live set, from ckpt_checkpoint_noalloc with
+        zero capacities (CKPT_E_MISMATCH reports them).  When the live set has
+        no chunks, that call is an empty pass of its own."""
+        n, d = ctypes.c_uint64(), ctypes.c_uint64()
+        rc = lib().ckpt_checkpoint_noalloc(self.handle, None, CKPT_FULL, None, None, 0, None, None, 0,
+                                           ctypes.byref(n), ctypes.byref(d))
+        if rc not in (CKPT_OK, CKPT_E_MISMATCH):
+            raise CkptError(rc, "ckpt_checkpoint_noalloc")
+        return n.value, d.value
+
+    def checkpoint_noalloc(self, crc, flags, dense=None, base_crc=None, mode=CKPT_FULL, stream=None,
+                           dense_bytes=None, chunk_cap=None):
+        """The allocation-free device pass into caller buffers (tensors or
+        device addresses): dense image, CRC and flag arrays.  Enqueued on
+        `stream`; returns (N, data_bytes).  Capacities default to the
+        tensors' sizes."""
+        n, d = ctypes.c_uint64(), ctypes.c_uint64()
+        if dense_bytes is None:
+            dense_bytes = _nbytes(dense) if isinstance(dense, torch.Tensor) else 0
+        if chunk_cap is None:
+            chunk_cap = min(_nbytes(crc) // 4, _nbytes(flags)) if isinstance(crc, torch.Tensor) else 0
+        _check(lib().ckpt_checkpoint_noalloc(self.handle, _stream_handle(stream), mode,
+                                             _ptr(base_crc) if base_crc is not None else None,
+                                             _ptr(dense) if dense is not None else None, dense_bytes,
+                                             _ptr(crc), _ptr(flags), chunk_cap, ctypes.byref(n), ctypes.byref(d)),
+               "ckpt_checkpoint_noalloc")
+        return n.value, d.value
 
     def restore(self, image, dsts, delta=None, stream=None, dst_bytes=None, raise_on_corrupt=False):
         """Refill dsts (tensors or device addresses) from image (+ delta).

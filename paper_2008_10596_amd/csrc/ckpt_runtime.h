@@ -283,6 +283,9 @@ struct ckpt_image {
 namespace ckpt {
 
 int ctx_setup(ckpt_ctx *ctx);
+// Looks up, once per device, the device address of the allocation-free
+// path's file-scope array (ckpt_checkpoint_noalloc); `device` must be current.
+int noalloc_setup(int device);
 // The device CRC operator tables for cfg (device, layout, pieces, rounds per
 // wave), made on first use and shared; NULL and *rc set on failure.
 const uint32_t *shared_tables(const ckpt_config &cfg, int *rc);

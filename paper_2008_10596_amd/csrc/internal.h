@@ -190,6 +190,10 @@ hipError_t launch_select(hipStream_t s, const SelArgs &a, uint64_t max_items);
 // grid: workgroups of 1024 threads (persistent; two per CU fill the chip)
 hipError_t launch_gather(hipStream_t s, const GatherArgs &a, int grid);
 hipError_t launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t n_words, uint64_t value);
+// rows: n rows of four u64 words (id, kind, address, size); writes addr[n],
+// size[n] and a plan with n_allocs = n and every other count 0.
+hipError_t launch_table_split(hipStream_t s, const uint64_t *rows, uint64_t n, DevPlan *plan, uint64_t *addr,
+                              uint64_t *size);
 hipError_t launch_pick_u64(hipStream_t s, const uint64_t *src, const uint64_t *idx, uint64_t *out,
                            uint32_t m);
 

@@ -1230,6 +1230,24 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v)
         p[i] = v;
 }
 
+// The allocation table as the host keeps it (rows of four words: id, kind,
+// address, size) split into the address and size arrays the scan and the
+// chunk kernels read; the first thread also writes a fresh plan for n rows.
+__global__ void k_table_split(const uint64_t *__restrict__ rows, uint64_t n, DevPlan *plan,
+                              uint64_t *__restrict__ addr, uint64_t *__restrict__ size)
+{
+    const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 == 0) {
+        DevPlan p = {};
+        p.n_allocs = n;
+        *plan = p;
+    }
+    for (uint64_t k = i0; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
+        addr[k] = rows[4 * k + 2];
+        size[k] = rows[4 * k + 3];
+    }
+}
+
 __global__ void k_pick_u64(const uint64_t *src, const uint64_t *idx, uint64_t *out, uint32_t m)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1342,6 +1360,15 @@ hipError_t launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t n_words, uint64_
     if (blocks > 4096)
         blocks = 4096;
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, n_words, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_split(hipStream_t s, const uint64_t *rows, uint64_t n, DevPlan *plan, uint64_t *addr,
+                              uint64_t *size)
+{
+    uint64_t blocks = (n + 255) / 256;
+    blocks = blocks < 1 ? 1 : blocks > 1024 ? 1024 : blocks;
+    hipLaunchKernelGGL(k_table_split, dim3((unsigned)blocks), dim3(256), 0, s, rows, n, plan, addr, size);
     return hipGetLastError();
 }
 

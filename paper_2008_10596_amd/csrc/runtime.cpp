@@ -413,7 +413,8 @@ int ckpt::ctx_setup(ckpt_ctx *ctx)
         CKPT_TRY(ctx->d_dense.ensure(cfg.staging_budget));
         ctx->reserved = true;
     }
-    return CKPT_OK;
+    // this device's address of the allocation-free path's device array
+    return noalloc_setup(cfg.device);
 }
 
 // Streams and events are made on first use, so that contexts that only hold
