@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--load-hint", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed pack steps")
+    ap.add_argument("--batched-only-graph", action="store_true",
+                    help="batched section: the graph-replayed batch only (no plain forms, drain or autotuner; "
+                         "profiler runs)")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the copy reference and the plain read/write/copy ceiling sweep (profiler runs)")
     ap.add_argument("--drain-steps", type=int, default=5)
@@ -91,11 +94,34 @@ def profiled_traffic(summary_glob="k_chunks_pack_*.md"):
     return None
 
 
-def algorithmic_bytes(sizes, C):
+def algorithmic_bytes(sizes, C, flags=None):
+    """(S, dense, N, alg) of a pack launch: every live byte read, the dense
+    image written, 5 bytes of CRC + flags per chunk.  With the chunks' flags
+    (the one-wave pack of chunks of at most 4 KiB, which leaves ZERO chunks
+    unwritten), only the non-ZERO chunks' bytes (each rounded up to 16) count
+    as written."""
     S = int(sum(sizes))
     dense = int(sum((s + 15) // 16 * 16 for s in sizes))
     N = int(sum((s + C - 1) // C for s in sizes))
-    return S, dense, N, S + dense + 5 * N
+    if flags is None:
+        return S, dense, N, S + dense + 5 * N
+    return S, dense, N, S + stored_bytes(sizes, C, flags) + 5 * N
+
+
+def stored_bytes(sizes, C, flags):
+    """Bytes of the non-ZERO chunks, each rounded up to 16 (what the one-wave
+    pack of small chunks writes, and what a drained image holds)."""
+    import numpy as np
+    lens = np.concatenate([np.minimum(C, s - np.arange(0, s, C, dtype=np.int64)) for s in sizes if s]
+                          or [np.zeros(0, np.int64)])
+    nz = (np.asarray(flags)[:lens.size] & 1) == 0
+    return int(((lens[nz] + 15) // 16 * 16).sum())
+
+
+def elides_zero(C, wpc):
+    """The pack kernel form that leaves ZERO chunks unwritten: one wave per
+    chunk, chunks of at most four 1 KiB rounds."""
+    return wpc in (0, 1) and C <= 4096
 
 
 def cpu_baseline(tensors, sizes, C, budget_bytes=8 << 30, reps=3):
@@ -317,6 +343,15 @@ def bench_batched(K, synth, torch, stream, args, reps=3):
     # batched, image kept in HBM: one graph replay
     leader = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN | K.CKPT_TIMING, **tune_kw(args))
     dev_ms = []
+    if elides_zero(C, args.wpc):
+        # the pack leaves ZERO chunks unwritten: count the bytes it moves
+        import numpy as np
+        imgs = K.checkpoint_batch([leader] + members, stream=stream)
+        flags = np.concatenate([im.flags for im in imgs[1:]])
+        for im in imgs:
+            im.close()
+        S, dense_b, N, alg = algorithmic_bytes(sizes, C, flags)
+        out["algorithmic_bytes"] = alg
 
     def batched_once():
         imgs = K.checkpoint_batch([leader] + members, stream=stream)
@@ -329,6 +364,11 @@ def bench_batched(K, synth, torch, stream, args, reps=3):
                            "gbps_device": round(alg / (statistics.median(dev_ms[1:]) * 1e-3) / 1e9, 1),
                            "launches": 1}
     log("batched pack: %s" % out["batched_pack"])
+    if args.batched_only_graph:
+        leader.close()
+        for c in members:
+            c.close()
+        return out
     # plain, image kept in HBM: one checkpoint call per allocation
     pctx = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN | K.CKPT_TIMING, **tune_kw(args))
 
@@ -775,6 +815,7 @@ def bench_serving(K, synth, torch, args):
         if fail_status or warm_failed:
             res["failed_by_status"] = {K.STATUS_NAMES.get(k, str(k)): v
                                        for k, v in list(fail_status.items()) + list(warm_failed.items())}
+            res["last_error"] = st.get("last_error", "")
         if p50_first is None:
             p50_first = st["p50_ms"]
         elif knee is None and st["p50_ms"] > 4 * p50_first:
@@ -853,8 +894,16 @@ def main():
         if prev is not None:
             prev.close()
         prev = img
+    flags = prev.flags.copy()
     prev.close()
     log("warmup done")
+    alg_dense = alg
+    if elides_zero(C, args.wpc):
+        # the one-wave pack of chunks of at most 4 KiB leaves ZERO chunks
+        # unwritten: the bytes it moves are the live bytes, the non-ZERO
+        # chunks' bytes and 5 bytes per chunk
+        S, dense_b, N, alg = algorithmic_bytes(sizes, C, flags)
+        log("algorithmic bytes per step: %d (%d with every chunk written)" % (alg, alg_dense))
     pack_ms, step_ms = [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -904,14 +953,10 @@ def main():
     prev.close()
     torch.cuda.synchronize()
     ms_wide = (time.perf_counter() - t0) * 1e3 / nwide
-    wctx.close()
     log("device-wide drain mode: %.3f ms per step" % ms_wide)
-    copy_ref, ceilings = {"ms": None, "gbps": None}, None
-    if not args.no_ceilings:
-        copy_ref = copy_reference(torch, int((8 << 30) * args.scale))
-        log("copy reference: %s" % copy_ref)
-        ceilings = hbm_ceilings(torch, int((16 << 30) * args.scale) // 16 * 16)
-        log("hbm ceilings: %s" % ceilings["best"])
+    # the copy reference and the ceilings are measured at the end: freeing
+    # their buffers keeps the device's copy engines busy clearing memory for a
+    # while, which would slow the host-link copies measured in between
     if args.copy_probe:
         a = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
         b = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
@@ -930,14 +975,14 @@ def main():
                                "scaled to %.2f GiB, half all-zero, C=%d B, image kept in HBM, "
                                "stream-ordered" % (len(sizes), S / 2**30, C),
                    "live_bytes": S, "chunks": N, "chunk_bytes": C,
+                   "bytes_per_step": alg, "bytes_per_step_every_chunk_written": alg_dense,
+                   "live_gbps": round(S / (elapsed / args.steps) / 1e9, 2),
                    "ms_per_step_device_wide_drain": round(ms_wide, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved / 1e9, 2), "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4), "traffic": None,
                      "kernel": "k_chunks<pack>", "algorithmic_bytes_per_launch": alg,
                      "kernel_ms": round(pack_avg, 4),
-                     "copy_reference": dict(copy_ref, pack_vs_copy=round(achieved / 1e9 / copy_ref["gbps"], 4)
-                                            if copy_ref["gbps"] else None),
-                     "ceilings": ceilings},
+                     "copy_reference": None, "ceilings": None},
     }
     prof = profiled_traffic()
     if prof is not None and prof[1] == alg:
@@ -1012,11 +1057,12 @@ def main():
         for t in tensors:
             octx.register(t)
         og, osc = [], []
-        for i in range(2):
+        for i in range(4):   # the first call allocates the staging and pinned buffers
             octx.checkpoint(stream=stream).close()
             og.append(octx.timing()["gather_ms"])
             octx.restore(img, dsts, stream=stream)
             osc.append(octx.timing()["scatter_ms"])
+        og, osc = og[1:], osc[1:]
         octx.close()
         g1, s1 = statistics.median(og), statistics.median(osc)
         result["drain"].update({
@@ -1068,6 +1114,7 @@ def main():
         result["cpu_baseline"] = cpu_baseline(tensors, sizes, C)
         log("cpu baseline: %s" % result["cpu_baseline"])
     ctx.close()
+    wctx.close()   # kept until here: see the note on freeing before the link is measured
     del tensors
     torch.cuda.empty_cache()
 
@@ -1086,6 +1133,13 @@ def main():
     if "sink" in result:
         result["sink"]["deflate"]["bf16"] = bench_sink_bf16(K, torch, args, result["sink"]["dir"])
         log("sink deflate (bf16): %s" % result["sink"]["deflate"]["bf16"])
+    if not args.no_ceilings:
+        copy_ref = copy_reference(torch, int((8 << 30) * args.scale))
+        log("copy reference: %s" % copy_ref)
+        result["roofline"]["copy_reference"] = dict(copy_ref, pack_vs_copy=round(achieved / 1e9 / copy_ref["gbps"], 4))
+        ceilings = hbm_ceilings(torch, int((16 << 30) * args.scale) // 16 * 16)
+        log("hbm ceilings: %s" % ceilings["best"])
+        result["roofline"]["ceilings"] = ceilings
     print(json.dumps(result), flush=True)
 
 

@@ -181,8 +181,11 @@ enum ckpt_section {
                             /* chunks in ascending id; incremental = DIRTY non-ZERO     */
                             /* chunks; each chunk padded with zeros to a multiple of 16 */
     CKPT_SEC_DIRTY_IDS = 4, /* host, uint64_t[n_dirty]: ascending ids of DIRTY chunks   */
-    CKPT_SEC_DENSE = 5,     /* DEVICE pointer, data_bytes: allocation k at off_k,       */
-                            /* pad bytes zero (with CKPT_KEEP_DENSE or CKPT_NO_DRAIN)    */
+    CKPT_SEC_DENSE = 5,     /* DEVICE pointer, data_bytes: allocation k at off_k, the   */
+                            /* pad of non-ZERO chunks zero; a ZERO chunk's bytes (and   */
+                            /* its pad) are unspecified, read them as zeros (the pack   */
+                            /* of chunks of at most 4 KiB does not store ZERO chunks)   */
+                            /* (with CKPT_KEEP_DENSE or CKPT_NO_DRAIN)                  */
     CKPT_SEC_ADDRS = 6      /* host, uint64_t[n_allocs]: device address of allocation k */
                             /* when the image was taken (0 if loaded from version-1     */
                             /* serialized data); used by ckpt_restore_at                 */
@@ -283,7 +286,7 @@ int ckpt_checkpoint(ckpt_ctx *ctx, void *stream, int mode, const ckpt_image *bas
  * library holds per device until the process ends (36 MiB: at most
  * 65536 allocations and 2^23 chunks; more is CKPT_E_BUDGET).  The results are
  * those of ckpt_checkpoint with CKPT_NO_DRAIN | CKPT_KEEP_DENSE: the dense
- * image (CKPT_SEC_DENSE's layout, pad bytes zero) and the CRC and flag
+ * image (CKPT_SEC_DENSE's layout and contents) and the CRC and flag
  * arrays, here in device memory.  There is no serialized DATA, no dirty-id
  * list and no image object.
  *
@@ -598,6 +601,12 @@ int ckpt_checkpoint_batch(ckpt_ctx *const *ctxs, size_t n, void *stream, ckpt_im
  * caller release older images); requests behind a request whose device
  * staging does not fit wait.  So a backlog queues instead of failing, and
  * images the caller keeps hold back later checkpoints until it frees them.
+ * The host may pin less than host_budget: a request whose preparation or
+ * finish (a finished checkpoint's image included) cannot get memory keeps its
+ * staging and runs that part again every few milliseconds until memory is
+ * released (after 30 s it fails with CKPT_E_NOMEM); a short image buffer also
+ * makes the server take the pinned bytes held at that moment as its host
+ * budget.  A step whose buffers cannot grow is run again the same way.
  * Every step is one kernel launch that
  * processes up to step_bytes of each admitted request, checkpoints and
  * restores together, so requests overlap on the device; a request that
@@ -658,8 +667,10 @@ typedef struct ckpt_stats {
     uint64_t steps;             /* step launches                                        */
     uint32_t max_concurrent;    /* most requests admitted at once                       */
     uint32_t pad;
-    uint64_t host_waits;        /* checkpoints held back for host memory                */
+    uint64_t host_waits;        /* checkpoints held back for host memory at admission,
+                                   and requests whose step waited for memory           */
     uint64_t host_peak;         /* most pinned bytes held plus reserved at an admission */
+    char last_error[160];       /* message of the latest failed request ("" if none)   */
 } ckpt_stats;
 
 /* CKPT_E_INVAL: bad config; CKPT_E_NOMEM: the staging budget could not be

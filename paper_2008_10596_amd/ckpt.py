@@ -114,7 +114,8 @@ class ckpt_stats(ctypes.Structure):
                 ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
                 ("makespan_s", ctypes.c_double), ("gbps", ctypes.c_double),
                 ("steps", ctypes.c_uint64), ("max_concurrent", ctypes.c_uint32),
-                ("pad", ctypes.c_uint32), ("host_waits", ctypes.c_uint64), ("host_peak", ctypes.c_uint64)]
+                ("pad", ctypes.c_uint32), ("host_waits", ctypes.c_uint64), ("host_peak", ctypes.c_uint64),
+                ("last_error", ctypes.c_char * 160)]
 
 
 _vp = ctypes.c_void_p
@@ -565,7 +566,9 @@ class Server:
     def stats(self):
         st = ckpt_stats()
         _check(lib().ckpt_server_stats(self.handle, ctypes.byref(st)), "ckpt_server_stats")
-        return {f: getattr(st, f) for f, _ in ckpt_stats._fields_ if f != "pad"}
+        out = {f: getattr(st, f) for f, _ in ckpt_stats._fields_ if f != "pad"}
+        out["last_error"] = out["last_error"].decode(errors="replace")
+        return out
 
     def reset_stats(self):
         _check(lib().ckpt_server_reset_stats(self.handle), "ckpt_server_reset_stats")

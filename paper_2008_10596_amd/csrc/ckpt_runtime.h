@@ -246,8 +246,7 @@ struct ckpt_ctx {
     ckpt::PinnedBuf h_up, h_plan, h_base_cb;
     bool reserved = false;      // CKPT_RESERVE_STAGING: d_dense is the reserved block
     uint64_t prev_serial = 0;   // image whose CRC array is in d_prev_crc
-    uint32_t zero_crc = 0;      // CRC-32C of chunk_bytes zero bytes, once computed
-    bool zero_crc_ready = false;
+    uint32_t zero_crc = 0;      // CRC-32C of chunk_bytes zero bytes (made at ckpt_init)
 
     ckpt_timing timing{};
 

@@ -2,9 +2,10 @@
 //
 // The CRC register is a linear function over GF(2) of its previous value and
 // the data, so "feed m zero bytes" is a 32 x 32 bit matrix.  Its columns are
-// found by running each single-bit register value through m zero bytes, bit by
-// bit; a table entry for byte position j and byte value b is the XOR of the
-// columns of b's set bits, shifted to position j.
+// found by running each single-bit register value through m zero bytes (bit by
+// bit, or by powers of the one-byte operator for long runs); a table entry for
+// byte position j and byte value b is the XOR of the columns of b's set bits,
+// shifted to position j.
 #include <vector>
 
 #include "internal.h"
@@ -14,10 +15,45 @@ namespace ckpt {
 // One zero bit through the reflected register.
 static uint32_t step_bit(uint32_t r) { return (r & 1u) ? (r >> 1) ^ kPolyReflected : (r >> 1); }
 
+// The operator m applied to v: the XOR of m's columns at v's set bits.
+static uint32_t apply_op(const uint32_t *m, uint32_t v)
+{
+    uint32_t r = 0;
+    for (int i = 0; v; i++, v >>= 1)
+        if (v & 1u)
+            r ^= m[i];
+    return r;
+}
+
 uint32_t host_shift(uint32_t reg, uint64_t nbytes)
 {
-    for (uint64_t i = 0; i < 8 * nbytes; i++)
-        reg = step_bit(reg);
+    if (nbytes <= 64) {
+        for (uint64_t i = 0; i < 8 * nbytes; i++)
+            reg = step_bit(reg);
+        return reg;
+    }
+    // Powers of the one-byte operator (its columns run bit by bit): the
+    // operator for 2^k bytes is the square of the one for 2^(k-1), and the
+    // register passes the power for each set bit of nbytes.  The powers of one
+    // operator commute, so the order does not matter.
+    uint32_t op[32], sq[32];
+    for (int i = 0; i < 32; i++) {
+        uint32_t c = 1u << i;
+        for (int b = 0; b < 8; b++)
+            c = step_bit(c);
+        op[i] = c;
+    }
+    while (nbytes) {
+        if (nbytes & 1)
+            reg = apply_op(op, reg);
+        nbytes >>= 1;
+        if (nbytes) {
+            for (int i = 0; i < 32; i++)
+                sq[i] = apply_op(op, op[i]);
+            for (int i = 0; i < 32; i++)
+                op[i] = sq[i];
+        }
+    }
     return reg;
 }
 

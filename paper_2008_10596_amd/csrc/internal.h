@@ -92,9 +92,11 @@ struct ChunkArgs {
     const uint32_t *want_crc;
     const uint8_t *want_flags;
     const uint64_t *ids;      // nullable: item i is chunk ids[i], else chunk i
-    uint32_t zero_crc;        // restore: CRC-32C of C zero bytes; a full-length ZERO
+    uint32_t zero_crc;        // CRC-32C of C zero bytes.  Restore: a full-length ZERO
                               // chunk is written as zeros and checked against it
-                              // without hashing the zeros
+                              // without hashing the zeros.  Pack (one wave per chunk
+                              // of at most four rounds): a full-length ZERO chunk
+                              // gets it as its CRC and is neither hashed nor stored
     uint32_t pad0;
     uint8_t *bad;             // per chunk, set to 1 when verification fails
     DevPlan *plan_rw;         // bad_count lives here

@@ -455,9 +455,11 @@ __device__ __forceinline__ void small_loads(const Desc &d, int lane, uint32_t r_
     }
 }
 
+// store: write the chunk's pieces (pack); a ZERO chunk's pieces are not
+// stored, since the dense image leaves ZERO chunks unwritten.
 template <int MODE, bool NT>
 __device__ __forceinline__ uint32_t small_rest(const Tabs &T, const Desc &d, int lane, uint32_t r_win,
-                                               uint4 (&v)[kLoadsInFlight], uint32_t *orv)
+                                               uint4 (&v)[kLoadsInFlight], uint32_t *orv, bool store)
 {
     constexpr int B = kLoadsInFlight;
     const uint32_t np = (d.len + 15) >> 4;
@@ -470,7 +472,7 @@ __device__ __forceinline__ uint32_t small_rest(const Tabs &T, const Desc &d, int
 #pragma unroll
         for (int b = 0; b < B; b++) {
             const uint32_t off = ((uint32_t)b * kPerRound + lane) * 16;
-            if (MODE != kModeHash && (uint32_t)b < r_win)
+            if (MODE != kModeHash && store && (uint32_t)b < r_win)
                 st16<NT>((uint8_t *)d.dst + off, v[b]);
             o |= v[b].x | v[b].y | v[b].z | v[b].w;
             if (b == 0 && lane == 0)
@@ -492,7 +494,7 @@ __device__ __forceinline__ uint32_t small_rest(const Tabs &T, const Desc &d, int
     for (int b = 0; b < B; b++) {
         const uint32_t r = r0 + b;
         const int p = (int)(r * kPerRound + lane) - (int)z;
-        if (r < r_win && p >= 0)
+        if (r < r_win && p >= 0 && store)
             store_piece<MODE, NT>(d, (uint32_t)p * 16, v[b]);
         o |= v[b].x | v[b].y | v[b].z | v[b].w;
         if (p == 0)
@@ -521,6 +523,17 @@ __device__ __forceinline__ void restore_zero_chunk(const ChunkArgs &a, const Des
         a.bad[d.g] = 1;
         atomicAdd(&a.plan_rw->bad_count, 1ull);
     }
+}
+
+// Pack / hash of a full-length ZERO chunk: its CRC is that of C zero bytes,
+// known beforehand, and the dense image leaves it unwritten.
+__device__ __forceinline__ void record_zero_chunk(const ChunkArgs &a, const Desc &d)
+{
+    uint8_t f = kFlagZero;
+    if (!d.has_base || d.want != a.zero_crc)
+        f |= kFlagDirty;
+    a.crc[d.g] = a.zero_crc;
+    a.flags[d.g] = f;
 }
 
 template <int MODE>
@@ -832,8 +845,23 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
                     restore_zero_chunk<NT>(a, d, lane);
                     continue;
                 }
+                bool store = true;
+                if (MODE != kModeRestore) {
+                    // ZERO is known once the chunk's loads are in: a ZERO
+                    // chunk is not stored, and a full-length one not hashed
+                    uint32_t o = 0;
+#pragma unroll
+                    for (int b = 0; b < kLoadsInFlight; b++)
+                        o |= cur[b].x | cur[b].y | cur[b].z | cur[b].w;
+                    store = __ballot(o != 0) != 0;   // uniform over the wave
+                    if (!store && d.len == C) {
+                        if (lane == 0)
+                            record_zero_chunk(a, d);
+                        continue;
+                    }
+                }
                 uint32_t orv = 0;
-                const uint32_t raw = small_rest<MODE, NT>(T, d, lane, r_win, cur, &orv);
+                const uint32_t raw = small_rest<MODE, NT>(T, d, lane, r_win, cur, &orv, store);
                 const bool nonzero = __ballot(orv != 0) != 0;
                 if (lane == 0)
                     finish_chunk<MODE>(a, d, raw, nonzero);

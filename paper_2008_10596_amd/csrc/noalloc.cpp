@@ -149,6 +149,7 @@ extern "C" int ckpt_checkpoint_noalloc(ckpt_ctx *ctx, void *stream, int mode, co
         a.C = C;
         a.waves_per_chunk = cfg.waves_per_chunk;
         a.nontemporal = cfg.load_hint == 2;
+        a.zero_crc = ctx->zero_crc;
         a.src = addr;
         a.size = size;
         a.off = off;

@@ -403,6 +403,9 @@ int ckpt::ctx_setup(ckpt_ctx *ctx)
     const int per_cu = cfg.wgs_per_cu ? (int)cfg.wgs_per_cu : 1;
     ctx->grid_chunks = ctx->cu_count * per_cu;
     ctx->grid_small = ctx->cu_count * 4;
+    // CRC-32C of C zero bytes (the register from its init through C zero
+    // bytes, then the final complement): the CRC of every full-length ZERO chunk
+    ctx->zero_crc = host_shift(0xFFFFFFFFu, cfg.chunk_bytes) ^ 0xFFFFFFFFu;
     int rc = CKPT_OK;
     ctx->tables = shared_tables(cfg, &rc);
     if (rc != CKPT_OK)
@@ -683,6 +686,7 @@ ChunkArgs ckpt::chunk_args(ckpt_ctx *ctx)
     a.C = ctx->cfg.chunk_bytes;
     a.waves_per_chunk = ctx->cfg.waves_per_chunk;
     a.nontemporal = ctx->cfg.load_hint == 2;
+    a.zero_crc = ctx->zero_crc;
     a.size = (const uint64_t *)ctx->d_size.p;
     a.off = (const uint64_t *)ctx->d_off.p;
     a.cb = (const uint64_t *)ctx->d_cb.p;
@@ -1476,10 +1480,6 @@ int ckpt::restore_impl(ckpt_ctx *ctx, void *stream, const ckpt_image *img, const
     a.soff = (const uint64_t *)ctx->d_soff.p;
     a.want_crc = (const uint32_t *)ctx->d_crc.p;
     a.want_flags = (const uint8_t *)ctx->d_flags.p;
-    if (!ctx->zero_crc_ready) {   // CRC-32C of C zero bytes: init through C zero bytes, xorout
-        ctx->zero_crc = host_shift(0xFFFFFFFFu, ctx->cfg.chunk_bytes) ^ 0xFFFFFFFFu;
-        ctx->zero_crc_ready = true;
-    }
     a.zero_crc = ctx->zero_crc;
     a.bad = (uint8_t *)ctx->d_bad.p;
     DevPlan P;

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -75,6 +76,8 @@ struct Req {
     uint64_t N = 0, data_bytes = 0, live = 0, ser_bytes = 0;
     uint64_t host_charge = 0;       // checkpoint: most pinned bytes its image can take
     bool waited_host = false;       // was held back for host memory
+    bool mem_waited = false;        // a step of it waited for memory
+    Clock::time_point t_mem_wait{};
     // device block and its parts
     uint64_t block_off = 0, block_bytes = 0;
     uint64_t *d_addr = nullptr, *d_size = nullptr, *d_off = nullptr, *d_cb = nullptr, *d_soff = nullptr;
@@ -90,8 +93,16 @@ struct Req {
 
 struct Task {
     Req *req;
-    bool prep;   // prep or finish
+    bool prep;                      // prep or finish
+    Clock::time_point not_before{}; // a finish waiting for pinned host memory
 };
+
+// finish_request: the image's pinned host memory could not be allocated now
+// (the request keeps its staging and is finished again later)
+constexpr int kRetryHost = 1;
+// how long a request (or a step) may wait for memory before it fails
+constexpr double kHostWaitLimitMs = 30000.0;
+constexpr int kHostRetryMs = 2;
 
 }  // namespace
 
@@ -124,6 +135,9 @@ struct ckpt_server {
     // statistics
     uint64_t submitted = 0, completed = 0, failed = 0, bytes = 0, steps = 0;
     uint64_t host_waits = 0, host_peak = 0;
+    char last_error[160] = {};                    // message of the latest failure
+    Clock::time_point t_step_wait{};              // a step waits for memory since
+    bool step_waiting = false;
     uint32_t max_concurrent = 0;
     std::vector<double> lat_ms;
     bool have_first = false;
@@ -304,8 +318,10 @@ int finish_request(ckpt_server *sv, Req *r, hipStream_t s, PinnedBuf &up)
     }
     img->ser_bytes = sel;
     if (alloc_meta(img.get(), N) || img->data.ensure(std::max<uint64_t>(sel, 1))) {
-        r->result.status = CKPT_E_NOMEM;
-        return CKPT_E_NOMEM;
+        // nothing is queued into the image's buffers yet: give them back and
+        // let the caller try again once host memory may have been released
+        sync_on_error.ok = true;
+        return kRetryHost;
     }
     if (sel) {
         GatherArgs g;
@@ -364,6 +380,12 @@ void complete(ckpt_server *sv, Req *r)
     sv->cv_step.notify_all();
 }
 
+// Keeps the failing thread's message (caller holds sv->mu).
+void note_failure(ckpt_server *sv)
+{
+    snprintf(sv->last_error, sizeof(sv->last_error), "%s", ckpt_last_error());
+}
+
 AdmitInfo admit_info(const Req *r)
 {
     AdmitInfo a;
@@ -419,23 +441,70 @@ void aux_loop(ckpt_server *sv)
     (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     PinnedBuf up;
     for (;;) {
-        Task t;
+        Task t{nullptr, false, {}};
         {
             std::unique_lock<std::mutex> lk(sv->mu);
-            sv->cv_aux.wait(lk, [&] { return sv->stop || !sv->aux_tasks.empty(); });
-            if (sv->aux_tasks.empty())
+            for (;;) {
+                if (sv->aux_tasks.empty() && sv->stop)
+                    break;
+                // the first task that may run now; else wait for the earliest
+                const auto now = Clock::now();
+                auto it = std::find_if(sv->aux_tasks.begin(), sv->aux_tasks.end(),
+                                       [&](const Task &x) { return x.not_before <= now; });
+                if (it != sv->aux_tasks.end()) {
+                    t = *it;
+                    sv->aux_tasks.erase(it);
+                    break;
+                }
+                if (sv->aux_tasks.empty()) {
+                    sv->cv_aux.wait(lk);
+                } else {
+                    auto first = sv->aux_tasks.front().not_before;
+                    for (const Task &x : sv->aux_tasks)
+                        first = std::min(first, x.not_before);
+                    sv->cv_aux.wait_until(lk, first);
+                }
+            }
+            if (!t.req)
                 break;   // stopping
-            t = sv->aux_tasks.front();
-            sv->aux_tasks.pop_front();
         }
         Req *r = t.req;
         int rc = t.prep ? prep_request(sv, r, s, up) : finish_request(sv, r, s, up);
         if (rc != CKPT_OK)
             (void)hipStreamSynchronize(s);   // nothing of r may still be queued when its block is freed
+        if (rc == kRetryHost || rc == CKPT_E_NOMEM) {
+            // Memory is short right now: pinned host memory for the image
+            // (kRetryHost) or for a staging buffer, or device memory.  The
+            // request keeps its staging block (a checkpoint: its packed image)
+            // and the same step is run again shortly.  A short image buffer
+            // also makes admission take the pinned bytes held now as the
+            // host's capacity, so later checkpoints queue.
+            const auto now = Clock::now();
+            std::lock_guard<std::mutex> lk(sv->mu);
+            if (!r->mem_waited) {
+                r->mem_waited = true;
+                r->t_mem_wait = now;
+                sv->host_waits++;
+            }
+            if (rc == kRetryHost)
+                sv->adm.host_budget = std::min<uint64_t>(sv->adm.host_budget ? sv->adm.host_budget : UINT64_MAX,
+                                                         std::max<uint64_t>(pinned_live_bytes(), uint64_t(1) << 30));
+            if (ms_between(r->t_mem_wait, now) < kHostWaitLimitMs) {
+                r->result.status = CKPT_OK;
+                sv->aux_tasks.push_back({r, t.prep, now + std::chrono::milliseconds(kHostRetryMs)});
+                sv->cv_aux.notify_one();
+                continue;
+            }
+            rc = set_error(CKPT_E_NOMEM, "memory for the request was not available for %.0f s",
+                           kHostWaitLimitMs / 1000);
+            r->result.status = rc;
+        }
         std::lock_guard<std::mutex> lk(sv->mu);
         if (rc != CKPT_OK || !t.prep) {
             if (rc != CKPT_OK && r->result.status == CKPT_OK)
                 r->result.status = rc;
+            if (rc != CKPT_OK)
+                note_failure(sv);
             complete(sv, r);
         } else {
             r->state = r->N ? kStepping : kFinish;
@@ -634,7 +703,24 @@ void step_loop(ckpt_server *sv)
         int rc = run_step(sv, reqs, ends);
         if (rc != CKPT_OK)
             (void)hipStreamSynchronize(sv->step_stream);
+        if (rc == CKPT_E_NOMEM) {
+            // a step buffer could not grow: the requests keep their place and
+            // the step runs again shortly, for as long as a request may wait
+            const auto now = Clock::now();
+            std::unique_lock<std::mutex> lk(sv->mu);
+            if (!sv->step_waiting) {
+                sv->step_waiting = true;
+                sv->t_step_wait = now;
+            }
+            if (ms_between(sv->t_step_wait, now) < kHostWaitLimitMs) {
+                sv->cv_step.wait_for(lk, std::chrono::milliseconds(kHostRetryMs));
+                continue;
+            }
+        }
         std::lock_guard<std::mutex> lk(sv->mu);
+        sv->step_waiting = false;
+        if (rc != CKPT_OK)
+            note_failure(sv);
         sv->steps++;
         for (size_t i = 0; i < reqs.size(); i++) {
             Req *r = reqs[i];
@@ -855,6 +941,7 @@ extern "C" int ckpt_server_stats(const ckpt_server *csv, ckpt_stats *out)
     out->max_concurrent = sv->max_concurrent;
     out->host_waits = sv->host_waits;
     out->host_peak = sv->host_peak;
+    memcpy(out->last_error, sv->last_error, sizeof(out->last_error));
     std::vector<double> v = sv->lat_ms;
     if (!v.empty()) {
         std::sort(v.begin(), v.end());
@@ -888,6 +975,7 @@ extern "C" int ckpt_server_reset_stats(ckpt_server *sv)
     sv->max_concurrent = sv->adm.n_active;
     sv->host_waits = 0;
     sv->host_peak = 0;
+    sv->last_error[0] = 0;
     sv->lat_ms.clear();
     sv->have_first = false;
     return CKPT_OK;

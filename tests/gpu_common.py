@@ -62,6 +62,37 @@ def r16(x):
     return (x + 15) // 16 * 16
 
 
+def dense_defined(sizes, C, flags):
+    """Mask of the dense image's defined bytes: every byte except those of
+    ZERO chunks and, for a ZERO tail chunk, its pad (the pack may leave ZERO
+    chunks unwritten; their bytes read as zeros by the flags)."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    off, cb, data_bytes, N = O.layout(sizes, C)
+    keep = np.ones(int(data_bytes), bool)
+    z = np.flatnonzero(np.asarray(flags) & FLAG_ZERO)
+    if z.size:
+        cb = np.asarray(cb, np.int64)
+        off = np.asarray(off, np.int64)
+        # the allocation of each chunk: the last k with cb[k] <= g (size-0
+        # allocations share their successor's cb and come before it)
+        k = np.searchsorted(cb, z, side="right") - 1
+        start = (z - cb[k]) * C
+        end = np.minimum(start + C, sizes[k])
+        end = np.where(end == sizes[k], (end + 15) // 16 * 16, end)   # a tail keeps its pad
+        for lo, hi in zip(off[k] + start, off[k] + end):
+            keep[lo:hi] = False
+    return keep
+
+
+def assert_dense(got, want, sizes, C, flags):
+    """The dense image equals the oracle's on every defined byte."""
+    got, want = np.asarray(got), np.asarray(want)
+    assert got.size == want.size
+    keep = dense_defined(sizes, C, flags)
+    diff = np.flatnonzero((got != want) & keep)
+    assert diff.size == 0, "dense image differs at bytes %s" % diff[:10]
+
+
 def check_full(img, ref, tensors, C, ids=None):
     """Bit-exact: allocation table, CRC, FLAGS, serialized DATA."""
     info = img.info()
