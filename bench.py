@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--load-hint", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed pack steps")
+    ap.add_argument("--batched-no-graph", action="store_true",
+                    help="batched section: plain launches of the same kernels instead of the replayed graph")
     ap.add_argument("--batched-only-graph", action="store_true",
                     help="batched section: the graph-replayed batch only (no plain forms, drain or autotuner; "
                          "profiler runs)")
@@ -341,7 +343,8 @@ def bench_batched(K, synth, torch, stream, args, reps=3):
         return statistics.median(w)
 
     # batched, image kept in HBM: one graph replay
-    leader = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN | K.CKPT_TIMING, **tune_kw(args))
+    leader = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN | K.CKPT_TIMING |
+                       (K.CKPT_NO_GRAPH if args.batched_no_graph else 0), **tune_kw(args))
     dev_ms = []
     if elides_zero(C, args.wpc):
         # the pack leaves ZERO chunks unwritten: count the bytes it moves
@@ -397,18 +400,28 @@ def bench_batched(K, synth, torch, stream, args, reps=3):
     log("plain per context: %s" % out["plain_per_context_pack"])
     out["batched_speedup_vs_plain_per_allocation"] = round(wall_pa / wall, 2)
     out["batched_speedup_vs_plain_per_context"] = round(wall_pc / wall, 2)
-    # with the drain to pinned host memory
-    dleader = K.Context(chunk_bytes=C, flags=K.CKPT_TIMING, **tune_kw(args))
+    # with the drain to pinned host memory: in the replayed graph (the gather
+    # stores into each image's pinned buffer), and without graphs (segments
+    # through device staging and the runtime's copies)
+    ser = {}
 
-    def batched_drain():
-        for im in K.checkpoint_batch([dleader] + members, stream=stream):
-            im.close()
-    wall_d = timed(batched_drain, 1)
-    out["batched_with_drain"] = {"wall_ms": round(wall_d, 1)}
-    log("batched with drain: %s" % out["batched_with_drain"])
+    def drained(leader_flags, key):
+        dl = K.Context(chunk_bytes=C, flags=K.CKPT_TIMING | leader_flags, **tune_kw(args))
+
+        def once():
+            imgs = K.checkpoint_batch([dl] + members, stream=stream)
+            ser[key] = sum(im.info()["serialized_bytes"] for im in imgs)
+            for im in imgs:
+                im.close()
+        w = timed(once, 2)
+        dl.close()
+        return {"wall_ms": round(w, 1), "serialized_bytes": ser[key],
+                "link_gbps": round(ser[key] / (w * 1e-3) / 1e9, 2)}
+    out["batched_with_drain"] = drained(0, "graph")
+    out["batched_with_drain_no_graph"] = drained(K.CKPT_NO_GRAPH, "plain")
+    log("batched with drain: %s; without graphs: %s" % (out["batched_with_drain"], out["batched_with_drain_no_graph"]))
     leader.close()
     pctx.close()
-    dleader.close()
     for c in members:
         c.close()
     # autotuner sweep on the same contexts

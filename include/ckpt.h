@@ -104,7 +104,9 @@ enum ckpt_status {
                                      host memory instead of gather + copy engine */
 #define CKPT_GRAPH          0x20u /* ckpt_checkpoint: replay a captured hipGraph of
                                      the table upload, size scan, chunk map and
-                                     pack (full checkpoints without a base)      */
+                                     pack, and of the drain's select and gather
+                                     into pinned host memory (full checkpoints
+                                     without a base)                              */
 #define CKPT_NO_GRAPH       0x40u /* ckpt_checkpoint_batch: plain launches instead
                                      of the captured graph it uses by default    */
 #define CKPT_RESERVE_STAGING 0x80u /* ckpt_init allocates the whole staging_budget
@@ -205,7 +207,8 @@ typedef struct ckpt_timing {
     float layout_ms;      /* descriptor upload + size scan + chunk map            */
     float pack_ms;        /* fused pack + CRC + flags (or hash-only) kernel; with a
                              replayed graph, the whole graph (upload, scan, map,
-                             pack) and layout_ms is 0                              */
+                             pack, and a drain's select and gather into host
+                             memory) and layout_ms is 0                            */
     float select_ms;      /* flag scan / compaction                                */
     float gather_ms;      /* gather of selected chunks, summed over the segments    */
     float d2h_ms;         /* device-to-host copy of data + metadata: from the start
@@ -572,8 +575,14 @@ void ckpt_image_free(ckpt_image *img);
  * Checkpoint (CKPT_FULL) several contexts in one pass: every context's
  * registrations are laid out in one table and packed by one persistent
  * kernel launch, replayed from a captured hipGraph (table upload from pinned
- * memory, size scan, chunk map, pack; captured again only when the table
- * outgrows the capacities of the last capture).  outs[i] is the image of
+ * memory, size scan, chunk map, pack, and, unless ctxs[0] has CKPT_NO_DRAIN,
+ * the drain: the select and a gather that stores each context's non-ZERO
+ * chunks straight into that image's pinned host buffer; captured again only
+ * when the table or the number of contexts outgrows the capacities of the
+ * last capture).  The host buffers are taken before the replay with room for
+ * each context's dense bytes.  With CKPT_NO_GRAPH (ctxs[0]) the kernels are
+ * launched one by one and the drain goes through device staging in segments
+ * and the runtime's copies.  outs[i] is the image of
  * ctxs[i], identical to what ckpt_checkpoint(ctxs[i], stream, CKPT_FULL,
  * NULL, ...) produces.  All contexts must be on one device with one chunk
  * size (else CKPT_E_INVAL); ctxs[0] provides the launch configuration,

@@ -223,6 +223,8 @@ struct ckpt_ctx {
     // captured prologue (graph_prologue) and what it was captured for
     hipGraphExec_t g_exec = nullptr;
     uint64_t g_n = 0, g_N = 0, g_D = 0;
+    bool g_drain = false;        // the graph also holds the drain (select + gather into host memory)
+    uint64_t g_outs = 0;         // outputs the drain tables hold
     std::vector<void *> g_ptrs;
     uint64_t graph_captures = 0;
 
@@ -243,6 +245,7 @@ struct ckpt_ctx {
     ckpt::DevBuf d_plan, d_addr, d_size, d_off, d_cb, d_map;
     ckpt::DevBuf d_crc, d_flags, d_base_crc, d_prev_crc, d_soff, d_ids, d_tile_b, d_tile_c;
     ckpt::DevBuf d_dense, d_compact, d_bad, d_pick, d_crc2, d_flags2, d_soff2, d_base_cb, d_snap_flags;
+    ckpt::DevBuf d_drain;   // the graph's drain tables: out_addr, out_chunk0, row_out
     ckpt::PinnedBuf h_up, h_plan, h_base_cb;
     bool reserved = false;      // CKPT_RESERVE_STAGING: d_dense is the reserved block
     uint64_t prev_serial = 0;   // image whose CRC array is in d_prev_crc
@@ -254,7 +257,7 @@ struct ckpt_ctx {
     {
         return {&d_plan, &d_addr, &d_size, &d_off, &d_cb, &d_map, &d_crc, &d_flags, &d_base_crc,
                 &d_prev_crc, &d_soff, &d_ids, &d_tile_b, &d_tile_c, &d_dense, &d_compact, &d_bad, &d_pick,
-                &d_crc2, &d_flags2, &d_soff2, &d_base_cb, &d_snap_flags};
+                &d_crc2, &d_flags2, &d_soff2, &d_base_cb, &d_snap_flags, &d_drain};
     }
 };
 
@@ -306,7 +309,17 @@ uint64_t segment_bytes(const ckpt_config &cfg);
 constexpr int kSegSlots = 4;
 // At least n events in ctx->seg_ev.
 int seg_events(ckpt_ctx *ctx, size_t n);
-int graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, uint64_t N, uint64_t data_bytes);
+// The drain a replayed graph may hold: the selected chunks of output i go
+// straight into pinned host buffer (*data)[i], which holds at least output
+// i's dense bytes.
+struct GraphDrain {
+    size_t nout;
+    const uint64_t *part_row;     // nout + 1: each output's first row, then n
+    const uint64_t *part_chunk;   // nout + 1: each output's first chunk, then N
+    std::vector<PinnedBuf> *data;
+};
+int graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, uint64_t N, uint64_t data_bytes,
+                   const GraphDrain *drain = nullptr);
 int upload_table(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, bool dst_side, uint64_t N_host,
                  uint64_t n_items);
 int read_plan(ckpt_ctx *ctx, hipStream_t s, DevPlan *out);

@@ -179,6 +179,14 @@ struct GatherArgs {
     uint64_t g_begin, g_end, soff_base;
     uint32_t tile;            // chunks per wave step (1 .. 64, a power of two); set by launch_gather
     uint32_t pad;
+    // Several outputs straight into host memory (the drain inside the batched
+    // graph), when out_addr is not null: chunk g of allocation row k belongs
+    // to output o = row_out[k], whose serialized bytes start at host address
+    // out_addr[o]; g's bytes go to out_addr[o] + soff[g] - soff[out_chunk0[o]]
+    // (out and soff_base are unused).
+    const uint64_t *out_addr;
+    const uint32_t *row_out;
+    const uint64_t *out_chunk0;
 };
 
 // Launch wrappers (kernels.hip).  All return the hipError_t of the launch.

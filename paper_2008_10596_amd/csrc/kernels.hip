@@ -1172,7 +1172,8 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_down(SelArgs a)
 // --------------------------------------------------------------- K6: gather
 //
 // Copies each selected chunk (roundup16(len) bytes) to out + soff[g], from the
-// dense image or straight from the allocation (zero pad written, never read).
+// dense image or straight from the allocation (zero pad written, never read);
+// or, for several outputs in host memory, into each output's own buffer.
 // Each wave takes `tile` consecutive chunks (up to 64, fewer when a launch
 // covers few chunks, so that every wave of the grid has work): lane l fetches
 // the descriptor of chunk t0 + l, so the descriptor loads are in flight
@@ -1237,7 +1238,12 @@ __global__ __launch_bounds__(1024) void k_gather(GatherArgs a)
                 const uint64_t rest = a.size[k] - start;
                 len = (uint32_t)(rest < a.C ? rest : a.C);
                 src = a.from_dense ? (uint64_t)(a.dense + a.off[k] + start) : a.src[k] + start;
-                dst = (uint64_t)(a.out + (so - a.soff_base));
+                if (a.out_addr) {
+                    const uint32_t o = a.row_out[k];
+                    dst = a.out_addr[o] + (so - a.soff[a.out_chunk0[o]]);
+                } else {
+                    dst = (uint64_t)(a.out + (so - a.soff_base));
+                }
             }
         }
         uint64_t m = __ballot(take);

@@ -746,32 +746,45 @@ bool same_table(const ckpt_image *a, const ckpt_image *b)
 // ------------------------------------------------------------ graph prologue
 //
 // The device part of a full checkpoint without a base -- table upload from
-// pinned memory, size scan, chunk map, pack -- captured once in a hipGraph and
+// pinned memory, size scan, chunk map, pack, and, when the checkpoint drains,
+// the select and a gather that stores every output's non-ZERO chunks straight
+// into that output's pinned host buffer -- captured once in a hipGraph and
 // replayed.  Every kernel reads its counts from the device plan, so one graph
 // serves any table that fits the capacities it was captured with; the host
-// only rewrites the pinned upload buffer.  A changed buffer address (a
-// buffer grown by another call) forces a new capture.
+// only rewrites the pinned upload buffer (descriptors, and for the drain each
+// output's host address, first chunk, and each row's output).  A changed
+// buffer address (a buffer grown by another call) forces a new capture.
 
 namespace {
 uint64_t grow(uint64_t x, uint64_t floor) { return std::max<uint64_t>(floor, x + x / 4); }
 }  // namespace
 
 int ckpt::graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, uint64_t N,
-                         uint64_t data_bytes)
+                         uint64_t data_bytes, const GraphDrain *drain)
 {
     const uint64_t n = rows.size();
-    std::vector<void *> ptrs = {ctx->d_plan.p, ctx->d_addr.p, ctx->d_size.p, ctx->d_off.p, ctx->d_cb.p,
-                                ctx->d_map.p,  ctx->d_crc.p,  ctx->d_flags.p, ctx->d_dense.p, ctx->h_up.p};
+    const size_t nout = drain ? drain->nout : 0;
+    auto buffers = [&]() {
+        std::vector<void *> v = {ctx->d_plan.p, ctx->d_addr.p, ctx->d_size.p, ctx->d_off.p, ctx->d_cb.p,
+                                 ctx->d_map.p,  ctx->d_crc.p,  ctx->d_flags.p, ctx->d_dense.p, ctx->h_up.p};
+        if (drain)
+            for (void *p : {ctx->d_soff.p, ctx->d_tile_b.p, ctx->d_tile_c.p, ctx->d_drain.p})
+                v.push_back(p);
+        return v;
+    };
     const bool fits = ctx->g_exec && n <= ctx->g_n && N <= ctx->g_N && data_bytes <= ctx->g_D &&
-                      ptrs == ctx->g_ptrs;
+                      (drain != nullptr) == ctx->g_drain && nout <= ctx->g_outs && buffers() == ctx->g_ptrs;
     if (!fits) {
         if (ctx->g_exec) {
             (void)hipGraphExecDestroy(ctx->g_exec);
             ctx->g_exec = nullptr;
         }
-        const uint64_t nc = grow(n, 64), Nc = grow(N, 1024);
+        const uint64_t nc = grow(n, 64), Nc = grow(N, 1024), oc = drain ? grow(nout, 8) : 0;
         // a reserved dense block is kept (a larger image is refused by the budget)
         const uint64_t Dc = ctx->reserved ? std::max<uint64_t>(data_bytes, ctx->d_dense.cap) : grow(data_bytes, 1 << 20);
+        // the drain tables: out_addr[oc], out_chunk0[oc], row_out[nc] (u32)
+        const uint64_t drain_bytes = drain ? 16 * oc + 4 * nc : 0;
+        const uint64_t tiles = (Nc + kSelTile - 1) / kSelTile;
         CKPT_TRY(ctx->d_addr.ensure(nc * 8));
         CKPT_TRY(ctx->d_size.ensure(nc * 8));
         CKPT_TRY(ctx->d_off.ensure((nc + 1) * 8));
@@ -780,7 +793,13 @@ int ckpt::graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &r
         CKPT_TRY(ctx->d_crc.ensure(Nc * 4));
         CKPT_TRY(ctx->d_flags.ensure(Nc));
         CKPT_TRY(ctx->d_dense.ensure(Dc));
-        CKPT_TRY(ctx->h_up.ensure(sizeof(DevPlan) + 16 * nc));
+        if (drain) {
+            CKPT_TRY(ctx->d_soff.ensure(Nc * 8));
+            CKPT_TRY(ctx->d_tile_b.ensure(tiles * 8));
+            CKPT_TRY(ctx->d_tile_c.ensure(tiles * 8));
+            CKPT_TRY(ctx->d_drain.ensure(drain_bytes));
+        }
+        CKPT_TRY(ctx->h_up.ensure(sizeof(DevPlan) + 16 * nc + drain_bytes));
         uint8_t *up = (uint8_t *)ctx->h_up.p;
         hipStream_t c = ctx->cap;
         HIP_TRY(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
@@ -789,6 +808,9 @@ int ckpt::graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &r
             HIP_TRY(hipMemcpyAsync(ctx->d_plan.p, up, sizeof(DevPlan), hipMemcpyHostToDevice, c));
             HIP_TRY(hipMemcpyAsync(ctx->d_addr.p, up + sizeof(DevPlan), 8 * nc, hipMemcpyHostToDevice, c));
             HIP_TRY(hipMemcpyAsync(ctx->d_size.p, up + sizeof(DevPlan) + 8 * nc, 8 * nc, hipMemcpyHostToDevice, c));
+            if (drain)
+                HIP_TRY(hipMemcpyAsync(ctx->d_drain.p, up + sizeof(DevPlan) + 16 * nc, drain_bytes,
+                                       hipMemcpyHostToDevice, c));
             HIP_TRY(launch_layout_scan(c, (DevPlan *)ctx->d_plan.p, (const uint64_t *)ctx->d_size.p,
                                        ctx->cfg.chunk_bytes, (uint64_t *)ctx->d_off.p, (uint64_t *)ctx->d_cb.p));
             HIP_TRY(launch_chunk_map(c, (const DevPlan *)ctx->d_plan.p, (const uint64_t *)ctx->d_cb.p,
@@ -799,6 +821,42 @@ int ckpt::graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &r
             a.crc = (uint32_t *)ctx->d_crc.p;
             a.flags = (uint8_t *)ctx->d_flags.p;
             HIP_TRY(launch_chunks(c, kModePack, a, ctx->grid_chunks, ctx->cfg.block_threads));
+            if (drain) {
+                // the drain: serialized offsets of the non-ZERO chunks, then each
+                // chunk straight into its output's pinned host buffer
+                SelArgs sa;
+                memset(&sa, 0, sizeof(sa));
+                sa.plan = (DevPlan *)ctx->d_plan.p;
+                sa.mode = kSelNonZero;
+                sa.C = ctx->cfg.chunk_bytes;
+                sa.size = (const uint64_t *)ctx->d_size.p;
+                sa.cb = (const uint64_t *)ctx->d_cb.p;
+                sa.map = (const uint32_t *)ctx->d_map.p;
+                sa.flags = (const uint8_t *)ctx->d_flags.p;
+                sa.tile_bytes = (uint64_t *)ctx->d_tile_b.p;
+                sa.tile_count = (uint64_t *)ctx->d_tile_c.p;
+                sa.soff = (uint64_t *)ctx->d_soff.p;
+                HIP_TRY(launch_select(c, sa, Nc));
+                GatherArgs ga;
+                memset(&ga, 0, sizeof(ga));
+                ga.plan = (const DevPlan *)ctx->d_plan.p;
+                ga.mode = kSelNonZero;
+                ga.from_dense = 1;
+                ga.C = ctx->cfg.chunk_bytes;
+                ga.src = (const uint64_t *)ctx->d_addr.p;
+                ga.size = (const uint64_t *)ctx->d_size.p;
+                ga.off = (const uint64_t *)ctx->d_off.p;
+                ga.cb = (const uint64_t *)ctx->d_cb.p;
+                ga.map = (const uint32_t *)ctx->d_map.p;
+                ga.dense = (const uint8_t *)ctx->d_dense.p;
+                ga.flags = (const uint8_t *)ctx->d_flags.p;
+                ga.soff = (const uint64_t *)ctx->d_soff.p;
+                ga.out_host = 1;
+                ga.out_addr = (const uint64_t *)ctx->d_drain.p;
+                ga.out_chunk0 = (const uint64_t *)ctx->d_drain.p + oc;
+                ga.row_out = (const uint32_t *)((const uint64_t *)ctx->d_drain.p + 2 * oc);
+                HIP_TRY(launch_gather(c, ga, 2 * ctx->cu_count));
+            }
             return CKPT_OK;
         };
         const int rc = capture();
@@ -819,8 +877,9 @@ int ckpt::graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &r
         ctx->g_n = nc;
         ctx->g_N = Nc;
         ctx->g_D = Dc;
-        ctx->g_ptrs = {ctx->d_plan.p, ctx->d_addr.p, ctx->d_size.p, ctx->d_off.p, ctx->d_cb.p,
-                       ctx->d_map.p,  ctx->d_crc.p,  ctx->d_flags.p, ctx->d_dense.p, ctx->h_up.p};
+        ctx->g_drain = drain != nullptr;
+        ctx->g_outs = oc;
+        ctx->g_ptrs = buffers();
         ctx->graph_captures++;
     }
     // New descriptor contents in the captured upload buffer.  The previous
@@ -834,6 +893,16 @@ int ckpt::graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &r
     for (uint64_t k = 0; k < n; k++) {
         addr[k] = rows[k].ptr;
         size[k] = rows[k].size;
+    }
+    if (drain) {
+        uint64_t *out_addr = size + ctx->g_n, *out_chunk0 = out_addr + ctx->g_outs;
+        auto *row_out = (uint32_t *)(out_chunk0 + ctx->g_outs);
+        for (size_t i = 0; i < nout; i++) {
+            out_addr[i] = (uint64_t)(uintptr_t)(*drain->data)[i].p;
+            out_chunk0[i] = drain->part_chunk[i];
+            for (uint64_t k = drain->part_row[i]; k < drain->part_row[i + 1]; k++)
+                row_out[k] = (uint32_t)i;
+        }
     }
     HIP_TRY(hipGraphLaunch(ctx->g_exec, s));
     return CKPT_OK;
@@ -901,6 +970,20 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
                 HIP_TRY(hipMemPrefetchAsync((const void *)r.ptr, r.size, cfg.device, s));
 
     const bool graph = use_graph && !incremental && !base && !keep_dense;
+    // A replayed graph also holds the drain when there is one: select, then a
+    // gather that stores each output's chunks straight into its pinned host
+    // buffer (sized to the output's dense bytes, which bound its serialized bytes).
+    const bool graph_drain = graph && !no_drain && !direct;
+    // Per-output slices: rows [parts[i], parts[i+1]) -> chunks [cb_i, cb_i+1)
+    // -> serialized bytes [soff(cb_i), soff(cb_i+1)).
+    const size_t nout = outs.size();
+    std::vector<uint64_t> part_row(nout + 1), part_chunk(nout + 1), part_data(nout + 1, 0);
+    for (size_t i = 0; i < nout; i++)
+        part_row[i] = parts[i];
+    part_row[nout] = n;
+    for (size_t i = 0; i <= nout; i++)
+        part_chunk[i] = L.cb[part_row[i]];
+    std::vector<PinnedBuf> data(nout);
     uint8_t *dense = nullptr;
     void *dense_owned = nullptr;
     struct DenseGuard {
@@ -910,9 +993,14 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     if (timing)
         HIP_TRY(hipEventRecord(ctx->ev[0], s));
     if (graph) {
-        // the replayed graph holds the upload, scan, map and pack: ev[0] -> ev[2]
-        // spans all of it (layout_ms is reported as 0)
-        CKPT_TRY(graph_prologue(ctx, s, rows, N, L.data_bytes));
+        // the replayed graph holds the upload, scan, map and pack (and the
+        // drain's select and gather): ev[0] -> ev[2] spans all of it (layout_ms
+        // is reported as 0)
+        GraphDrain gd{nout, part_row.data(), part_chunk.data(), &data};
+        if (graph_drain)
+            for (size_t i = 0; i < nout; i++)
+                CKPT_TRY(data[i].ensure(std::max<uint64_t>(L.off[part_row[i + 1]] - L.off[part_row[i]], 16)));
+        CKPT_TRY(graph_prologue(ctx, s, rows, N, L.data_bytes, graph_drain ? &gd : nullptr));
         dense = (uint8_t *)ctx->d_dense.p;
         if (timing) {
             HIP_TRY(hipEventRecord(ctx->ev[2], s));
@@ -989,8 +1077,6 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     uint64_t *d_soff = (uint64_t *)ctx->d_soff.p;
     DevPlan P;
     uint8_t *d_out = nullptr;        // where the gather writes (device compact or pinned host)
-    std::vector<PinnedBuf> data(outs.size());
-    PinnedBuf all_data;              // one pinned buffer when there is a single output
 
     hipStream_t ds = ctx->side;      // drain stream: the copies to the host
     hipStream_t gs = ctx->side;      // the stream the gather runs on
@@ -1020,6 +1106,8 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
         if (no_drain) {
             P.sel_bytes = 0;
             P.sel_count = 0;
+        } else if (graph_drain) {
+            CKPT_TRY(read_plan(ctx, ds, &P));   // the graph has selected and gathered
         } else {
             CKPT_TRY(run_select(ctx, ds, kSelNonZero, a.flags, nullptr, N, d_soff, nullptr, 0));
             CKPT_TRY(read_plan(ctx, ds, &P));
@@ -1028,15 +1116,6 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     if (timing)
         HIP_TRY(hipEventRecord(ctx->ev[4], gs));
 
-    // Per-output slices: rows [parts[i], parts[i+1]) -> chunks [cb_i, cb_i+1)
-    // -> serialized bytes [soff(cb_i), soff(cb_i+1)).
-    const size_t nout = outs.size();
-    std::vector<uint64_t> part_row(nout + 1), part_chunk(nout + 1), part_data(nout + 1, 0);
-    for (size_t i = 0; i < nout; i++)
-        part_row[i] = parts[i];
-    part_row[nout] = n;
-    for (size_t i = 0; i <= nout; i++)
-        part_chunk[i] = L.cb[part_row[i]];
     const uint64_t sel_bytes = no_drain ? 0 : P.sel_bytes;
     // A full checkpoint drains in segments of seg_chunks chunks: each
     // segment's gather (on the gather stream, into one of kSegSlots device
@@ -1046,7 +1125,7 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     // link); CKPT_DRAIN_DIRECT stores to the host from the gather itself.
     const uint64_t seg_b = segment_bytes(cfg);
     const uint64_t seg_chunks = seg_b ? std::max<uint64_t>(1, seg_b / C) : 0;
-    const uint64_t n_seg = (!no_drain && sel_bytes && !incremental && !direct && seg_b)
+    const uint64_t n_seg = (!no_drain && sel_bytes && !incremental && !direct && !graph_drain && seg_b)
                                ? (N + seg_chunks - 1) / seg_chunks : 0;
     const bool segmented = n_seg > 1;
     const uint64_t slot_bytes = seg_chunks * C;   // a segment's serialized bytes never exceed this
@@ -1080,7 +1159,7 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
 
     // Drain: gather the selected chunks, then copy them to pinned host memory.
     uint64_t n_timed = 0;   // segments with per-segment gather events
-    if (!no_drain && sel_bytes) {
+    if (!no_drain && sel_bytes && !graph_drain) {
         const uint64_t stage = segmented ? std::min<uint64_t>(sel_bytes, kSegSlots * slot_bytes) : sel_bytes;
         if (cfg.staging_budget && !direct && (incremental ? 0 : L.data_bytes) + stage > cfg.staging_budget)
             return set_error(CKPT_E_BUDGET, "drain staging %llu B exceeds the budget",
