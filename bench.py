@@ -480,7 +480,9 @@ def hbm_ceilings(torch, nbytes, reps=3):
     """Plain read, write and copy kernels (libckpt_probe.so, not on the path)
     swept over pieces per lane in flight, workgroups per CU and load/store
     hints: the most this GPU moves for each kind of traffic.  read and write
-    touch nbytes; copy reads nbytes / 2 and writes nbytes / 2."""
+    touch nbytes; the copies read nbytes / 2 and write nbytes / 2 (copy: both
+    hints alike; copy_nt_loads / copy_nt_stores: only the loads / only the
+    stores non-temporal)."""
     import ctypes
     from paper_2008_10596_amd import build as B
     if not os.path.exists(B.PROBE_LIB):
@@ -498,16 +500,16 @@ def hbm_ceilings(torch, nbytes, reps=3):
     stream = torch.cuda.current_stream()
     half = nbytes // 2 // 16 * 16
     table, best = [], {}
-    for kind, name in ((0, "read"), (1, "write"), (2, "copy")):
+    for kind, name in ((0, "read"), (1, "write"), (2, "copy"), (3, "copy_nt_loads"), (4, "copy_nt_stores")):
         for loads in (4, 8, 16):
             for per_cu in (1, 2):
-                for nt in (0, 1):
+                for nt in ((0, 1) if kind < 3 else (1,)):
                     if kind == 0:
                         args = (a.data_ptr(), sink.data_ptr(), nbytes)
                     elif kind == 1:
                         args = (None, b.data_ptr(), nbytes)
                     else:
-                        args = (a.data_ptr(), a.data_ptr() + half, half)
+                        args = (a.data_ptr(), a.data_ptr() + half, half)   # the copies move half each way
                     def launch():
                         rc = lib.probe_launch(kind, args[0], args[1], args[2], loads, nt, cus * per_cu, 1024,
                                               ctypes.c_void_p(stream.cuda_stream))
@@ -523,7 +525,7 @@ def hbm_ceilings(torch, nbytes, reps=3):
                         e1.synchronize()
                         ms.append(e0.elapsed_time(e1))
                     m = statistics.median(ms)
-                    moved = nbytes if kind != 2 else 2 * half
+                    moved = nbytes if kind < 2 else 2 * half
                     row = {"kind": name, "loads_per_lane": loads, "wgs_per_cu": per_cu, "nontemporal": nt,
                            "ms": round(m, 4), "gbps": round(moved / (m * 1e-3) / 1e9, 1)}
                     table.append(row)

@@ -96,6 +96,29 @@ __global__ __launch_bounds__(1024) void k_copy(const u32x4 *__restrict__ src, u3
     }
 }
 
+// A copy whose loads and stores take separate hints (NL: loads, NS: stores).
+template <int U, bool NL, bool NS>
+__global__ __launch_bounds__(1024) void k_copy2(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, uint64_t n16)
+{
+    const uint64_t lane = threadIdx.x & 63;
+    const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t W = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t base = w * 64 * U; base < n16; base += W * 64 * U) {
+        u32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint64_t p = base + u * 64 + lane;
+            v[u] = p < n16 ? ld<NL>(src + p) : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint64_t p = base + u * 64 + lane;
+            if (p < n16)
+                st<NS>(dst + p, v[u]);
+        }
+    }
+}
+
 template <int U, bool NT>
 void launch(int kind, const void *src, void *dst, uint64_t n16, int grid, int block, hipStream_t s)
 {
@@ -103,19 +126,27 @@ void launch(int kind, const void *src, void *dst, uint64_t n16, int grid, int bl
         hipLaunchKernelGGL((k_read<U, NT>), dim3(grid), dim3(block), 0, s, (const u32x4 *)src, n16, (uint32_t *)dst);
     else if (kind == 1)
         hipLaunchKernelGGL((k_write<U, NT>), dim3(grid), dim3(block), 0, s, (u32x4 *)dst, n16, 0u);
-    else
+    else if (kind == 2)
         hipLaunchKernelGGL((k_copy<U, NT>), dim3(grid), dim3(block), 0, s, (const u32x4 *)src, (u32x4 *)dst, n16);
+    else if (kind == 3)   // non-temporal loads only when NT, regular stores
+        hipLaunchKernelGGL((k_copy2<U, NT, false>), dim3(grid), dim3(block), 0, s, (const u32x4 *)src, (u32x4 *)dst,
+                           n16);
+    else                  // regular loads, non-temporal stores only when NT
+        hipLaunchKernelGGL((k_copy2<U, false, NT>), dim3(grid), dim3(block), 0, s, (const u32x4 *)src, (u32x4 *)dst,
+                           n16);
 }
 
 }  // namespace
 
-// kind: 0 read (dst: a 4-byte sink), 1 write, 2 copy.  bytes: a multiple of
+// kind: 0 read (dst: a 4-byte sink), 1 write, 2 copy, 3 copy with only the
+// loads non-temporal (when nt), 4 copy with only the stores non-temporal
+// (when nt).  bytes: a multiple of
 // 16.  loads: 1, 2, 4, 8 or 16 pieces per lane per iteration; nt: 0/1.
 // Returns 0, or -1 for bad arguments, or the hipError_t of the launch.
 extern "C" int probe_launch(int kind, const void *src, void *dst, uint64_t bytes, int loads, int nt, int grid,
                             int block, void *stream)
 {
-    if (kind < 0 || kind > 2 || bytes % 16 || grid <= 0 || (block != 256 && block != 512 && block != 1024))
+    if (kind < 0 || kind > 4 || bytes % 16 || grid <= 0 || (block != 256 && block != 512 && block != 1024))
         return -1;
     if ((kind != 1 && !src) || !dst)
         return -1;

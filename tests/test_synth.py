@@ -89,3 +89,26 @@ def test_bench_algorithmic_bytes_match_the_layout(C):
     _, _, data_bytes, n_chunks = O.layout(sizes, C)
     assert S == sum(sizes) and dense == data_bytes and N == n_chunks
     assert alg == S + dense + 5 * N
+
+
+@pytest.mark.parametrize("C", [4096, 1024])
+def test_bench_bytes_with_flags_are_the_serialized_bytes(C):
+    """With the chunks' flags, the bench counts as written exactly what a
+    drained image holds: the oracle's serialized bytes."""
+    import bench
+    rng = np.random.default_rng(C)
+    sizes = [int(x) for x in rng.integers(0, 20000, 40)]
+    allocs = []
+    for k, n in enumerate(sizes):
+        a = rng.integers(0, 256, n, dtype=np.uint8)
+        if k % 3 == 0:
+            a[:] = 0                                  # whole allocation ZERO
+        elif k % 3 == 1 and n > C:
+            a[:C] = 0                                 # one ZERO chunk
+        allocs.append(a)
+    ref = O.checkpoint(allocs, C)
+    S, dense, N, alg = bench.algorithmic_bytes(sizes, C, ref["flags"])
+    assert alg == S + ref["serialized_bytes"] + 5 * N
+    assert bench.stored_bytes(sizes, C, ref["flags"]) == ref["serialized_bytes"]
+    assert bench.elides_zero(4096, 0) and bench.elides_zero(4096, 1)
+    assert not bench.elides_zero(8192, 0) and not bench.elides_zero(4096, 2)
