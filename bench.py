@@ -178,8 +178,16 @@ def cpu_baseline(tensors, sizes, C, budget_bytes=8 << 30, reps=3):
     t1 = statistics.median(t1s)
     cpu = ""
     try:
+        # the model name, with family and model numbers (some hosts report only
+        # the brand in the name) and the logical CPUs the host has
+        info = {}
         with open("/proc/cpuinfo") as f:
-            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+            for l in f:
+                k, _, v = l.partition(":")
+                info.setdefault(k.strip(), v.strip())
+        cpu = "%s (family %s, model %s, stepping %s; %d logical CPUs on the host)" % (
+            info.get("model name", "?"), info.get("cpu family", "?"), info.get("model", "?"),
+            info.get("stepping", "?"), os.cpu_count() or 0)
     except OSError:
         pass
     return {"value": round(alg / t / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",

@@ -56,7 +56,7 @@ struct DevPlan {
     uint64_t sel_bytes;   // selection scan: total selected bytes
     uint64_t sel_count;   // selection scan: total selected ids
     unsigned long long bad_count;  // restore: chunks that failed verification
-    uint64_t pad;
+    unsigned long long tile_next;  // chunk launches: the next tile to take (zero between launches)
 };
 
 enum ChunkMode { kModePack = 0, kModeHash = 1, kModeRestore = 2 };

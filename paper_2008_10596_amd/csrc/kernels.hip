@@ -554,6 +554,38 @@ __device__ __forceinline__ void finish_chunk(const ChunkArgs &a, const Desc &d, 
     }
 }
 
+// One chunk of the one-wave form, its loads in v: a full-length ZERO chunk
+// of a restore is written as zeros; in a pack or hash, ZERO is known once the
+// loads are in, so a ZERO chunk is not stored and a full-length one not
+// hashed; every other chunk is hashed (and stored) and finished.
+template <int MODE, bool NT>
+__device__ __forceinline__ void small_chunk(const ChunkArgs &a, const Tabs &T, const Desc &d, int lane,
+                                            uint32_t r_win, uint32_t C, uint4 (&v)[kLoadsInFlight])
+{
+    if (MODE == kModeRestore && d.zero && d.len == C) {   // uniform over the wave
+        restore_zero_chunk<NT>(a, d, lane);
+        return;
+    }
+    bool store = true;
+    if (MODE != kModeRestore) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int b = 0; b < kLoadsInFlight; b++)
+            o |= v[b].x | v[b].y | v[b].z | v[b].w;
+        store = __ballot(o != 0) != 0;   // uniform over the wave
+        if (!store && d.len == C) {
+            if (lane == 0)
+                record_zero_chunk(a, d);
+            return;
+        }
+    }
+    uint32_t orv = 0;
+    const uint32_t raw = small_rest<MODE, NT>(T, d, lane, r_win, v, &orv, store);
+    const bool nonzero = __ballot(orv != 0) != 0;
+    if (lane == 0)
+        finish_chunk<MODE>(a, d, raw, nonzero);
+}
+
 // Balanced interleaved rounds: the M items go in R rounds of at most
 // gridDim.x * tile; round r covers [floor(M r / R), floor(M (r+1) / R)) and is
 // split evenly over the workgroups.  Every quotient is formed once: with
@@ -723,6 +755,22 @@ __device__ __forceinline__ uint32_t quad_combine(const Tabs &T, uint32_t acc, in
     return acc;
 }
 
+// The tile counter of a chunk launch: every workgroup takes tiles until its
+// first miss (a value of at least n_tiles), so a launch makes n_tiles + grid
+// takes.  The workgroup whose miss is the last take of the launch sets the
+// counter back to zero for the next launch on the same plan (launches on one
+// plan are stream-ordered; the host writes every plan with a zero counter).
+__device__ __forceinline__ uint64_t take_tile(DevPlan *p)
+{
+    return atomicAdd(&p->tile_next, 1ull);
+}
+
+__device__ __forceinline__ void tiles_done(DevPlan *p, uint64_t miss, uint64_t n_tiles)
+{
+    if (miss == n_tiles + gridDim.x - 1)
+        atomicExch(&p->tile_next, 0ull);
+}
+
 // FORM: kFormWave (one or more waves per chunk), kFormSmall (every chunk is
 // one batch of rounds and one wave hashes it; the wave keeps the next chunk's
 // loads in flight while it finishes the current one) or kFormQuad (above).
@@ -757,25 +805,41 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
     const uint64_t M = (MODE != kModeRestore) ? a.plan->n_chunks
                        : a.item_end ? a.item_end - a.item_begin : a.plan->n_items;
 
-    // The items go in rounds of at most gridDim.x * kTile, each split evenly
-    // over the workgroups, so the whole grid sweeps one window of memory at a
-    // time and no workgroup gets more than one item above another.
+    // The items go in tiles that the workgroups take in order from a counter
+    // in the plan, one tile ahead (thread 0 takes the tile after the next
+    // while the workgroup works on the current one), so the grid sweeps the
+    // memory in order and a workgroup whose tiles are cheap (ZERO chunks,
+    // read only) takes more of them.
     const int tile = kDescTile < (int)blockDim.x ? kDescTile : (int)blockDim.x;
-    Rounds rs;
-    rs.init(M, (uint32_t)tile);
-    const uint64_t R = rs.R;
+    const uint64_t n_tiles = (M + tile - 1) / tile;
     const bool stager = (int)threadIdx.x < tile;
-    uint64_t g0 = 0, hi = 0;
-    if (R)
-        rs.next(&g0, &hi);
-    if (stager && g0 + threadIdx.x < hi)
-        desc[0][threadIdx.x] = make_desc<MODE>(a, g0 + threadIdx.x, C);
+    __shared__ uint64_t s_tile[2];
+    if (threadIdx.x == 0) {
+        const uint64_t c = take_tile(a.plan_rw);
+        uint64_t n = n_tiles;
+        if (c < n_tiles)
+            n = take_tile(a.plan_rw);
+        if (c >= n_tiles)
+            tiles_done(a.plan_rw, c, n_tiles);
+        else if (n >= n_tiles)
+            tiles_done(a.plan_rw, n, n_tiles);
+        s_tile[0] = c;
+        s_tile[1] = n;
+    }
+    __syncthreads();
+    uint64_t cur = s_tile[0], nxt = s_tile[1];   // the tile worked on, the tile staged meanwhile
+    if (cur < n_tiles && stager && cur * tile + threadIdx.x < M)
+        desc[0][threadIdx.x] = make_desc<MODE>(a, cur * tile + threadIdx.x, C);
     int buf = 0;
-    for (uint64_t r = 0; r < R; r++, buf ^= 1) {
-        __syncthreads();   // tables and this tile's descriptors are in LDS
-        uint64_t n0 = 0, n1 = 0;
-        if (r + 1 < R)
-            rs.next(&n0, &n1);
+    for (uint32_t it = 0; cur < n_tiles; it++, buf ^= 1) {
+        __syncthreads();   // tables, this tile's descriptors and the last take are in LDS
+        if (it > 0)
+            nxt = s_tile[(it + 1) & 1];   // taken during the previous iteration
+        uint64_t taken = n_tiles;
+        if (threadIdx.x == 0 && nxt < n_tiles)
+            taken = take_tile(a.plan_rw);   // its value is first needed at the end of the tile
+        const uint64_t g0 = cur * tile, hi = g0 + tile < M ? g0 + tile : M;
+        const uint64_t n0 = nxt * tile, n1 = nxt < n_tiles ? (n0 + tile < M ? n0 + tile : M) : n0;
         Desc nd;
         if (stager && n0 + threadIdx.x < n1)
             nd = make_desc<MODE>(a, n0 + threadIdx.x, C);   // loads in flight during the tile
@@ -824,47 +888,23 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
                     finish_chunk<MODE>(a, dc, raw, ((nz >> (q * kQuadLanes)) & 0xFFFFull) != 0);
             }
         } else if constexpr (FORM == kFormSmall) {
-            // one batch per chunk: the next chunk's loads go out before this
-            // chunk is hashed, combined and finished
-            uint4 cur[kLoadsInFlight], nxt[kLoadsInFlight];
-            Desc dn;
-            if (group < cnt) {
-                dn = desc[buf][group];
-                small_loads<MODE, NT>(dn, lane, r_win, nxt);
-            }
-            for (int t = group; t < cnt; t += groups) {
-                const Desc d = dn;
-#pragma unroll
-                for (int b = 0; b < kLoadsInFlight; b++)
-                    cur[b] = nxt[b];
-                if (t + groups < cnt) {
-                    dn = desc[buf][t + groups];
-                    small_loads<MODE, NT>(dn, lane, r_win, nxt);
-                }
-                if (MODE == kModeRestore && d.zero && d.len == C) {   // uniform over the wave
-                    restore_zero_chunk<NT>(a, d, lane);
-                    continue;
-                }
-                bool store = true;
-                if (MODE != kModeRestore) {
-                    // ZERO is known once the chunk's loads are in: a ZERO
-                    // chunk is not stored, and a full-length one not hashed
-                    uint32_t o = 0;
-#pragma unroll
-                    for (int b = 0; b < kLoadsInFlight; b++)
-                        o |= cur[b].x | cur[b].y | cur[b].z | cur[b].w;
-                    store = __ballot(o != 0) != 0;   // uniform over the wave
-                    if (!store && d.len == C) {
-                        if (lane == 0)
-                            record_zero_chunk(a, d);
-                        continue;
-                    }
-                }
-                uint32_t orv = 0;
-                const uint32_t raw = small_rest<MODE, NT>(T, d, lane, r_win, cur, &orv, store);
-                const bool nonzero = __ballot(orv != 0) != 0;
-                if (lane == 0)
-                    finish_chunk<MODE>(a, d, raw, nonzero);
+            // Two register buffers in rotation: while the wave hashes and
+            // stores one chunk, the next chunk's loads are in flight.  The
+            // loop is unrolled by two so that no buffer is ever copied into
+            // the other (a copy would wait for its loads).
+            uint4 v0[kLoadsInFlight], v1[kLoadsInFlight];
+            const Desc *td = desc[buf];
+            if (group < cnt)
+                small_loads<MODE, NT>(td[group], lane, r_win, v0);
+            for (int t = group; t < cnt; t += 2 * groups) {   // uniform over the wave
+                if (t + groups < cnt)
+                    small_loads<MODE, NT>(td[t + groups], lane, r_win, v1);
+                small_chunk<MODE, NT>(a, T, td[t], lane, r_win, C, v0);
+                if (t + groups >= cnt)
+                    break;
+                if (t + 2 * groups < cnt)
+                    small_loads<MODE, NT>(td[t + 2 * groups], lane, r_win, v0);
+                small_chunk<MODE, NT>(a, T, td[t + groups], lane, r_win, C, v1);
             }
         } else {
         for (int slot = 0; slot < cnt; slot += groups) {
@@ -905,8 +945,12 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
         }
         if (stager && n0 + threadIdx.x < n1)
             desc[buf ^ 1][threadIdx.x] = nd;   // the other tile was consumed before the last barrier
-        g0 = n0;
-        hi = n1;
+        if (threadIdx.x == 0 && nxt < n_tiles) {
+            s_tile[it & 1] = taken;   // read after the next barrier
+            if (taken >= n_tiles)
+                tiles_done(a.plan_rw, taken, n_tiles);
+        }
+        cur = nxt;
     }
 }
 
