@@ -490,7 +490,8 @@ def hbm_ceilings(torch, nbytes, reps=3):
     hints: the most this GPU moves for each kind of traffic.  read and write
     touch nbytes; the copies read nbytes / 2 and write nbytes / 2 (copy: both
     hints alike; copy_nt_loads / copy_nt_stores: only the loads / only the
-    stores non-temporal)."""
+    stores non-temporal).  The _dyn kinds take tiles of 256 KiB from a counter
+    instead of a fixed grid-stride split."""
     import ctypes
     from paper_2008_10596_amd import build as B
     if not os.path.exists(B.PROBE_LIB):
@@ -508,13 +509,15 @@ def hbm_ceilings(torch, nbytes, reps=3):
     stream = torch.cuda.current_stream()
     half = nbytes // 2 // 16 * 16
     table, best = [], {}
-    for kind, name in ((0, "read"), (1, "write"), (2, "copy"), (3, "copy_nt_loads"), (4, "copy_nt_stores")):
+    kinds = ((0, "read"), (1, "write"), (2, "copy"), (3, "copy_nt_loads"), (4, "copy_nt_stores"),
+             (5, "read_dyn"), (6, "write_dyn"), (7, "copy_dyn"))
+    for kind, name in kinds:
         for loads in (4, 8, 16):
             for per_cu in (1, 2):
-                for nt in ((0, 1) if kind < 3 else (1,)):
-                    if kind == 0:
+                for nt in ((1,) if kind in (3, 4) else (0, 1)):
+                    if kind in (0, 5):
                         args = (a.data_ptr(), sink.data_ptr(), nbytes)
-                    elif kind == 1:
+                    elif kind in (1, 6):
                         args = (None, b.data_ptr(), nbytes)
                     else:
                         args = (a.data_ptr(), a.data_ptr() + half, half)   # the copies move half each way
@@ -533,7 +536,7 @@ def hbm_ceilings(torch, nbytes, reps=3):
                         e1.synchronize()
                         ms.append(e0.elapsed_time(e1))
                     m = statistics.median(ms)
-                    moved = nbytes if kind < 2 else 2 * half
+                    moved = nbytes if kind in (0, 1, 5, 6) else 2 * half
                     row = {"kind": name, "loads_per_lane": loads, "wgs_per_cu": per_cu, "nontemporal": nt,
                            "ms": round(m, 4), "gbps": round(moved / (m * 1e-3) / 1e9, 1)}
                     table.append(row)
@@ -886,6 +889,8 @@ def main():
             out["incremental"] = bench_incremental(K, synth, torch, stream, args)
         if "batched" in sections:
             out["batched"] = bench_batched(K, synth, torch, stream, args)
+        if "serving" in sections:
+            out["serving"] = bench_serving(K, synth, torch, args)
         if "hook" in sections:
             out["hook"] = bench_hook(args)
         print(json.dumps(out), flush=True)

@@ -57,6 +57,7 @@ struct DevPlan {
     uint64_t sel_count;   // selection scan: total selected ids
     unsigned long long bad_count;  // restore: chunks that failed verification
     unsigned long long tile_next;  // chunk launches: the next tile to take (zero between launches)
+    unsigned long long gather_next;  // gather launches: the same for the gather's tiles
 };
 
 enum ChunkMode { kModePack = 0, kModeHash = 1, kModeRestore = 2 };
@@ -130,6 +131,7 @@ struct RowArgs {
     uint64_t n_items;
     const StepRow *rows;
     const uint32_t *map;   // item -> row
+    unsigned long long *tile_ctr;   // the step plan's tile_next (zero at launch)
 };
 
 enum SelMode {
@@ -177,8 +179,9 @@ struct GatherArgs {
     // by segments: chunks [g_begin, g_end) when g_end != 0 (else all chunks
     // of the plan); out holds the serialized bytes from offset soff_base on
     uint64_t g_begin, g_end, soff_base;
-    uint32_t tile;            // chunks per wave step (1 .. 64, a power of two); set by launch_gather
+    uint32_t tile;            // chunks per tile (1 .. 64, a power of two); set by launch_gather
     uint32_t pad;
+    unsigned long long *tile_ctr;   // the plan's gather_next; set by launch_gather
     // Several outputs straight into host memory (the drain inside the batched
     // graph), when out_addr is not null: chunk g of allocation row k belongs
     // to output o = row_out[k], whose serialized bytes start at host address

@@ -219,7 +219,7 @@ __global__ void k_chunk_map(const DevPlan *plan, const uint64_t *__restrict__ cb
 
 // -------------------------------------------- K3/K4/K8: the chunk kernels
 //
-// Persistent workgroups take tiles of kTile chunk items; each tile's
+// Persistent workgroups take tiles of kTile chunk items from a counter; each tile's
 // descriptors are staged in LDS once, then groups of waves_per_chunk waves
 // take one item each.
 //   kModePack:    read the allocation, write the dense image, CRC + flags.
@@ -586,38 +586,6 @@ __device__ __forceinline__ void small_chunk(const ChunkArgs &a, const Tabs &T, c
         finish_chunk<MODE>(a, d, raw, nonzero);
 }
 
-// Balanced interleaved rounds: the M items go in R rounds of at most
-// gridDim.x * tile; round r covers [floor(M r / R), floor(M (r+1) / R)) and is
-// split evenly over the workgroups.  Every quotient is formed once: with
-// q = M / R and rem = M % R, a round's span is q or q + 1 (a carry from the
-// running remainder), and this workgroup's offsets within a span of either
-// size are fixed.  next() yields the workgroup's range in the next round.
-struct Rounds {
-    uint64_t R, q, rem, lo_a, hi_a, lo_b, hi_b, base, acc;
-
-    __device__ void init(uint64_t M, uint32_t tile)
-    {
-        const uint64_t per_round = (uint64_t)gridDim.x * tile;
-        R = (M + per_round - 1) / per_round;
-        q = R ? M / R : 0;
-        rem = R ? M % R : 0;
-        lo_a = q * blockIdx.x / gridDim.x;
-        hi_a = q * (blockIdx.x + 1) / gridDim.x;
-        lo_b = (q + 1) * blockIdx.x / gridDim.x;
-        hi_b = (q + 1) * (blockIdx.x + 1) / gridDim.x;
-        base = 0;
-        acc = 0;
-    }
-    __device__ void next(uint64_t *lo, uint64_t *hi)
-    {
-        const bool carry = acc + rem >= R;   // acc, rem < R: no overflow
-        *lo = base + (carry ? lo_b : lo_a);
-        *hi = base + (carry ? hi_b : hi_a);
-        base += q + (carry ? 1 : 0);
-        acc = carry ? acc + rem - R : acc + rem;
-    }
-};
-
 // The descriptor of item i (chunk g = i, or ids[i] in a delta restore).
 template <int MODE>
 __device__ __forceinline__ Desc make_desc(const ChunkArgs &a, uint64_t i, uint32_t C)
@@ -755,20 +723,21 @@ __device__ __forceinline__ uint32_t quad_combine(const Tabs &T, uint32_t acc, in
     return acc;
 }
 
-// The tile counter of a chunk launch: every workgroup takes tiles until its
-// first miss (a value of at least n_tiles), so a launch makes n_tiles + grid
-// takes.  The workgroup whose miss is the last take of the launch sets the
-// counter back to zero for the next launch on the same plan (launches on one
-// plan are stream-ordered; the host writes every plan with a zero counter).
-__device__ __forceinline__ uint64_t take_tile(DevPlan *p)
+// Tile counters: every taker (a workgroup of a chunk launch, a wave of a
+// gather) takes tiles until its first miss (a value of at least n_tiles), so
+// a launch makes n_tiles + takers takes.  The taker whose miss is the last
+// take of the launch sets the counter back to zero for the next launch on the
+// same plan (such launches are stream-ordered, and the host writes every plan
+// with zero counters).
+__device__ __forceinline__ uint64_t take_tile(unsigned long long *ctr)
 {
-    return atomicAdd(&p->tile_next, 1ull);
+    return atomicAdd(ctr, 1ull);
 }
 
-__device__ __forceinline__ void tiles_done(DevPlan *p, uint64_t miss, uint64_t n_tiles)
+__device__ __forceinline__ void tiles_done(unsigned long long *ctr, uint64_t miss, uint64_t n_tiles, uint64_t takers)
 {
-    if (miss == n_tiles + gridDim.x - 1)
-        atomicExch(&p->tile_next, 0ull);
+    if (miss == n_tiles + takers - 1)
+        atomicExch(ctr, 0ull);
 }
 
 // FORM: kFormWave (one or more waves per chunk), kFormSmall (every chunk is
@@ -815,14 +784,14 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
     const bool stager = (int)threadIdx.x < tile;
     __shared__ uint64_t s_tile[2];
     if (threadIdx.x == 0) {
-        const uint64_t c = take_tile(a.plan_rw);
+        const uint64_t c = take_tile(&a.plan_rw->tile_next);
         uint64_t n = n_tiles;
         if (c < n_tiles)
-            n = take_tile(a.plan_rw);
+            n = take_tile(&a.plan_rw->tile_next);
         if (c >= n_tiles)
-            tiles_done(a.plan_rw, c, n_tiles);
+            tiles_done(&a.plan_rw->tile_next, c, n_tiles, gridDim.x);
         else if (n >= n_tiles)
-            tiles_done(a.plan_rw, n, n_tiles);
+            tiles_done(&a.plan_rw->tile_next, n, n_tiles, gridDim.x);
         s_tile[0] = c;
         s_tile[1] = n;
     }
@@ -837,7 +806,7 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
             nxt = s_tile[(it + 1) & 1];   // taken during the previous iteration
         uint64_t taken = n_tiles;
         if (threadIdx.x == 0 && nxt < n_tiles)
-            taken = take_tile(a.plan_rw);   // its value is first needed at the end of the tile
+            taken = take_tile(&a.plan_rw->tile_next);   // its value is first needed at the end of the tile
         const uint64_t g0 = cur * tile, hi = g0 + tile < M ? g0 + tile : M;
         const uint64_t n0 = nxt * tile, n1 = nxt < n_tiles ? (n0 + tile < M ? n0 + tile : M) : n0;
         Desc nd;
@@ -948,7 +917,7 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
         if (threadIdx.x == 0 && nxt < n_tiles) {
             s_tile[it & 1] = taken;   // read after the next barrier
             if (taken >= n_tiles)
-                tiles_done(a.plan_rw, taken, n_tiles);
+                tiles_done(&a.plan_rw->tile_next, taken, n_tiles, gridDim.x);
         }
         cur = nxt;
     }
@@ -1010,22 +979,37 @@ __global__ __launch_bounds__(1024) void k_rows(RowArgs a)
     const uint32_t r_win = (C + kRoundBytes - 1) / kRoundBytes;
     const uint64_t M = a.n_items;
 
-    // Balanced interleaved rounds and double-buffered descriptors, as in k_chunks.
-    Rounds rs;
-    rs.init(M, kTile);
-    const uint64_t R = rs.R;
+    // Tiles taken from the step's counter, one ahead, and double-buffered
+    // descriptors, as in k_chunks.
+    const uint64_t n_tiles = (M + kTile - 1) / kTile;
     const bool stager = threadIdx.x < kTile;
-    uint64_t g0 = 0, hi = 0;
-    if (R)
-        rs.next(&g0, &hi);
-    if (stager && g0 + threadIdx.x < hi)
-        desc[0][threadIdx.x] = make_row_desc(a, g0 + threadIdx.x, C);
+    __shared__ uint64_t s_tile[2];
+    if (threadIdx.x == 0) {
+        const uint64_t c = take_tile(a.tile_ctr);
+        uint64_t n = n_tiles;
+        if (c < n_tiles)
+            n = take_tile(a.tile_ctr);
+        if (c >= n_tiles)
+            tiles_done(a.tile_ctr, c, n_tiles, gridDim.x);
+        else if (n >= n_tiles)
+            tiles_done(a.tile_ctr, n, n_tiles, gridDim.x);
+        s_tile[0] = c;
+        s_tile[1] = n;
+    }
+    __syncthreads();
+    uint64_t cur = s_tile[0], nxt = s_tile[1];
+    if (cur < n_tiles && stager && cur * kTile + threadIdx.x < M)
+        desc[0][threadIdx.x] = make_row_desc(a, cur * kTile + threadIdx.x, C);
     int buf = 0;
-    for (uint64_t r = 0; r < R; r++, buf ^= 1) {
+    for (uint32_t it = 0; cur < n_tiles; it++, buf ^= 1) {
         __syncthreads();
-        uint64_t n0 = 0, n1 = 0;
-        if (r + 1 < R)
-            rs.next(&n0, &n1);
+        if (it > 0)
+            nxt = s_tile[(it + 1) & 1];
+        uint64_t taken = n_tiles;
+        if (threadIdx.x == 0 && nxt < n_tiles)
+            taken = take_tile(a.tile_ctr);
+        const uint64_t g0 = cur * kTile, hi = g0 + kTile < M ? g0 + kTile : M;
+        const uint64_t n0 = nxt * kTile, n1 = nxt < n_tiles ? (n0 + kTile < M ? n0 + kTile : M) : n0;
         RowDesc nd;
         if (stager && n0 + threadIdx.x < n1)
             nd = make_row_desc(a, n0 + threadIdx.x, C);
@@ -1053,8 +1037,12 @@ __global__ __launch_bounds__(1024) void k_rows(RowArgs a)
         }
         if (stager && n0 + threadIdx.x < n1)
             desc[buf ^ 1][threadIdx.x] = nd;
-        g0 = n0;
-        hi = n1;
+        if (threadIdx.x == 0 && nxt < n_tiles) {
+            s_tile[it & 1] = taken;
+            if (taken >= n_tiles)
+                tiles_done(a.tile_ctr, taken, n_tiles, gridDim.x);
+        }
+        cur = nxt;
     }
 }
 
@@ -1218,10 +1206,10 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_down(SelArgs a)
 // Copies each selected chunk (roundup16(len) bytes) to out + soff[g], from the
 // dense image or straight from the allocation (zero pad written, never read);
 // or, for several outputs in host memory, into each output's own buffer.
-// Each wave takes `tile` consecutive chunks (up to 64, fewer when a launch
-// covers few chunks, so that every wave of the grid has work): lane l fetches
-// the descriptor of chunk t0 + l, so the descriptor loads are in flight
-// together.  The wave then copies its selected chunks one after the other
+// Each wave takes tiles of `tile` consecutive chunks (up to 64, fewer when a
+// launch covers few chunks, so that every wave of the grid has work) from a
+// counter in the plan, in order: lane l fetches the descriptor of chunk
+// t0 + l, so the descriptor loads are in flight together.  The wave then copies its selected chunks one after the other
 // (their addresses read from the owning lane), each lane issuing up to
 // kGatherLoads 16-byte loads before its first store.
 
@@ -1259,15 +1247,36 @@ __device__ __forceinline__ void gather_copy(const uint8_t *s, uint8_t *d, uint32
     }
 }
 
+// A wave's take from the gather's tile counter (lane 0 takes, every lane
+// gets the value).
+__device__ __forceinline__ uint64_t gather_take(unsigned long long *ctr, uint64_t n_tiles, uint64_t waves, int lane)
+{
+    uint64_t t = 0;
+    if (lane == 0) {
+        t = take_tile(ctr);
+        if (t >= n_tiles)
+            tiles_done(ctr, t, n_tiles, waves);
+    }
+    return readlane_u64(t, 0);
+}
+
 template <bool NT_ST>
 __global__ __launch_bounds__(1024) void k_gather(GatherArgs a)
 {
     const uint64_t N = a.g_end ? a.g_end : a.plan->n_chunks;
     const int lane = threadIdx.x & 63;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint32_t tile = a.tile;
-    for (uint64_t t0 = a.g_begin + wave * tile; t0 < N; t0 += waves * tile) {
+    const uint64_t n_tiles = N > a.g_begin ? (N - a.g_begin + tile - 1) / tile : 0;
+    // Wave w's first tile is tile w; the rest are taken in order from the
+    // plan's counter, so that a wave whose tiles hold few selected chunks takes
+    // more of them.  A launch with about one tile per wave (a segment of the
+    // drain) thus makes few takes, and the waves do not all take at its start.
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t n_dyn = n_tiles > waves ? n_tiles - waves : 0;   // tiles taken from the counter
+    for (uint64_t cur = wave; cur < n_tiles;
+         cur = n_dyn ? waves + gather_take(a.tile_ctr, n_dyn, waves, lane) : n_tiles) {
+        const uint64_t t0 = a.g_begin + cur * tile;
         const uint64_t g = t0 + lane;
         bool take = false;
         uint64_t src = 0, dst = 0;
@@ -1414,6 +1423,7 @@ hipError_t launch_select(hipStream_t s, const SelArgs &a, uint64_t max_items)
 hipError_t launch_gather(hipStream_t s, const GatherArgs &a_in, int grid)
 {
     GatherArgs a = a_in;
+    a.tile_ctr = (unsigned long long *)((uintptr_t)a.plan + offsetof(DevPlan, gather_next));
     // a launch over a chunk range gives every wave of the grid at least one
     // tile; without a range (all chunks of the plan) the tile is 64
     a.tile = 64;

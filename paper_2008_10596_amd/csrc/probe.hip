@@ -3,7 +3,7 @@
 // drain/refill kernels of libckpt are compared with.  None of them is on the
 // checkpoint path.
 //
-// Each kernel sweeps one buffer with a grid of persistent workgroups: in
+// Each static kernel sweeps one buffer with a grid of persistent workgroups: in
 // iteration i, wave w of W handles the U * 1 KiB at ((i * W + w) * U) KiB, lane
 // l the 16-byte pieces l, l + 64, ..., so the whole grid moves through memory
 // one window of W * U KiB at a time.  U loads are issued before any of them is
@@ -119,6 +119,64 @@ __global__ __launch_bounds__(1024) void k_copy2(const u32x4 *__restrict__ src, u
     }
 }
 
+// The same three kernels as the chunk kernels of libckpt schedule their work:
+// each workgroup takes tiles of 256 KiB in order from a counter (thread 0
+// takes, the workgroup reads the value from LDS), and its waves take the
+// tile's blocks of 64 * U pieces in turn (KIND 0 read, 1 write, 2 copy; both
+// hints alike).  Every workgroup takes until its first miss (a value of at
+// least n_tiles); the workgroup whose miss is the launch's last take sets the
+// counter back to zero for the next launch.
+__device__ unsigned long long g_tile;
+constexpr uint64_t kTile16 = 16384;   // 16-byte pieces per tile
+
+template <int KIND, int U, bool NT>
+__global__ __launch_bounds__(1024) void k_dyn(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, uint64_t n16,
+                                              uint32_t *__restrict__ sink)
+{
+    __shared__ uint64_t s_t;
+    const uint64_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint64_t n_tiles = (n16 + kTile16 - 1) / kTile16;
+    u32x4 acc = {0u, 0u, 0u, 0u};
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint64_t t = atomicAdd(&g_tile, 1ull);
+            if (t == n_tiles + gridDim.x - 1)
+                atomicExch(&g_tile, 0ull);
+            s_t = t;
+        }
+        __syncthreads();
+        const uint64_t t = s_t;
+        __syncthreads();   // every wave has read s_t before it is written again
+        if (t >= n_tiles)
+            break;
+        const uint64_t end = (t + 1) * kTile16 < n16 ? (t + 1) * kTile16 : n16;
+        for (uint64_t base = t * kTile16 + wave * 64 * U; base < end; base += nw * 64 * U) {
+            u32x4 v[U];
+            if (KIND != 1) {
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const uint64_t p = base + u * 64 + lane;
+                    v[u] = p < end ? ld<NT>(src + p) : zero;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const uint64_t p = base + u * 64 + lane;
+                if (KIND == 0)
+                    acc |= v[u];
+                else if (p < end)
+                    st<NT>(dst + p, KIND == 1 ? zero : v[u]);
+            }
+        }
+    }
+    if (KIND == 0) {
+        const uint32_t r = acc.x | acc.y | acc.z | acc.w;
+        if (r == 0x9E3779B9u)   // practically never: keeps the loads without a store per thread
+            sink[0] = r;
+    }
+}
+
 template <int U, bool NT>
 void launch(int kind, const void *src, void *dst, uint64_t n16, int grid, int block, hipStream_t s)
 {
@@ -131,24 +189,33 @@ void launch(int kind, const void *src, void *dst, uint64_t n16, int grid, int bl
     else if (kind == 3)   // non-temporal loads only when NT, regular stores
         hipLaunchKernelGGL((k_copy2<U, NT, false>), dim3(grid), dim3(block), 0, s, (const u32x4 *)src, (u32x4 *)dst,
                            n16);
-    else                  // regular loads, non-temporal stores only when NT
+    else if (kind == 4)   // regular loads, non-temporal stores only when NT
         hipLaunchKernelGGL((k_copy2<U, false, NT>), dim3(grid), dim3(block), 0, s, (const u32x4 *)src, (u32x4 *)dst,
                            n16);
+    else if (kind == 5)
+        hipLaunchKernelGGL((k_dyn<0, U, NT>), dim3(grid), dim3(block), 0, s, (const u32x4 *)src, nullptr, n16,
+                           (uint32_t *)dst);
+    else if (kind == 6)
+        hipLaunchKernelGGL((k_dyn<1, U, NT>), dim3(grid), dim3(block), 0, s, nullptr, (u32x4 *)dst, n16, nullptr);
+    else
+        hipLaunchKernelGGL((k_dyn<2, U, NT>), dim3(grid), dim3(block), 0, s, (const u32x4 *)src, (u32x4 *)dst, n16,
+                           nullptr);
 }
 
 }  // namespace
 
 // kind: 0 read (dst: a 4-byte sink), 1 write, 2 copy, 3 copy with only the
 // loads non-temporal (when nt), 4 copy with only the stores non-temporal
-// (when nt).  bytes: a multiple of
+// (when nt); 5, 6, 7: read, write and copy taking tiles from a counter.
+// Launches of kinds 5-7 must not overlap (they share one counter).  bytes: a multiple of
 // 16.  loads: 1, 2, 4, 8 or 16 pieces per lane per iteration; nt: 0/1.
 // Returns 0, or -1 for bad arguments, or the hipError_t of the launch.
 extern "C" int probe_launch(int kind, const void *src, void *dst, uint64_t bytes, int loads, int nt, int grid,
                             int block, void *stream)
 {
-    if (kind < 0 || kind > 4 || bytes % 16 || grid <= 0 || (block != 256 && block != 512 && block != 1024))
+    if (kind < 0 || kind > 7 || bytes % 16 || grid <= 0 || (block != 256 && block != 512 && block != 1024))
         return -1;
-    if ((kind != 1 && !src) || !dst)
+    if ((kind != 1 && kind != 6 && !src) || !dst)
         return -1;
     const uint64_t n16 = bytes / 16;
     hipStream_t s = (hipStream_t)stream;

@@ -669,6 +669,7 @@ int run_step(ckpt_server *sv, const std::vector<Req *> &reqs, std::vector<uint64
     a.n_items = items;
     a.rows = (const StepRow *)(d + sizeof(DevPlan));
     a.map = (const uint32_t *)sv->d_map.p;
+    a.tile_ctr = &((DevPlan *)d)->tile_next;
     HIP_TRY(launch_rows(s, a, sv->cu_count, sv->cfg.block_threads));
     HIP_TRY(hipStreamSynchronize(s));
     return CKPT_OK;
