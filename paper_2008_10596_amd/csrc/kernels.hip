@@ -1206,12 +1206,13 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_down(SelArgs a)
 // Copies each selected chunk (roundup16(len) bytes) to out + soff[g], from the
 // dense image or straight from the allocation (zero pad written, never read);
 // or, for several outputs in host memory, into each output's own buffer.
-// Each wave takes tiles of `tile` consecutive chunks (up to 64, fewer when a
-// launch covers few chunks, so that every wave of the grid has work) from a
-// counter in the plan, in order: lane l fetches the descriptor of chunk
-// t0 + l, so the descriptor loads are in flight together.  The wave then copies its selected chunks one after the other
-// (their addresses read from the owning lane), each lane issuing up to
-// kGatherLoads 16-byte loads before its first store.
+// A workgroup takes tiles of 16 * `tile` consecutive chunks (`tile` up to 64,
+// fewer when a launch covers few chunks, so that every wave of the grid has
+// work); wave w of the workgroup takes chunks w, w + 16, ... of the tile, and
+// its lane l fetches the descriptor of the l-th of them, so the descriptor
+// loads are in flight together.  The wave then copies its selected chunks one
+// after the other (their addresses read from the owning lane), each lane
+// issuing up to kGatherLoads 16-byte loads before its first store.
 
 constexpr int kGatherLoads = 8;
 
@@ -1247,37 +1248,39 @@ __device__ __forceinline__ void gather_copy(const uint8_t *s, uint8_t *d, uint32
     }
 }
 
-// A wave's take from the gather's tile counter (lane 0 takes, every lane
-// gets the value).
-__device__ __forceinline__ uint64_t gather_take(unsigned long long *ctr, uint64_t n_tiles, uint64_t waves, int lane)
-{
-    uint64_t t = 0;
-    if (lane == 0) {
-        t = take_tile(ctr);
-        if (t >= n_tiles)
-            tiles_done(ctr, t, n_tiles, waves);
-    }
-    return readlane_u64(t, 0);
-}
-
 template <bool NT_ST>
 __global__ __launch_bounds__(1024) void k_gather(GatherArgs a)
 {
+    __shared__ uint64_t s_t[2];
     const uint64_t N = a.g_end ? a.g_end : a.plan->n_chunks;
-    const int lane = threadIdx.x & 63;
-    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    const uint32_t tile = a.tile;
-    const uint64_t n_tiles = N > a.g_begin ? (N - a.g_begin + tile - 1) / tile : 0;
-    // Wave w's first tile is tile w; the rest are taken in order from the
-    // plan's counter, so that a wave whose tiles hold few selected chunks takes
-    // more of them.  A launch with about one tile per wave (a segment of the
-    // drain) thus makes few takes, and the waves do not all take at its start.
-    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const uint64_t n_dyn = n_tiles > waves ? n_tiles - waves : 0;   // tiles taken from the counter
-    for (uint64_t cur = wave; cur < n_tiles;
-         cur = n_dyn ? waves + gather_take(a.tile_ctr, n_dyn, waves, lane) : n_tiles) {
-        const uint64_t t0 = a.g_begin + cur * tile;
-        const uint64_t g = t0 + lane;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t tile = a.tile;                       // chunks per wave per tile
+    const uint64_t span = (uint64_t)tile * nw;          // chunks per tile
+    const uint64_t n_tiles = N > a.g_begin ? (N - a.g_begin + span - 1) / span : 0;
+    // Workgroup b's first tile is tile b; the rest are taken in order from the
+    // plan's counter by thread 0, so that a workgroup whose tiles hold few
+    // selected chunks takes more of them.  The waves of a workgroup share its
+    // tile chunk by chunk (wave w: chunks w, w + nw, ...), so that together
+    // they stream through one window of memory.
+    const uint64_t n_dyn = n_tiles > gridDim.x ? n_tiles - gridDim.x : 0;
+    for (uint32_t it = 0;; it++) {
+        if (threadIdx.x == 0) {
+            uint64_t t = n_tiles;
+            if (it == 0) {
+                t = blockIdx.x;
+            } else if (n_dyn) {
+                const uint64_t v = take_tile(a.tile_ctr);
+                if (v >= n_dyn)
+                    tiles_done(a.tile_ctr, v, n_dyn, gridDim.x);
+                t = gridDim.x + v;
+            }
+            s_t[it & 1] = t;   // the other slot may still be read
+        }
+        __syncthreads();
+        const uint64_t cur = s_t[it & 1];
+        if (cur >= n_tiles)
+            break;
+        const uint64_t g = a.g_begin + cur * span + (uint64_t)lane * nw + wave;
         bool take = false;
         uint64_t src = 0, dst = 0;
         uint32_t len = 0;
