@@ -779,7 +779,15 @@ __global__ __launch_bounds__(1024) void k_chunks(ChunkArgs a)
     // while the workgroup works on the current one), so the grid sweeps the
     // memory in order and a workgroup whose tiles are cheap (ZERO chunks,
     // read only) takes more of them.
-    const int tile = kDescTile < (int)blockDim.x ? kDescTile : (int)blockDim.x;
+    // A tile holds at most kDescTile chunks and, for large chunks, about
+    // 1 MiB (but at least one chunk per group of waves), so that a launch
+    // has many tiles per workgroup and its last tiles end close together.
+    int tile = kDescTile < (int)blockDim.x ? kDescTile : (int)blockDim.x;
+    if (FORM == kFormWave) {
+        const int by_bytes = (int)((1u << 20) / C);
+        const int want = by_bytes > groups ? by_bytes : groups;
+        tile = want < tile ? want : tile;
+    }
     const uint64_t n_tiles = (M + tile - 1) / tile;
     const bool stager = (int)threadIdx.x < tile;
     __shared__ uint64_t s_tile[2];
