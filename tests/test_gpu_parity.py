@@ -828,6 +828,45 @@ def test_autotuner_shapes_match_the_oracle(tmp_path):
     assert again["cached"] and again["best"] == res["best"]
 
 
+# ------------------------------------------------------------- work split
+
+@pytest.mark.parametrize("C", [4096, 65536])
+def test_consecutive_launches_on_one_plan(C):
+    """The chunk and gather kernels take their tiles from counters in the
+    context's plan, which each launch leaves at zero.  Launches of very
+    different sizes on one context (fewer tiles than workgroups, then many;
+    pack, hash-only and restore in 1 MiB segments) must each cover every
+    chunk exactly: any tile left untaken shows as a CRC, flag or byte
+    mismatch."""
+    MiB = 1 << 20
+    small = random_allocs([100], seed=51)
+    large = random_allocs([9 * MiB + 3, 5 * MiB, 4096 * 7 + 5, 12 * MiB], seed=52, zero=(1,))
+    large[3][2 * MiB:4 * MiB] = 0
+    ctx = K.Context(chunk_bytes=C, segment_mib=1)
+    for rep in range(2):
+        for live in (small, large, small + large, small):
+            for t in live:
+                ctx.register(t)
+            ref = O.checkpoint([host(t) for t in live], C)
+            img = ctx.checkpoint()
+            check_full(img, ref, live, C)
+            live[-1][-1] ^= 0x11                     # one dirty chunk for the hash-only pass
+            dref = O.delta([host(t) for t in live], C, ref["crc"])
+            delta = ctx.checkpoint(mode=K.CKPT_INCREMENTAL, base=img)
+            assert np.array_equal(delta.crc, dref["crc"]), rep
+            assert np.array_equal(delta.flags, dref["flags"]), rep
+            assert np.array_equal(delta.dirty_ids, dref["dirty_ids"]) and dref["dirty_ids"].size == 1, rep
+            dsts = [torch.full_like(t, 0x3C) for t in live]
+            rc, rpt = ctx.restore(img, dsts, delta=delta)
+            assert rc == K.CKPT_OK and rpt["n_bad"] == 0, (rep, rpt)
+            check_restored(dsts, live)
+            delta.close()
+            img.close()
+            for t in live:
+                ctx.unregister(t)
+    ctx.close()
+
+
 # ------------------------------------------------------------- segments
 
 @pytest.mark.parametrize("C", [4096, 65536])
