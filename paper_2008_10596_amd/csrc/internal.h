@@ -195,6 +195,12 @@ struct GatherArgs {
 // Launch wrappers (kernels.hip).  All return the hipError_t of the launch.
 hipError_t launch_layout_scan(hipStream_t s, DevPlan *plan, const uint64_t *size, uint32_t C,
                               uint64_t *off, uint64_t *cb);
+// The same scan over a table in pinned host memory (`up`: a plan header,
+// then n addresses, then n sizes, n from the header), which it also copies
+// to plan, addr and size.  The host must not rewrite `up` until the stream
+// has passed the launch.
+hipError_t launch_upload_scan(hipStream_t s, const void *up, DevPlan *plan, uint64_t *addr, uint64_t *size,
+                              uint32_t C, uint64_t *off, uint64_t *cb);
 hipError_t launch_chunk_map(hipStream_t s, const DevPlan *plan, const uint64_t *cb, uint32_t *map,
                             int grid);
 hipError_t launch_chunks(hipStream_t s, int mode, const ChunkArgs &a, int grid, int block);

@@ -156,17 +156,37 @@ __device__ __forceinline__ uint32_t finish_crc(uint32_t raw, uint32_t n)
 // sum of ceil(size / C); off[n] and cb[n] get the totals, copied to the plan.
 // One workgroup of 1024 threads walks the table in tiles of 1024.
 
-__global__ __launch_bounds__(1024) void k_layout_scan(DevPlan *plan, const uint64_t *__restrict__ size,
+// With `up` (the table in pinned host memory: a plan header, then n
+// addresses, then n sizes), the kernel also copies it to the device: the
+// header to `plan`, the addresses and sizes to `addr_out` and `size`, with no
+// separate copies before it.  Without `up`, it reads `plan` and `size`.
+template <bool FROM_HOST>
+__global__ __launch_bounds__(1024) void k_layout_scan(DevPlan *plan, uint64_t *__restrict__ size,
                                                       uint32_t C, uint64_t *__restrict__ off,
-                                                      uint64_t *__restrict__ cb)
+                                                      uint64_t *__restrict__ cb, const uint8_t *up,
+                                                      uint64_t *__restrict__ addr_out)
 {
     __shared__ uint64_t s_off[16], s_cb[16];
-    const uint64_t n = plan->n_allocs;
+    const DevPlan *hp = (const DevPlan *)up;
+    const uint64_t n = FROM_HOST ? hp->n_allocs : plan->n_allocs;
+    const uint64_t *h_addr = FROM_HOST ? (const uint64_t *)(up + sizeof(DevPlan)) : nullptr;
+    const uint64_t *h_size = FROM_HOST ? h_addr + n : nullptr;
+    if (FROM_HOST && threadIdx.x == 0)
+        *plan = *hp;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint64_t carry_off = 0, carry_cb = 0;
     for (uint64_t base = 0; base < n; base += 1024) {
         const uint64_t k = base + threadIdx.x;
-        const uint64_t sz = k < n ? size[k] : 0;
+        uint64_t sz = 0;
+        if (k < n) {
+            if (FROM_HOST) {
+                sz = h_size[k];
+                size[k] = sz;
+                addr_out[k] = h_addr[k];
+            } else {
+                sz = size[k];
+            }
+        }
         const uint64_t e = round_up16(sz), c = (sz + C - 1) / C;
         const uint64_t ie = wave_incl_scan(e, lane), ic = wave_incl_scan(c, lane);
         if (lane == 63) {
@@ -1358,7 +1378,16 @@ __global__ void k_pick_u64(const uint64_t *src, const uint64_t *idx, uint64_t *o
 hipError_t launch_layout_scan(hipStream_t s, DevPlan *plan, const uint64_t *size, uint32_t C, uint64_t *off,
                               uint64_t *cb)
 {
-    hipLaunchKernelGGL(k_layout_scan, dim3(1), dim3(1024), 0, s, plan, size, C, off, cb);
+    hipLaunchKernelGGL(k_layout_scan<false>, dim3(1), dim3(1024), 0, s, plan, const_cast<uint64_t *>(size), C, off,
+                       cb, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_upload_scan(hipStream_t s, const void *up, DevPlan *plan, uint64_t *addr, uint64_t *size,
+                              uint32_t C, uint64_t *off, uint64_t *cb)
+{
+    hipLaunchKernelGGL(k_layout_scan<true>, dim3(1), dim3(1024), 0, s, plan, size, C, off, cb, (const uint8_t *)up,
+                       addr);
     return hipGetLastError();
 }
 

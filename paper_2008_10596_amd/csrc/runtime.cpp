@@ -628,17 +628,17 @@ int ckpt::upload_table(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &row
         size[k] = rows[k].size;
     }
     (void)dst_side;
-    HIP_TRY(hipMemcpyAsync(ctx->d_plan.p, plan, sizeof(DevPlan), hipMemcpyHostToDevice, s));
-    if (n) {
-        HIP_TRY(hipMemcpyAsync(ctx->d_addr.p, addr, 8 * n, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(ctx->d_size.p, size, 8 * n, hipMemcpyHostToDevice, s));
-    }
-    HIP_TRY(launch_layout_scan(s, (DevPlan *)ctx->d_plan.p, (const uint64_t *)ctx->d_size.p, ctx->cfg.chunk_bytes,
-                               (uint64_t *)ctx->d_off.p, (uint64_t *)ctx->d_cb.p));
+    // The scan reads the table from the pinned buffer and copies it to the
+    // device itself (no copies on the runtime's copy path, which the previous
+    // call's copies to the host may still be using).
+    HIP_TRY(launch_upload_scan(s, ctx->h_up.p, (DevPlan *)ctx->d_plan.p, (uint64_t *)ctx->d_addr.p,
+                               (uint64_t *)ctx->d_size.p, ctx->cfg.chunk_bytes, (uint64_t *)ctx->d_off.p,
+                               (uint64_t *)ctx->d_cb.p));
     if (N_host)
         HIP_TRY(launch_chunk_map(s, (const DevPlan *)ctx->d_plan.p, (const uint64_t *)ctx->d_cb.p,
                                  (uint32_t *)ctx->d_map.p, ctx->grid_small));
-    // the host waits on this copy before it next rewrites h_up
+    // every call synchronizes before it returns, so the kernel has read h_up
+    // before the host next rewrites it
     return CKPT_OK;
 }
 
