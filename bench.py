@@ -775,6 +775,22 @@ def bench_serving(K, synth, torch, args):
             if old is not None:
                 retire(old)
 
+    def claim_all(tickets):
+        # claim results in the order they finish, not in arrival order:
+        # finished checkpoints' images hold pinned memory that a checkpoint
+        # held back for host memory may be waiting for
+        while tickets:
+            still = []
+            for entry in tickets:
+                r = srv.poll(entry[0])
+                if r is None:
+                    still.append(entry)
+                else:
+                    done(entry, r)
+            if len(still) == len(tickets):
+                time.sleep(0.0005)
+            tickets = still
+
     def run_rate(lam, n_total, warm):
         arr = np.cumsum(rng.exponential(1.0 / lam, n_total))
         ops = rng.random(n_total) < 0.7
@@ -784,8 +800,7 @@ def bench_serving(K, synth, torch, args):
         for i in range(n_total):
             if i == warm:
                 # measure from here: the warm-up requests finish first
-                for entry in tickets:
-                    done(entry, srv.wait(entry[0]))
+                claim_all(tickets)
                 tickets = []
                 srv.reset_stats()
                 t0 = time.perf_counter() - arr[i]
@@ -818,8 +833,7 @@ def bench_serving(K, synth, torch, args):
                 else:
                     done(entry, r)
             tickets = still
-        for entry in tickets:
-            done(entry, srv.wait(entry[0]))
+        claim_all(tickets)
         return srv.stats()
 
     knee = p50_first = None

@@ -610,6 +610,10 @@ int ckpt_checkpoint_batch(ckpt_ctx *const *ctxs, size_t n, void *stream, ckpt_im
  * caller release older images); requests behind a request whose device
  * staging does not fit wait.  So a backlog queues instead of failing, and
  * images the caller keeps hold back later checkpoints until it frees them.
+ * Finished checkpoints' images count too before the caller claims them: a
+ * caller that waits for one held-back checkpoint while later results stay
+ * unclaimed should claim results as they finish (ckpt_server_poll).  A
+ * checkpoint held back for host memory for 30 s fails with CKPT_E_NOMEM.
  * The host may pin less than host_budget: a request whose preparation or
  * finish (a finished checkpoint's image included) cannot get memory keeps its
  * staging and runs that part again every few milliseconds until memory is

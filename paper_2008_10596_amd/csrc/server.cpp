@@ -124,6 +124,8 @@ struct ckpt_server {
     std::deque<Task> aux_tasks;
     AdmitState adm;                               // slots and host reservations
     bool host_blocked = false;                    // a checkpoint waits for host memory
+    const Req *held = nullptr;                    // that checkpoint, held back since t_held
+    Clock::time_point t_held{};
 
     // step buffers (owned by the step thread)
     PinnedBuf h_step;
@@ -395,8 +397,28 @@ AdmitInfo admit_info(const Req *r)
     return a;
 }
 
+// A queued request that was never admitted ends with `status` (caller holds
+// sv->mu): it has no staging block and no device work.
+void fail_queued(ckpt_server *sv, Req *r, int status)
+{
+    sv->queue.erase(std::remove(sv->queue.begin(), sv->queue.end(), r), sv->queue.end());
+    r->t_done = Clock::now();
+    r->t_admit = r->t_done;
+    r->state = kDone;
+    r->result.status = status;
+    r->result.latency_ms = ms_between(r->t_submit, r->t_done);
+    r->result.queue_ms = r->result.latency_ms;
+    sv->failed++;
+    sv->t_last = r->t_done;
+    sv->cv_done.notify_all();
+}
+
 // Admit queued requests (admission.h): in arrival order while a slot and
 // staging are free; restores may pass a checkpoint that waits for host memory.
+// A checkpoint held back for host memory longer than kHostWaitLimitMs fails
+// with CKPT_E_NOMEM: the memory it waits for may be held by finished
+// checkpoints' images that the caller has not claimed while it waits for this
+// one.
 void admit_locked(ckpt_server *sv)
 {
     for (;;) {
@@ -404,13 +426,29 @@ void admit_locked(ckpt_server *sv)
         bool blocked = false;
         const long i = next_admissible(sv->queue, sv->adm, sv->arena.map(), host_live, admit_info, &blocked);
         sv->host_blocked = blocked;
+        Req *held = nullptr;   // when blocked, the first queued checkpoint is the one held back
         if (blocked)
             for (Req *q : sv->queue)
-                if (q->op == CKPT_REQ_CHECKPOINT && !q->waited_host) {
-                    q->waited_host = true;   // the first queued checkpoint is the one held back
-                    sv->host_waits++;
+                if (q->op == CKPT_REQ_CHECKPOINT) {
+                    held = q;
                     break;
                 }
+        const auto now = Clock::now();
+        if (held != sv->held) {   // a new hold (or none): its clock starts now
+            sv->held = held;
+            sv->t_held = now;
+            if (held && !held->waited_host) {
+                held->waited_host = true;
+                sv->host_waits++;
+            }
+        } else if (held && ms_between(sv->t_held, now) >= kHostWaitLimitMs) {
+            set_error(CKPT_E_NOMEM, "checkpoint held back %.0f s for host memory: %llu pinned bytes held, budget %llu",
+                      kHostWaitLimitMs / 1000, (unsigned long long)host_live, (unsigned long long)sv->adm.host_budget);
+            note_failure(sv);
+            fail_queued(sv, held, CKPT_E_NOMEM);
+            sv->held = nullptr;
+            continue;   // the queue changed: look again
+        }
         if (i < 0)
             return;
         Req *r = sv->queue[(size_t)i];
@@ -418,6 +456,8 @@ void admit_locked(ckpt_server *sv)
         if (off == UINT64_MAX)
             return;   // cannot happen: next_admissible checked that it fits
         sv->queue.erase(sv->queue.begin() + i);
+        if (r == sv->held)
+            sv->held = nullptr;
         r->block_off = off;
         plan_block(r, sv->arena.base() + off);
         r->state = kPrep;
