@@ -307,8 +307,11 @@ def bench_churn(K, synth, torch, stream, args, tensors, sizes, C=65536, reps=3):
 def bench_batched(K, synth, torch, stream, args, reps=3):
     """Batched workload: 512 contexts of 1-64 allocations (log-uniform 1 MiB -
     256 MiB per context), random bytes with 20% of the 256 KiB cells zero.
-    Plain forms (one checkpoint call per allocation, or per context) against
-    one batched call that replays a captured graph; then the autotuner."""
+    First the autotuner (chunk size, waves per chunk, workgroup size, load/store
+    hint); then, in its best shape at C = 4 KiB (the section's chunk size),
+    one batched call that replays a captured graph against the plain forms
+    (one checkpoint call per allocation, or per context) in the same shape.
+    Launch-shape flags on the command line override the tuned shape."""
     from paper_2008_10596_amd import autotune
     spec = synth.batched()
     C = 4096
@@ -338,6 +341,23 @@ def bench_batched(K, synth, torch, stream, args, reps=3):
         members.append(c)
     out = {"workload": "batched: %d contexts, %d allocations, %.2f GiB, 20%% zero 256 KiB cells, C=%d"
                        % (len(sets), len(tensors), S / 2**30, C), "algorithmic_bytes": alg}
+    shape = {}
+    if not args.batched_only_graph:
+        # autotuner sweep on the same allocations
+        alloc_sets = [[(t.data_ptr(), t.numel()) for t in allocs] for allocs in sets]
+        tuned = autotune.tune(alloc_sets, chunks=(4096, 16384, 65536, 262144), waves=(1, 2, 4),
+                              blocks=(256, 1024), reps=2, stream=stream)
+        at_c = min((t for t in tuned["trials"] if t["chunk_bytes"] == C), key=lambda t: t["device_ms"])
+        out["autotune"] = {"best": tuned["best"], "best_at_c": at_c, "trials": len(tuned["trials"]),
+                           "worst_gbps": min(t["gbps"] for t in tuned["trials"]),
+                           "c4096_best_gbps": at_c["gbps"]}
+        log("autotune: %s" % out["autotune"])
+        shape = {"waves_per_chunk": at_c["waves_per_chunk"], "block_threads": at_c["block_threads"],
+                 "load_hint": at_c["load_hint"]}
+    for key, v in tune_kw(args).items():
+        if v:
+            shape[key] = v
+    out["shape"] = dict(shape)
 
     def timed(fn, n):
         fn()
@@ -352,9 +372,9 @@ def bench_batched(K, synth, torch, stream, args, reps=3):
 
     # batched, image kept in HBM: one graph replay
     leader = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN | K.CKPT_TIMING |
-                       (K.CKPT_NO_GRAPH if args.batched_no_graph else 0), **tune_kw(args))
+                       (K.CKPT_NO_GRAPH if args.batched_no_graph else 0), **shape)
     dev_ms = []
-    if elides_zero(C, args.wpc):
+    if elides_zero(C, shape.get("waves_per_chunk", 0)):
         # the pack leaves ZERO chunks unwritten: count the bytes it moves
         import numpy as np
         imgs = K.checkpoint_batch([leader] + members, stream=stream)
@@ -381,7 +401,7 @@ def bench_batched(K, synth, torch, stream, args, reps=3):
             c.close()
         return out
     # plain, image kept in HBM: one checkpoint call per allocation
-    pctx = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN | K.CKPT_TIMING, **tune_kw(args))
+    pctx = K.Context(chunk_bytes=C, flags=K.CKPT_NO_DRAIN | K.CKPT_TIMING, **shape)
 
     def plain_alloc():
         for t in tensors:
@@ -414,7 +434,7 @@ def bench_batched(K, synth, torch, stream, args, reps=3):
     ser = {}
 
     def drained(leader_flags, key):
-        dl = K.Context(chunk_bytes=C, flags=K.CKPT_TIMING | leader_flags, **tune_kw(args))
+        dl = K.Context(chunk_bytes=C, flags=K.CKPT_TIMING | leader_flags, **shape)
 
         def once():
             imgs = K.checkpoint_batch([dl] + members, stream=stream)
@@ -432,14 +452,6 @@ def bench_batched(K, synth, torch, stream, args, reps=3):
     pctx.close()
     for c in members:
         c.close()
-    # autotuner sweep on the same contexts
-    alloc_sets = [[(t.data_ptr(), t.numel()) for t in allocs] for allocs in sets]
-    tuned = autotune.tune(alloc_sets, chunks=(4096, 16384, 65536, 262144), waves=(1, 2, 4),
-                          blocks=(256, 1024), reps=2, stream=stream)
-    out["autotune"] = {"best": tuned["best"], "trials": len(tuned["trials"]),
-                       "worst_gbps": min(t["gbps"] for t in tuned["trials"]),
-                       "c4096_best_gbps": max(t["gbps"] for t in tuned["trials"] if t["chunk_bytes"] == 4096)}
-    log("autotune: %s" % out["autotune"])
     del tensors, sets
     return out
 

@@ -1,7 +1,7 @@
 """Autotuner for the batched checkpoint (ckpt_checkpoint_batch).
 
-Sweeps chunk size C, waves per chunk W and workgroup size on the caller's own
-contexts' allocations, timing the device part of one batched checkpoint (the
+Sweeps chunk size C, waves per chunk W, workgroup size and the load/store
+hint (non-temporal or regular) on the caller's own contexts' allocations, timing the device part of one batched checkpoint (the
 replayed graph: table upload, size scan, chunk map, fused pack + CRC + flags)
 with the image kept in HBM; the best shape is the fastest.  Each trial also
 reports GB/s of the bytes its kernel form moves (one wave per chunk of at most
@@ -27,6 +27,10 @@ from . import ckpt as K
 DEFAULT_CHUNKS = (4096, 16384, 65536, 262144)
 DEFAULT_WAVES = (1, 2, 4, 8)
 DEFAULT_BLOCKS = (256, 512, 1024)
+# ckpt_config.load_hint: 2 non-temporal, 1 regular.  Non-temporal is faster
+# where the dense image's chunks start on 128-byte lines; regular where most
+# of them do not (many allocations of arbitrary sizes), as in a batch.
+DEFAULT_HINTS = (2, 1)
 
 
 def signature(alloc_sets):
@@ -66,10 +70,10 @@ def _digest(imgs):
 
 
 def tune(alloc_sets, chunks=DEFAULT_CHUNKS, waves=DEFAULT_WAVES, blocks=DEFAULT_BLOCKS, reps=3,
-         device=0, stream=None, cache_path=None, log=None):
+         device=0, stream=None, cache_path=None, log=None, hints=DEFAULT_HINTS):
     """alloc_sets: one list of (device address, bytes) per context.
     Returns {"best": {...}, "trials": [...], "cached": bool}."""
-    key = "%s|%s" % (device_key(device), signature(alloc_sets))
+    key = "%s|%s|hints%s" % (device_key(device), signature(alloc_sets), ",".join(str(h) for h in hints))
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
@@ -91,36 +95,38 @@ def tune(alloc_sets, chunks=DEFAULT_CHUNKS, waves=DEFAULT_WAVES, blocks=DEFAULT_
         ref = None
         for W in waves:
             for B in blocks:
-                if W > B // 64 or (C + 1023) // 1024 < W:
-                    continue
-                leader = K.Context(device=device, chunk_bytes=C, flags=K.CKPT_NO_DRAIN | K.CKPT_TIMING,
-                                   waves_per_chunk=W, block_threads=B)
-                imgs = K.checkpoint_batch([leader] + members, stream=stream)   # capture + warm
-                d = _digest(imgs[1:])
-                if stored is None:
-                    stored = _stored(alloc_sets, C, imgs[1:])
-                if ref is None:
-                    ref = d
-                elif d != ref:
-                    raise RuntimeError("C=%d W=%d block=%d changed the result" % (C, W, B))
-                for im in imgs:
-                    im.close()
-                ms = []
-                for _ in range(reps):
-                    t0 = time.perf_counter()
-                    imgs = K.checkpoint_batch([leader] + members, stream=stream)
-                    wall = (time.perf_counter() - t0) * 1e3
-                    ms.append(leader.timing()["pack_ms"])
+                for H in hints:
+                    if W > B // 64 or (C + 1023) // 1024 < W:
+                        continue
+                    leader = K.Context(device=device, chunk_bytes=C, flags=K.CKPT_NO_DRAIN | K.CKPT_TIMING,
+                                       waves_per_chunk=W, block_threads=B, load_hint=H)
+                    imgs = K.checkpoint_batch([leader] + members, stream=stream)   # capture + warm
+                    d = _digest(imgs[1:])
+                    if stored is None:
+                        stored = _stored(alloc_sets, C, imgs[1:])
+                    if ref is None:
+                        ref = d
+                    elif d != ref:
+                        raise RuntimeError("C=%d W=%d block=%d hint=%d changed the result" % (C, W, B, H))
                     for im in imgs:
                         im.close()
-                t = statistics.median(ms)
-                alg = live + (stored if W == 1 and C <= 4096 else dense) + 5 * N
-                trial = {"chunk_bytes": C, "waves_per_chunk": W, "block_threads": B, "device_ms": round(t, 4),
-                         "gbps": round(alg / (t * 1e-3) / 1e9, 2), "wall_ms": round(wall, 3)}
-                trials.append(trial)
-                if log:
-                    log("autotune %s" % trial)
-                leader.close()
+                    ms = []
+                    for _ in range(reps):
+                        t0 = time.perf_counter()
+                        imgs = K.checkpoint_batch([leader] + members, stream=stream)
+                        wall = (time.perf_counter() - t0) * 1e3
+                        ms.append(leader.timing()["pack_ms"])
+                        for im in imgs:
+                            im.close()
+                    t = statistics.median(ms)
+                    alg = live + (stored if W == 1 and C <= 4096 else dense) + 5 * N
+                    trial = {"chunk_bytes": C, "waves_per_chunk": W, "block_threads": B, "load_hint": H,
+                             "device_ms": round(t, 4), "gbps": round(alg / (t * 1e-3) / 1e9, 2),
+                             "wall_ms": round(wall, 3)}
+                    trials.append(trial)
+                    if log:
+                        log("autotune %s" % trial)
+                    leader.close()
         for c in members:
             c.close()
     best = min(trials, key=lambda t: t["device_ms"])

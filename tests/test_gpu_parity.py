@@ -778,7 +778,7 @@ def test_batch_no_drain_dense_views():
 
 def test_autotuner_shapes_match_the_oracle(tmp_path):
     """autotune.tune on a small uneven batch; then, for every chunk size it
-    swept, a batch run in that size's best (waves, block) shape -- the global
+    swept, a batch run in that size's best (waves, block, hint) shape -- the global
     best among them -- must give each context the oracle's image.  A second
     tune call with the same cache file reuses the result."""
     from paper_2008_10596_amd import autotune
@@ -807,15 +807,16 @@ def test_autotuner_shapes_match_the_oracle(tmp_path):
         if c not in best_per_c or t["device_ms"] < best_per_c[c]["device_ms"]:
             best_per_c[c] = t
     assert res["best"] in best_per_c.values()
+    assert {t["load_hint"] for t in res["trials"]} == {1, 2}
     for C, t in sorted(best_per_c.items()):
-        W, B = t["waves_per_chunk"], t["block_threads"]
-        log("C=%d: best W=%d block=%d (%.0f GB/s)" % (C, W, B, t["gbps"]))
+        W, B, H = t["waves_per_chunk"], t["block_threads"], t["load_hint"]
+        log("C=%d: best W=%d block=%d hint=%d (%.0f GB/s)" % (C, W, B, H, t["gbps"]))
         members = []
         for tens in sets:
             c = K.Context(chunk_bytes=C)
             register_all(c, tens)
             members.append(c)
-        leader = K.Context(chunk_bytes=C, waves_per_chunk=W, block_threads=B)
+        leader = K.Context(chunk_bytes=C, waves_per_chunk=W, block_threads=B, load_hint=H)
         imgs = K.checkpoint_batch([leader] + members)
         for i, tens in enumerate(sets):
             check_full(imgs[i + 1], O.checkpoint(hosts[i], C), tens, C)
