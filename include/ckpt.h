@@ -132,7 +132,10 @@ typedef struct ckpt_config {
     uint32_t lane_pieces;      /* 16-byte pieces each lane hashes per round: 1 (0
                                   selects 1; other values are CKPT_E_INVAL)           */
     uint32_t load_hint;        /* bulk loads/stores: 1 regular, 2 non-temporal;
-                                  0 selects 2                                         */
+                                  0 selects 2, except for a pack whose live bytes
+                                  mostly sit in allocations whose dense image
+                                  starts off a 128-byte line (many allocations of
+                                  arbitrary sizes): there 1                      */
     uint32_t table_mode;       /* CRC operator tables in LDS: 2, replicated per lane
                                   (124 KiB, bank-conflict-free lookups, one workgroup
                                   per CU); 0 selects 2, other values are

@@ -225,6 +225,7 @@ struct ckpt_ctx {
     uint64_t g_n = 0, g_N = 0, g_D = 0;
     bool g_drain = false;        // the graph also holds the drain (select + gather into host memory)
     uint64_t g_outs = 0;         // outputs the drain tables hold
+    bool g_nt = false;           // the captured pack's hint (non-temporal)
     std::vector<void *> g_ptrs;
     uint64_t graph_captures = 0;
 
@@ -248,6 +249,7 @@ struct ckpt_ctx {
     ckpt::DevBuf d_drain;   // the graph's drain tables: out_addr, out_chunk0, row_out
     ckpt::PinnedBuf h_up, h_plan, h_base_cb;
     bool reserved = false;      // CKPT_RESERVE_STAGING: d_dense is the reserved block
+    bool hint_auto = false;     // load_hint was 0: the pack picks its hint (pack_hint)
     uint64_t prev_serial = 0;   // image whose CRC array is in d_prev_crc
     uint32_t zero_crc = 0;      // CRC-32C of chunk_bytes zero bytes (made at ckpt_init)
 
@@ -319,7 +321,9 @@ struct GraphDrain {
     std::vector<PinnedBuf> *data;
 };
 int graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, uint64_t N, uint64_t data_bytes,
-                   const GraphDrain *drain = nullptr);
+                   const GraphDrain *drain, bool nontemporal);
+// The pack's load/store hint for these rows and their dense offsets (runtime.cpp).
+bool pack_hint(const ckpt_ctx *ctx, const std::vector<Row> &rows, const std::vector<uint64_t> &off);
 int upload_table(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, bool dst_side, uint64_t N_host,
                  uint64_t n_items);
 int read_plan(ckpt_ctx *ctx, hipStream_t s, DevPlan *out);

@@ -330,8 +330,11 @@ extern "C" int ckpt_init(const ckpt_config *cfg_in, ckpt_ctx **out)
         return set_error(CKPT_E_INVAL, "waves_per_chunk %u with block_threads %u", w, cfg.block_threads);
     if ((cfg.flags & CKPT_RESERVE_STAGING) && cfg.staging_budget == 0)
         return set_error(CKPT_E_INVAL, "CKPT_RESERVE_STAGING needs a staging_budget");
+    // 0: non-temporal (streaming: every byte is touched once), except for a
+    // pack whose dense image mostly starts off 128-byte lines (pack_hint)
+    const bool hint_auto = cfg.load_hint == 0;
     if (cfg.load_hint == 0)
-        cfg.load_hint = 2;      // streaming: every byte is touched once
+        cfg.load_hint = 2;
     if (cfg.load_hint > 2)
         return set_error(CKPT_E_INVAL, "load_hint %u", cfg.load_hint);
     int ndev = 0;
@@ -344,6 +347,7 @@ extern "C" int ckpt_init(const ckpt_config *cfg_in, ckpt_ctx **out)
     DeviceGuard g(cfg.device);
     auto *ctx = new ckpt_ctx();
     ctx->cfg = cfg;
+    ctx->hint_auto = hint_auto;
     int rc = ctx_setup(ctx);
     if (rc != CKPT_OK) {
         ckpt_destroy(ctx);
@@ -760,7 +764,7 @@ uint64_t grow(uint64_t x, uint64_t floor) { return std::max<uint64_t>(floor, x +
 }  // namespace
 
 int ckpt::graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &rows, uint64_t N,
-                         uint64_t data_bytes, const GraphDrain *drain)
+                         uint64_t data_bytes, const GraphDrain *drain, bool nontemporal)
 {
     const uint64_t n = rows.size();
     const size_t nout = drain ? drain->nout : 0;
@@ -773,7 +777,8 @@ int ckpt::graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &r
         return v;
     };
     const bool fits = ctx->g_exec && n <= ctx->g_n && N <= ctx->g_N && data_bytes <= ctx->g_D &&
-                      (drain != nullptr) == ctx->g_drain && nout <= ctx->g_outs && buffers() == ctx->g_ptrs;
+                      (drain != nullptr) == ctx->g_drain && nout <= ctx->g_outs && buffers() == ctx->g_ptrs &&
+                      nontemporal == ctx->g_nt;
     if (!fits) {
         if (ctx->g_exec) {
             (void)hipGraphExecDestroy(ctx->g_exec);
@@ -816,6 +821,7 @@ int ckpt::graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &r
             HIP_TRY(launch_chunk_map(c, (const DevPlan *)ctx->d_plan.p, (const uint64_t *)ctx->d_cb.p,
                                      (uint32_t *)ctx->d_map.p, ctx->grid_small));
             ChunkArgs a = chunk_args(ctx);
+            a.nontemporal = nontemporal ? 1 : 0;
             a.src = (const uint64_t *)ctx->d_addr.p;
             a.dense = (uint8_t *)ctx->d_dense.p;
             a.crc = (uint32_t *)ctx->d_crc.p;
@@ -879,6 +885,7 @@ int ckpt::graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &r
         ctx->g_D = Dc;
         ctx->g_drain = drain != nullptr;
         ctx->g_outs = oc;
+        ctx->g_nt = nontemporal;
         ctx->g_ptrs = buffers();
         ctx->graph_captures++;
     }
@@ -913,6 +920,24 @@ int ckpt::graph_prologue(ckpt_ctx *ctx, hipStream_t s, const std::vector<Row> &r
 // rows: the table to drain, possibly the concatenation of several contexts'
 // tables (batched form); parts[i] = first row of output i (parts.size() =
 // number of outputs).  Each output's image is the one its rows alone give.
+
+// The load/store hint of a pack.  With load_hint 0, non-temporal, unless most
+// live bytes sit in allocations whose dense image starts off a 128-byte line:
+// then the line two neighbouring chunks share is written in two parts by two
+// waves, and regular stores let the two parts meet in the L2 instead of going
+// to HBM one by one (many allocations of arbitrary sizes, as in a batch).
+bool ckpt::pack_hint(const ckpt_ctx *ctx, const std::vector<Row> &rows, const std::vector<uint64_t> &off)
+{
+    if (!ctx->hint_auto)
+        return ctx->cfg.load_hint == 2;
+    uint64_t live = 0, off_line = 0;
+    for (size_t k = 0; k < rows.size(); k++) {
+        live += rows[k].size;
+        if (off[k] % 128)
+            off_line += rows[k].size;
+    }
+    return 2 * off_line <= live;
+}
 
 int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_image *base, const std::vector<Row> &rows,
                          const std::vector<size_t> &parts, std::vector<ckpt_image *> &outs, bool use_graph)
@@ -1000,7 +1025,7 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
         if (graph_drain)
             for (size_t i = 0; i < nout; i++)
                 CKPT_TRY(data[i].ensure(std::max<uint64_t>(L.off[part_row[i + 1]] - L.off[part_row[i]], 16)));
-        CKPT_TRY(graph_prologue(ctx, s, rows, N, L.data_bytes, graph_drain ? &gd : nullptr));
+        CKPT_TRY(graph_prologue(ctx, s, rows, N, L.data_bytes, graph_drain ? &gd : nullptr, pack_hint(ctx, rows, L.off)));
         dense = (uint8_t *)ctx->d_dense.p;
         if (timing) {
             HIP_TRY(hipEventRecord(ctx->ev[2], s));
@@ -1059,6 +1084,8 @@ int ckpt::run_checkpoint(ckpt_ctx *ctx, hipStream_t s, int mode, const ckpt_imag
     a.flags = (uint8_t *)ctx->d_flags.p;
     a.base_crc = d_base;
     a.base_cb = d_base_cb;
+    if (!incremental)
+        a.nontemporal = pack_hint(ctx, rows, L.off) ? 1 : 0;
     if (N)
         HIP_TRY(launch_chunks(s, incremental ? kModeHash : kModePack, a, ctx->grid_chunks, cfg.block_threads));
     if (timing)
